@@ -1,0 +1,442 @@
+"""Pins for the CPU oracle: closed forms, worked examples printed in the paper,
+invariants and brute force -- none of them re-types the oracle's own formulas.
+
+Each test names the passage it follows.  ``test_planted_*`` plant a plausible
+mistake in a copy of an oracle function (on the CPU) and check that a pin catches it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import lind_inputs as li
+from oracle import gradient as og
+from oracle import krylov as ok
+from oracle import lindblad as ol
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split("=")
+            nums = [float(x) for x in v.split()]
+            vals[k.strip()] = nums if len(nums) > 1 else nums[0]
+    return vals
+
+
+def coherent(n, beta):
+    """Truncated coherent state |beta> (unit-normalised)."""
+    k = np.arange(n)
+    from scipy.special import gammaln
+    amp = np.exp(-0.5 * abs(beta) ** 2 + k * np.log(abs(beta) + 0j) - 0.5 * gammaln(k + 1)) * np.exp(1j * k * np.angle(beta))
+    amp = amp / np.linalg.norm(amp)
+    return np.outer(amp, amp.conj())
+
+
+# --------------------------------------------------------------------------------------
+# operators against the textbook vec identity and closed forms
+# --------------------------------------------------------------------------------------
+
+def test_superop_matches_matrix_free():
+    """Dense column-stacked superoperator (vec(AXB) = (B^T kron A) vec X) against the
+    term-by-term definition, eq. (lindblad_def), on random matrices."""
+    H, Ls = li.random_dense(6, 3, seed=11)
+    X = li.random_state(6, seed=4, hermitian=False)
+    M = ol.superop_dense(H, Ls)
+    assert np.allclose(M @ ol.vec(X), ol.vec(ol.lindblad_apply(H, Ls, X)), atol=1e-13)
+    # L = S + K with G of eq. (G)
+    G = ol.no_jump_generator(H, Ls)
+    assert np.allclose(ol.S_apply(G, X) + ol.K_apply(Ls, X), ol.lindblad_apply(H, Ls, X), atol=1e-13)
+
+
+def test_trace_annihilation_and_hermiticity():
+    """Tr L(X) = 0 and L(X^+) = L(X)^+ for every X (identity is a left null vector, Section 2.1)."""
+    H, Ls = li.random_dense(7, 2, seed=3)
+    X = li.random_state(7, seed=5, hermitian=False)
+    LX = ol.lindblad_apply(H, Ls, X)
+    assert abs(np.trace(LX)) < 1e-13
+    assert np.allclose(ol.lindblad_apply(H, Ls, X.conj().T), LX.conj().T, atol=1e-13)
+
+
+def test_adjoint_is_hs_adjoint():
+    """<L*(X), Y> = <X, L(Y)> (Section 1.2 definition of X*)."""
+    H, Ls = li.random_dense(5, 2, seed=8)
+    X = li.random_state(5, seed=1, hermitian=False)
+    Y = li.random_state(5, seed=2, hermitian=False)
+    lhs = ol.hs_inner(ol.lindblad_adjoint_apply(H, Ls, X), Y)
+    rhs = ol.hs_inner(X, ol.lindblad_apply(H, Ls, Y))
+    assert abs(lhs - rhs) < 1e-12
+
+
+def test_coherent_state_linear_cavity():
+    """Kerr workload with K = 0: the steady state is |beta><beta|, beta = -i eps/(i Delta + kappa/2)."""
+    g = read_golden("kerr_linear_coherent.txt")
+    beta = -1j * g["eps"] / (1j * g["Delta"] + g["kappa"] / 2)
+    assert abs(beta - complex(g["beta_re"], g["beta_im"])) < 1e-15
+    H, Ls = li.kerr_cavity(32, Delta=g["Delta"], eps=g["eps"], K=0.0, kappa=g["kappa"])
+    ref = coherent(32, beta)
+    assert ol.max_norm(ol.lindblad_apply(H, Ls, ref)) < 1e-12
+    rho = ol.steady_state_dense(H, Ls)
+    assert ol.trace_distance(rho, ref) < 1e-12
+    rho_svd = ol.steady_state_svd(H, Ls)
+    assert ol.trace_distance(rho_svd, ref) < 1e-10
+
+
+def test_thermal_state_is_geometric():
+    """Damped oscillator at temperature: the truncated birth-death chain is in detailed balance,
+    so p_k is exactly proportional to (nbar/(1+nbar))^k."""
+    nbar = 0.3
+    H, Ls = li.thermal_oscillator(12, omega=1.3, kappa=0.7, nbar=nbar)
+    rho = ol.steady_state_dense(H, Ls)
+    q = nbar / (1 + nbar)
+    p = q ** np.arange(12)
+    p /= p.sum()
+    assert np.allclose(np.diag(rho).real, p, atol=1e-13)
+    assert np.max(np.abs(rho - np.diag(np.diag(rho)))) < 1e-13
+
+
+def test_thermal_low_spectrum():
+    """Damped oscillator spectrum lambda = -i omega l - kappa (m + |l|/2): at small nbar and a
+    large enough truncation the lowest modes agree with it (to the truncation effect)."""
+    H, Ls = li.thermal_oscillator(14, omega=1.0, kappa=1.0, nbar=0.1)
+    ev = ol.low_spectrum_dense(H, Ls, 6)
+    expected = np.array([-0.5 - 1j, -0.5 + 1j, -1.0, -1.5 - 1j, -1.5 + 1j, -1 - 2j])
+    for e in expected:
+        assert np.min(np.abs(ev - e)) < 1e-6 or abs(e) > np.max(np.abs(ev))
+
+
+def test_three_level_cyclic_golden():
+    """Remark "Peripheral spectra of Phi": rho_inf = I/3 and Phi has eigenvalues 1, exp(+-2 pi i/3)."""
+    g = read_golden("three_level_cyclic.txt")
+    H, Ls = li.three_level_cyclic()
+    rho = ol.steady_state_dense(H, Ls)
+    assert np.allclose(np.diag(rho).real, g["steady_state_diag"], atol=1e-14)
+    G = ol.no_jump_generator(H, Ls)
+    P = ol.superop_of_map(lambda X: ol.phi_apply(G, Ls, X), 3)
+    ev = np.linalg.eigvals(P)
+    per = np.array(g["peripheral_eigs_re"]) + 1j * np.array(g["peripheral_eigs_im"])
+    for e in per:
+        assert np.min(np.abs(ev - e)) < 1e-12
+    assert np.sum(np.abs(np.abs(ev) - 1) < 1e-9) == 3
+    # Algorithm 4 (Arnoldi, Ritz value nearest 1) still converges to I/3
+    rho_a = ok.steady_state_phi(H, Ls, tol=1e-12, m=8)
+    assert np.allclose(rho_a, np.eye(3) / 3, atol=1e-12)
+
+
+def test_two_level_footnote_golden():
+    """Footnote on left vs right preconditioning: R K rho = (gamma/lambda) rho_11 |0><0| and
+    K R rho = gamma/(gamma+lambda) rho_11 |0><0| (resolvent R = (lambda - S)^{-1}, G_lambda = G - lambda/2)."""
+    g = read_golden("two_level_footnote.txt")
+    H, Ls = li.two_level_decay(g["gamma"])
+    G = ol.no_jump_generator(H, Ls)
+    rho = li.random_state(2, seed=9)
+    lam = g["lambda"]
+    RK = ol.resolvent_S(G, ol.K_apply(Ls, rho), lam)
+    KR = ol.K_apply(Ls, ol.resolvent_S(G, rho, lam))
+    E00 = np.array([[1, 0], [0, 0]], dtype=complex)
+    assert np.allclose(RK, g["RK_coefficient"] * rho[1, 1] * E00, atol=1e-14)
+    assert np.allclose(KR, g["KR_coefficient"] * rho[1, 1] * E00, atol=1e-14)
+
+
+def test_lyapunov_three_ways():
+    """S^{-1} by LAPACK Bartels-Stewart, by the Kronecker definition, and by the integral form
+    eq. (lyapunov_solution); plus the residual G X + X G^+ = Y."""
+    H, Ls = li.random_dense(5, 3, seed=21)
+    Ls = [4 * L for L in Ls]  # faster decay -> shorter quadrature
+    G = ol.no_jump_generator(H, Ls)
+    Y = li.random_state(5, seed=6, hermitian=False)
+    X1 = ol.lyap_solve(G, Y)
+    X2 = ol.lyap_solve_kron(G, Y)
+    X3 = ol.lyap_integral(G, Y, t_max=40.0, steps=8000)
+    assert np.allclose(ol.S_apply(G, X1), Y, atol=1e-13)
+    assert np.allclose(X1, X2, atol=1e-12)
+    assert np.allclose(X1, X3, atol=1e-9)
+    # shifted form: (S - mu) X = Y
+    Xm = ol.lyap_solve(G, Y, mu=0.7)
+    assert np.allclose(ol.S_apply(G, Xm) - 0.7 * Xm, Y, atol=1e-13)
+    # eigendecomposition route (eq. lyapu_eig_solution)
+    R = ol.EigResolvent(G)
+    assert np.allclose(R.sinv(Y), X1, atol=1e-12)
+    assert np.allclose(R.sinv(Y, 0.7), Xm, atol=1e-12)
+
+
+def test_hermitian_in_hermitian_out_and_cp():
+    """Hermitian Y gives Hermitian X (Section A.1), -S^{-1} and Phi are completely positive
+    (eq. lyapunov_solution; Theorem 1), Phi is trace preserving (Appendix lemma)."""
+    H, Ls = li.random_dense(4, 2, seed=31)
+    G = ol.no_jump_generator(H, Ls)
+    Y = li.random_state(4, seed=2)
+    X = ol.lyap_solve(G, Y)
+    assert np.allclose(X, X.conj().T, atol=1e-14)
+    C1 = ol.choi(lambda E: -ol.lyap_solve(G, E), 4)
+    C2 = ol.choi(lambda E: ol.phi_apply(G, Ls, E), 4)
+    assert np.min(np.linalg.eigvalsh(ol.hermitize(C1))) > -1e-12
+    assert np.min(np.linalg.eigvalsh(ol.hermitize(C2))) > -1e-12
+    Z = li.random_state(4, seed=3, hermitian=False)
+    assert abs(np.trace(ol.phi_apply(G, Ls, Z)) - np.trace(Z)) < 1e-13
+
+
+def test_phi_spectrum_in_unit_disk_and_fixed_point():
+    """Theorem 1: Phi is CPTP with spectrum in the closed unit disk, 1 simple; its fixed point
+    xi_inf = K rho_inf and rho_inf = -S^{-1} xi_inf / Tr(.)."""
+    H, Ls = li.random_dense(5, 3, seed=41)
+    G = ol.no_jump_generator(H, Ls)
+    P = ol.superop_of_map(lambda X: ol.phi_apply(G, Ls, X), 5)
+    ev = np.linalg.eigvals(P)
+    assert np.max(np.abs(ev)) < 1 + 1e-12
+    assert np.sum(np.abs(ev - 1) < 1e-8) == 1
+    rho = ol.steady_state_dense(H, Ls)
+    xi = ol.K_apply(Ls, rho)
+    assert np.allclose(ol.phi_apply(G, Ls, xi), xi, atol=1e-13)
+    back = -ol.lyap_solve(G, xi)
+    assert np.allclose(back / np.trace(back), rho, atol=1e-12)
+
+
+def test_sherman_morrison_exact():
+    """eq. (ShermanMorr): Precond(X, lam, c) is exactly ((lam - S) - c |I><I|)^{-1} X."""
+    H, Ls = li.random_dense(4, 2, seed=51)
+    G = ol.no_jump_generator(H, Ls)
+    X = li.random_state(4, seed=7, hermitian=False)
+    for lam, c in [(0.0, 1.0), (0.3, 1.0), (0.0, 2.5)]:
+        Z = ol.precond_apply(G, X, lam, c)
+        back = lam * Z - ol.S_apply(G, Z) - c * np.trace(Z) * np.eye(4)
+        assert np.allclose(back, X, atol=1e-12)
+
+
+def test_deflation_moves_zero_to_eta_n():
+    """Section 4.2: L~_eta keeps every nonzero eigenvalue and sends 0 to eta n."""
+    H, Ls = li.random_dense(4, 2, seed=61)
+    n = 4
+    ev = np.sort_complex(ol.spectrum_dense(H, Ls))
+    eta = 0.7
+    M = ol.superop_dense(H, Ls)
+    vI = ol.vec(np.eye(n))
+    ev2 = np.linalg.eigvals(M + eta * np.outer(vI, vI.conj()))
+    j0 = np.argmin(np.abs(ev))
+    assert np.min(np.abs(ev2 - eta * n)) < 1e-10
+    rest = np.delete(ev, j0)
+    for e in rest:
+        assert np.min(np.abs(ev2 - e)) < 1e-9
+
+
+def test_contraction_theorem():
+    """Theorem 2: ||K R^S_lambda|| = ||(R^S_lambda)*(sum L^+L)||_inf < 1 for lambda > 0, and = 1
+    at lambda = 0 (Remark "Loss of the contraction at zero shift")."""
+    H, Ls = li.random_dense(5, 2, seed=71)
+    G = ol.no_jump_generator(H, Ls)
+    n = 5
+    KR = ol.superop_of_map(lambda X: ol.K_apply(Ls, ol.resolvent_S(G, X, 0.0)), n)
+    # adjoint applied to I, unvec back
+    for lam in [0.0, 0.1, 1.0]:
+        KRl = ol.superop_of_map(lambda X: ol.K_apply(Ls, ol.resolvent_S(G, X, lam)), n)
+        dual_I = ol.unvec(KRl.conj().T @ ol.vec(np.eye(n)), n)
+        norm = np.max(np.linalg.eigvalsh(ol.hermitize(dual_I)))
+        if lam == 0.0:
+            assert abs(norm - 1) < 1e-12
+        else:
+            assert norm < 1 - 1e-6
+    del KR
+
+
+def test_resolvent_series():
+    """Corollary (Resolvent of the Lindbladian): R^L_lambda = R^S_lambda sum_k (K R^S_lambda)^k, lambda > 0."""
+    H, Ls = li.random_dense(4, 2, seed=81)
+    G = ol.no_jump_generator(H, Ls)
+    lam = 2.0
+    n = 4
+    b = li.random_state(n, seed=3, hermitian=False)
+    term = b.copy()
+    acc = np.zeros_like(b)
+    for _ in range(400):
+        acc = acc + term
+        term = ol.K_apply(Ls, ol.resolvent_S(G, term, lam))
+    series = ol.resolvent_S(G, acc, lam)
+    M = ol.superop_dense(H, Ls)
+    exact = ol.unvec(np.linalg.solve(lam * np.eye(n * n) - M, ol.vec(b)), n)
+    assert np.allclose(series, exact, atol=1e-10)
+
+
+def test_dephasing_closed_form():
+    """Linear cavity with dephasing: <N> = eps^2 Gamma / (kappa (Delta^2 + Gamma^2/4)),
+    Gamma = kappa + gamma (closed Heisenberg equations for <a> and <a^dag a>)."""
+    D, e, k, gm = 0.5, 1.0, 1.0, 0.05
+    H, Ls = li.kerr_cavity(40, Delta=D, eps=e, K=0.0, kappa=k, gamma_dephasing=gm)
+    rho = ol.steady_state_dense(H, Ls)
+    a = li.destroy(40)
+    N = a.conj().T @ a
+    Gm = k + gm
+    ref = e ** 2 * Gm / (k * (D ** 2 + Gm ** 2 / 4))
+    assert abs(np.trace(N @ rho).real - ref) < 1e-11
+
+
+def test_coupled_cavities_product_coherent():
+    """Two coupled linear cavities (K = 0, gamma = 0): the steady state is a product of coherent
+    states with (i D1 + k/2) b1 + i g b2 = -i eps, (i D2 + k/2) b2 + i g b1 = 0."""
+    m = 8
+    D1, D2, g, eps, k = 0.3, -0.2, 0.4, 0.3, 1.0
+    H, Ls = li.coupled_kerr(m, Delta=(D1, D2), K=(0.0, 0.0), g=g, eps=eps, kappa=k, gamma=0.0)
+    A = np.array([[1j * D1 + k / 2, 1j * g], [1j * g, 1j * D2 + k / 2]])
+    b1, b2 = np.linalg.solve(A, np.array([-1j * eps, 0.0]))
+    ref = np.kron(coherent(m, b1), coherent(m, b2))
+    r = ol.lindblad_apply(H, Ls[:2], ref)
+    assert ol.max_norm(r) < 1e-5  # truncation at 8 levels per mode
+    rho = ol.steady_state_dense(H, Ls[:2])
+    assert ol.trace_distance(rho, ref) < 1e-4
+
+
+def test_phi_arnoldi_matches_dense():
+    """Algorithm "Steady state as the fixed point of Phi" (plain) against the dense null vector."""
+    H, Ls = li.random_dense(20, 8, seed=0)
+    rho_d = ol.steady_state_dense(H, Ls)
+    rho_a, info = ok.steady_state_phi(H, Ls, tol=1e-12, m=20, return_info=True)
+    assert ol.trace_distance(rho_a, rho_d) < 1e-11
+    assert info["resid"] < 1e-12
+    # Kerr cavity (the 32-level workload)
+    H, Ls, _ = li.workload("kerr32")
+    rho_d = ol.steady_state_dense(H, Ls)
+    rho_a = ok.steady_state_phi(H, Ls, tol=1e-11, m=30)
+    assert ol.trace_distance(rho_a, rho_d) < 1e-10
+
+
+def test_gmres_deflated_steady_state():
+    """Algorithm "Steady state via preconditioned GMRES" reaches the dense steady state."""
+    H, Ls = li.random_dense(10, 3, seed=5)
+    n = 10
+    G = ol.no_jump_generator(H, Ls)
+    I = np.eye(n, dtype=complex)
+    W = ol.resolvent_S(G, I, 0.0)
+
+    def P(X):
+        return ol.precond_apply(G, X, 0.0, 1.0, W)
+
+    def A(X):
+        return -ol.deflated_apply(H, Ls, X, 1.0)
+
+    rho = ok.gmres(A, -I, P, m=20, atol=1e-13)
+    rho = ol.hermitize(rho) / np.trace(rho).real
+    assert ol.trace_distance(rho, ol.steady_state_dense(H, Ls)) < 1e-11
+
+
+def test_low_spectrum_matches_dense():
+    """Algorithm "Low-lying spectrum via shift-invert Arnoldi" (plain) against dense eig."""
+    H, Ls = li.random_dense(7, 3, seed=2)
+    ref = ol.low_spectrum_dense(H, Ls, 4)
+    lam, vecs = ok.low_spectrum(H, Ls, 5)  # one extra: a conjugate pair may straddle the cut
+    for e in ref:
+        assert np.min(np.abs(lam - e)) < 1e-9
+    for l, v in zip(lam, vecs):
+        assert ok.eigen_residual(H, Ls, l, v) < 1e-8
+
+
+def test_gradient_three_routes():
+    """Remark "Differentiating the steady state": the adjoint gradients equal the dense forward
+    sensitivities and central finite differences."""
+    H, Ls = li.random_dense(4, 2, seed=13)
+    O = li.random_observable(4, seed=1)
+    J, gH_f, gL_f = og.grad_forward_dense(H, Ls, O)
+    J2, gH_a, gL_a, mu = og.grad_adjoint(H, Ls, O)
+    assert abs(J - J2) < 1e-14
+    assert np.allclose(gH_a, gH_f, atol=1e-10)
+    for a, b in zip(gL_a, gL_f):
+        assert np.allclose(a, b, atol=1e-10)
+    dirs = og.random_directions(4, 2, 8)
+    Jof = lambda H_, Ls_: og.expectation(O, ol.steady_state_dense(H_, Ls_))  # noqa: E731
+    fd = og.grad_fd(Jof, H, Ls, dirs)
+    ad = np.array([og.directional(gH_a, gL_a, dH, dL) for dH, dL in dirs])
+    assert np.linalg.norm(ad - fd) / np.linalg.norm(fd) < 1e-7
+
+
+def test_gradient_dephasing_closed_form():
+    """d<N>/d(Delta, eps, kappa, gamma) from the adjoint gradients (chain rule through
+    H = Delta N + eps(a + a^dag), L1 = sqrt(kappa) a, L2 = sqrt(gamma) N) against the
+    derivatives of the closed form <N> = eps^2 Gamma/(kappa(Delta^2 + Gamma^2/4))."""
+    D, e, k, gm = 0.5, 1.0, 1.0, 0.05
+    n = 30
+    H, Ls = li.kerr_cavity(n, Delta=D, eps=e, K=0.0, kappa=k, gamma_dephasing=gm)
+    a = li.destroy(n)
+    N = a.conj().T @ a
+    J, gH, gL, _ = og.grad_adjoint(H, Ls, N)
+
+    def f(D, e, k, gm):
+        Gm = k + gm
+        return e ** 2 * Gm / (k * (D ** 2 + Gm ** 2 / 4))
+
+    h = 1e-6
+    ref = [(f(D + h, e, k, gm) - f(D - h, e, k, gm)) / (2 * h),
+           (f(D, e + h, k, gm) - f(D, e - h, k, gm)) / (2 * h),
+           (f(D, e, k + h, gm) - f(D, e, k - h, gm)) / (2 * h),
+           (f(D, e, k, gm + h) - f(D, e, k, gm - h)) / (2 * h)]
+    zero = np.zeros_like(H)
+    got = [og.directional(gH, gL, N, [zero, zero]),
+           og.directional(gH, gL, a + a.conj().T, [zero, zero]),
+           og.directional(gH, gL, zero, [a / (2 * np.sqrt(k)), zero]),
+           og.directional(gH, gL, zero, [zero, N / (2 * np.sqrt(gm))])]
+    assert np.allclose(got, ref, rtol=1e-7, atol=1e-9)
+
+
+# --------------------------------------------------------------------------------------
+# planted mistakes: each must be caught by one of the pins above
+# --------------------------------------------------------------------------------------
+
+def _lindblad_wrong_commutator(H, Ls, rho):
+    out = +1j * (H @ rho - rho @ H)  # planted: sign of the Hamiltonian term
+    for L in Ls:
+        LdL = L.conj().T @ L
+        out = out + L @ rho @ L.conj().T - 0.5 * (LdL @ rho + rho @ LdL)
+    return out
+
+
+def _lindblad_transposed_jump(H, Ls, rho):
+    out = -1j * (H @ rho - rho @ H)
+    for L in Ls:
+        LdL = L.conj().T @ L
+        out = out + L.conj().T @ rho @ L - 0.5 * (LdL @ rho + rho @ LdL)  # planted: L^+ rho L
+    return out
+
+
+def _lindblad_dropped_half(H, Ls, rho):
+    out = -1j * (H @ rho - rho @ H)
+    for L in Ls:
+        LdL = L.conj().T @ L
+        out = out + L @ rho @ L.conj().T - (LdL @ rho + rho @ LdL)  # planted: dropped 1/2
+    return out
+
+
+@pytest.mark.parametrize("bad", [_lindblad_wrong_commutator, _lindblad_transposed_jump, _lindblad_dropped_half])
+def test_planted_lindblad_mistakes_are_caught(bad):
+    g = read_golden("kerr_linear_coherent.txt")
+    beta = complex(g["beta_re"], g["beta_im"])
+    H, Ls = li.kerr_cavity(32, K=0.0)
+    ref = coherent(32, beta)
+    caught = ol.max_norm(bad(H, Ls, ref)) > 1e-6
+    X = li.random_state(6, seed=1, hermitian=False)
+    H6, L6 = li.random_dense(6, 2, seed=1)
+    caught = caught or abs(np.trace(bad(H6, L6, X))) > 1e-8
+    assert caught
+
+
+def test_planted_phi_sign_is_caught():
+    """Phi with the wrong sign (+K S^{-1}) fails the three-level golden spectrum."""
+    g = read_golden("three_level_cyclic.txt")
+    H, Ls = li.three_level_cyclic()
+    G = ol.no_jump_generator(H, Ls)
+    P = ol.superop_of_map(lambda X: ol.K_apply(Ls, ol.lyap_solve(G, X)), 3)
+    ev = np.linalg.eigvals(P)
+    assert np.min(np.abs(ev - 1.0)) > 1e-3
+
+
+def test_planted_resolvent_shift_is_caught():
+    """A resolvent with G - lambda (instead of G - lambda/2) fails the two-level footnote."""
+    g = read_golden("two_level_footnote.txt")
+    H, Ls = li.two_level_decay(g["gamma"])
+    G = ol.no_jump_generator(H, Ls)
+    rho = li.random_state(2, seed=9)
+    lam = g["lambda"]
+    wrong = -ol.lyap_solve(G - 0.5 * lam * np.eye(2), ol.K_apply(Ls, rho), lam)
+    assert abs(wrong[0, 0] - g["RK_coefficient"] * rho[1, 1]) > 1e-3
