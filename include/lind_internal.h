@@ -1,0 +1,39 @@
+/*
+ * lind_internal.h -- kernel-level entry points of liblindx, exported for unit tests and for
+ * the benchmark's per-kernel timing.  Not part of the stable API in lind.h.
+ * All pointers are device pointers to complex128 (or complex64 where stated) row-major data;
+ * stream is a hipStream_t (NULL = default).  Return 0 on success, a negative LIND_E* code on error.
+ */
+#ifndef LINDX_LIND_INTERNAL_H
+#define LINDX_LIND_INTERNAL_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha * sum_{b < nbatch} op(A_b) op(B_b) (+ C if beta), op: 0 = as stored, 2 = conjugate
+   transpose; A_b = A + b*sA, B_b = B + b*sB (element strides).  prec 0: complex128 operands;
+   prec 1 (FP32 MFMA) / 2 (BF16 split, FP32 accumulate): complex64 operands, complex64 output
+   unless out64 != 0 (complex128 output). */
+int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void* A, long long lda, long long sA, int opA,
+               const void* B, long long ldb, long long sB, int opB, void* C, long long ldc, double alpha_re,
+               double alpha_im, int beta, int out64, void* stream);
+
+/* Schur form in place: on entry A = G (n x n), on exit A = T (upper triangular), Z unitary with
+   G = Z T Z^H.  stop_after_hessenberg != 0 returns the Hessenberg form instead of T. */
+int lindx_schur(void* A, void* Z, int n, int stop_after_hessenberg, void* stream);
+
+/* eigenvalues w (m) and unit-norm right eigenvectors Y (m x m, column j for w[j]) of a dense
+   m x m matrix A (m <= 64), one workgroup */
+int lindx_small_eig(const void* A, int m, void* w, void* Y, void* stream);
+
+/* eigenvectors Y of upper-triangular T (unit diagonal) and the inverse of a unit upper-triangular Y */
+int lindx_trevec(const void* T, void* Y, int n, void* stream);
+int lindx_triinv(const void* Y, void* Yinv, int n, void* stream);
+
+/* T X + X T^H + shift X = C in place (X holds C on entry), T upper triangular */
+int lindx_trisylv(const void* T, void* X, int n, double shift_re, double shift_im, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,489 @@
+// Bandwidth-bound kernels on complex128 n x n matrices and n^2-long Krylov vectors:
+// Gram-Schmidt dot products and updates (FP64), norms, traces, hermitisation, conversions.
+// All reductions are two-stage with a fixed order (no atomics), so results are deterministic.
+#include "kernels.hpp"
+
+namespace lindx {
+
+static constexpr int RB = 256;      // threads per block
+static constexpr int NPART = 1024;  // first-stage partial count
+
+__device__ inline double warp_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ inline double warp_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+// block-wide sum of 256 threads; result valid in thread 0
+__device__ inline double block_sum(double v, double* sh) {
+  v = warp_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+__device__ inline double block_max(double v, double* sh) {
+  v = warp_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  __syncthreads();
+  return r;
+}
+
+static int nparts(long long len) {
+  long long p = (len + RB * 4 - 1) / (RB * 4);
+  if (p > NPART) p = NPART;
+  if (p < 1) p = 1;
+  return (int)p;
+}
+
+// ---------------------------------------------------------------- multi-dot (Gram-Schmidt) ----
+// stage 1: block b handles a contiguous chunk; groups of 8 basis vectors share one read of w.
+__global__ __launch_bounds__(RB) void k_mdot1(const zd* __restrict__ V, long long ld, int k,
+                                              const zd* __restrict__ w, long long len,
+                                              zd* __restrict__ part, int np) {
+  __shared__ double sh[4];
+  long long chunk = (len + np - 1) / np;
+  long long i0 = (long long)blockIdx.x * chunk;
+  long long i1 = i0 + chunk < len ? i0 + chunk : len;
+  for (int j0 = 0; j0 < k; j0 += 8) {
+    double sr[8], si[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) { sr[t] = 0; si[t] = 0; }
+    for (long long i = i0 + threadIdx.x; i < i1; i += RB) {
+      zd x = w[i];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (j0 + t < k) {
+          zd v = V[(long long)(j0 + t) * ld + i];
+          sr[t] += v.x * x.x + v.y * x.y;
+          si[t] += v.x * x.y - v.y * x.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (j0 + t < k) {
+        double a = block_sum(sr[t], sh);
+        double b = block_sum(si[t], sh);
+        if (threadIdx.x == 0) part[(long long)(j0 + t) * np + blockIdx.x] = zmk(a, b);
+      }
+    }
+  }
+}
+__global__ __launch_bounds__(RB) void k_mdot2(const zd* __restrict__ part, int np, zd* __restrict__ h) {
+  __shared__ double sh[4];
+  int j = blockIdx.x;
+  double a = 0, b = 0;
+  for (int p = threadIdx.x; p < np; p += RB) {
+    zd v = part[(long long)j * np + p];
+    a += v.x;
+    b += v.y;
+  }
+  a = block_sum(a, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) h[j] = zmk(a, b);
+}
+
+int multi_dot(const zd* V, long long ld, int k, const zd* w, long long len, zd* h, zd* scratch,
+              hipStream_t st) {
+  if (k <= 0) return 0;
+  int np = nparts(len);
+  hipLaunchKernelGGL(k_mdot1, dim3(np), dim3(RB), 0, st, V, ld, k, w, len, scratch, np);
+  hipLaunchKernelGGL(k_mdot2, dim3(k), dim3(RB), 0, st, scratch, np, h);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// ---------------------------------------------------------------- multi-axpy -----------------
+__global__ __launch_bounds__(RB) void k_maxpy(const zd* __restrict__ V, long long ld, int k,
+                                              const zd* __restrict__ h, zd* __restrict__ w,
+                                              long long len, int accumulate, double coeff) {
+  __shared__ zd hs[128];
+  for (int t = threadIdx.x; t < k; t += RB) hs[t] = h[t];
+  __syncthreads();
+  long long stride = (long long)gridDim.x * RB;
+  for (long long i = (long long)blockIdx.x * RB + threadIdx.x; i < len; i += stride) {
+    double ar = 0, ai = 0;
+    for (int j = 0; j < k; ++j) {
+      zd v = V[(long long)j * ld + i];
+      zd c = hs[j];
+      ar += c.x * v.x - c.y * v.y;
+      ai += c.x * v.y + c.y * v.x;
+    }
+    zd o = accumulate ? w[i] : zmk(0, 0);
+    w[i] = zmk(o.x + coeff * ar, o.y + coeff * ai);
+  }
+}
+
+int multi_axpy(const zd* V, long long ld, int k, const zd* h, zd* w, long long len, int accumulate,
+               double coeff, hipStream_t st) {
+  if (k > 128) return -1;
+  long long nb = (len + RB - 1) / RB;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_maxpy, dim3((int)nb), dim3(RB), 0, st, V, ld, k, h, w, len, accumulate, coeff);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// ---------------------------------------------------------------- norms ----------------------
+__global__ __launch_bounds__(RB) void k_sumsq1(const zd* __restrict__ w, long long len, double* part, int np) {
+  __shared__ double sh[4];
+  long long chunk = (len + np - 1) / np;
+  long long i0 = (long long)blockIdx.x * chunk;
+  long long i1 = i0 + chunk < len ? i0 + chunk : len;
+  double s = 0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += RB) {
+    zd x = w[i];
+    s += x.x * x.x + x.y * x.y;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ __launch_bounds__(RB) void k_sqrt_sum2(const double* part, int np, double* out) {
+  __shared__ double sh[4];
+  double s = 0;
+  for (int p = threadIdx.x; p < np; p += RB) s += part[p];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+int nrm2(const zd* w, long long len, double* out, double* scratch, hipStream_t st) {
+  int np = nparts(len);
+  hipLaunchKernelGGL(k_sumsq1, dim3(np), dim3(RB), 0, st, w, len, scratch, np);
+  hipLaunchKernelGGL(k_sqrt_sum2, dim3(1), dim3(RB), 0, st, scratch, np, out);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_scale_inv(zd* w, long long len, const double* s) {
+  double f = 1.0 / s[0];
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    zd x = w[i];
+    w[i] = zmk(x.x * f, x.y * f);
+  }
+}
+static int grid_for(long long len) {
+  long long nb = (len + RB - 1) / RB;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+int scale_by_inv(zd* w, long long len, const double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_inv, dim3(grid_for(len)), dim3(RB), 0, st, w, len, s);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_axpby(zd a, const zd* x, zd b, zd* y, long long len) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    zd xv = x[i], yv = y[i];
+    y[i] = zadd(zmul(a, xv), zmul(b, yv));
+  }
+}
+int axpby(zd a, const zd* x, zd b, zd* y, long long len, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(len)), dim3(RB), 0, st, a, x, b, y, len);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+int copy(const zd* x, zd* y, long long len, hipStream_t st) {
+  if (len <= 0) return 0;
+  return hipMemcpyAsync(y, x, (size_t)len * sizeof(zd), hipMemcpyDeviceToDevice, st) == hipSuccess ? 0 : -4;
+}
+__global__ void k_zero(unsigned int* p, long long nwords) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) p[i] = 0u;
+}
+int fill_zero(void* p, long long bytes, hipStream_t st) {
+  if (bytes <= 0) return 0;
+  if (bytes % 4) return -1;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(bytes / 4)), dim3(RB), 0, st, (unsigned int*)p, bytes / 4);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+__global__ void k_to64(const zd* x, zf* y, long long len) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+    y[i] = make_float2((float)x[i].x, (float)x[i].y);
+}
+__global__ void k_to128(const zf* x, zd* y, long long len) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+    y[i] = zmk(x[i].x, x[i].y);
+}
+int to_c64(const zd* x, zf* y, long long len, hipStream_t st) {
+  hipLaunchKernelGGL(k_to64, dim3(grid_for(len)), dim3(RB), 0, st, x, y, len);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+int to_c128(const zf* x, zd* y, long long len, hipStream_t st) {
+  hipLaunchKernelGGL(k_to128, dim3(grid_for(len)), dim3(RB), 0, st, x, y, len);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// ---------------------------------------------------------------- matrix helpers ------------
+__global__ void k_hermitize(zd* X, int n) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    int i = (int)(t / n), j = (int)(t - (long long)i * n);
+    if (j < i) continue;
+    if (i == j) {
+      X[t].y = 0.0;
+    } else {
+      zd a = X[(long long)i * n + j], b = X[(long long)j * n + i];
+      zd m = zmk(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      X[(long long)i * n + j] = m;
+      X[(long long)j * n + i] = zconj(m);
+    }
+  }
+}
+__global__ __launch_bounds__(RB) void k_trace(const zd* X, int n, zd* out) {
+  __shared__ double sh[4];
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < n; i += RB) {
+    zd v = X[(long long)i * n + i];
+    a += v.x;
+    b += v.y;
+  }
+  a = block_sum(a, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) out[0] = zmk(a, b);
+}
+__global__ void k_scale_by_trace(zd* X, long long len, const zd* tr) {
+  double f = 1.0 / tr[0].x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    zd x = X[i];
+    X[i] = zmk(x.x * f, x.y * f);
+  }
+}
+int hermitize(zd* X, int n, int normalize_trace, zd* trace_out, double* scratch, hipStream_t st) {
+  (void)scratch;
+  long long len = (long long)n * n;
+  hipLaunchKernelGGL(k_hermitize, dim3(grid_for(len)), dim3(RB), 0, st, X, n);
+  if (trace_out) hipLaunchKernelGGL(k_trace, dim3(1), dim3(RB), 0, st, X, n, trace_out);
+  if (normalize_trace && trace_out)
+    hipLaunchKernelGGL(k_scale_by_trace, dim3(grid_for(len)), dim3(RB), 0, st, X, len, trace_out);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+int trace(const zd* X, int n, zd* out, double* scratch, hipStream_t st) {
+  (void)scratch;
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(RB), 0, st, X, n, out);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// column sums of |x|^2 and column max |x| over row chunks
+__global__ __launch_bounds__(RB) void k_colnorm1(const zd* X, int n, int rchunk, double* psum, double* pmax,
+                                                 double* pdiag) {
+  // block: 64 columns x 4 row groups
+  __shared__ double ss[4][64], sm[4][64];
+  int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  int rg = threadIdx.x >> 6;
+  int r0 = blockIdx.y * rchunk;
+  int r1 = r0 + rchunk < n ? r0 + rchunk : n;
+  double s = 0, mx = 0, di = 0;
+  if (c < n) {
+    for (int r = r0 + rg; r < r1; r += 4) {
+      zd v = X[(long long)r * n + c];
+      double a2 = v.x * v.x + v.y * v.y;
+      s += a2;
+      mx = fmax(mx, a2);
+      if (r == c) di = fabs(v.y);
+    }
+  }
+  ss[rg][threadIdx.x & 63] = s;
+  sm[rg][threadIdx.x & 63] = mx;
+  (void)di;
+  __syncthreads();
+  if (rg == 0 && c < n) {
+    double t = ss[0][threadIdx.x] + ss[1][threadIdx.x] + ss[2][threadIdx.x] + ss[3][threadIdx.x];
+    double m = fmax(fmax(sm[0][threadIdx.x], sm[1][threadIdx.x]), fmax(sm[2][threadIdx.x], sm[3][threadIdx.x]));
+    psum[(long long)blockIdx.y * n + c] = t;
+    pmax[(long long)blockIdx.y * n + c] = m;
+  }
+  if (c < n && c >= r0 && c < r1 && pdiag) {
+    // diagonal entry lives in this row chunk: record |Im x_cc|
+    zd v = X[(long long)c * n + c];
+    if (rg == 0) pdiag[c] = fabs(v.y);
+  }
+}
+__global__ __launch_bounds__(RB) void k_colnorm2(int n, int nrc, const double* psum, const double* pmax,
+                                                 const double* pdiag, double* out) {
+  __shared__ double sh[4];
+  double fro = 0, mx = 0, colsum = 0, dmx = 0;
+  for (int c = threadIdx.x; c < n; c += RB) {
+    double s = 0, m = 0;
+    for (int r = 0; r < nrc; ++r) {
+      s += psum[(long long)r * n + c];
+      m = fmax(m, pmax[(long long)r * n + c]);
+    }
+    fro += s;
+    mx = fmax(mx, m);
+    colsum += sqrt(s);
+    dmx = fmax(dmx, pdiag[c]);
+  }
+  fro = block_sum(fro, sh);
+  colsum = block_sum(colsum, sh);
+  mx = block_max(mx, sh);
+  dmx = block_max(dmx, sh);
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(fro);
+    out[1] = sqrt(mx);
+    out[2] = colsum;
+    out[3] = dmx;
+  }
+}
+int mat_norms(const zd* X, int n, double* out, double* scratch, hipStream_t st) {
+  int nrc = (n + 63) / 64;
+  if (nrc > 32) nrc = 32;
+  int rchunk = (n + nrc - 1) / nrc;
+  double* psum = scratch;
+  double* pmax = scratch + (long long)nrc * n;
+  double* pdiag = scratch + 2LL * nrc * n;
+  hipLaunchKernelGGL(k_colnorm1, dim3((n + 63) / 64, nrc), dim3(RB), 0, st, X, n, rchunk, psum, pmax, pdiag);
+  hipLaunchKernelGGL(k_colnorm2, dim3(1), dim3(RB), 0, st, n, nrc, psum, pmax, pdiag, out);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_add_identity(zd* X, int n, zd c) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[(long long)i * n + i] = zadd(X[(long long)i * n + i], c);
+}
+int add_identity(zd* X, int n, zd c, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_identity, dim3((n + RB - 1) / RB), dim3(RB), 0, st, X, n, c);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_sm_coef(const zd* trZ, zd c, zd trW, zd* coef) {
+  // coef = c Tr(Z) / (1 - c Tr W)
+  zd num = zmul(c, trZ[0]);
+  zd den = zsub(zmk(1.0, 0.0), zmul(c, trW));
+  coef[0] = zdiv(num, den);
+}
+__global__ void k_axpy_dev(const zd* coef, const zd* W, zd* Z, long long len) {
+  zd a = coef[0];
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+    Z[i] = zadd(Z[i], zmul(a, W[i]));
+}
+int sherman_morrison(zd* Z, const zd* W, int n, zd c, zd trW, zd* scratch_tr, double* scratch,
+                     hipStream_t st) {
+  (void)scratch;
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(RB), 0, st, Z, n, scratch_tr);
+  hipLaunchKernelGGL(k_sm_coef, dim3(1), dim3(1), 0, st, scratch_tr, c, trW, scratch_tr + 1);
+  long long len = (long long)n * n;
+  hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(len)), dim3(RB), 0, st, scratch_tr + 1, W, Z, len);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_make_G(const zd* H, const zd* W, zd* G, long long len) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    zd h = H[i], w = W[i];
+    // -i h - w/2
+    G[i] = zmk(h.y - 0.5 * w.x, -h.x - 0.5 * w.y);
+  }
+}
+int make_generator(const zd* H, const zd* W, zd* G, int n, hipStream_t st) {
+  long long len = (long long)n * n;
+  hipLaunchKernelGGL(k_make_G, dim3(grid_for(len)), dim3(RB), 0, st, H, W, G, len);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_scale_cols(zd* X, int n, const double* s, int invert) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    int j = (int)(t % n);
+    double f = invert ? 1.0 / s[j] : s[j];
+    X[t] = zscale(X[t], f);
+  }
+}
+int scale_cols(zd* X, int n, const double* s, int invert, hipStream_t st) {
+  long long len = (long long)n * n;
+  hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(len)), dim3(RB), 0, st, X, n, s, invert);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+__global__ void k_col_norms(const zd* X, int n, double* out) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0;
+  for (int i = 0; i < n; ++i) s += zabs2(X[(long long)i * n + j]);
+  out[j] = sqrt(s);
+}
+int col_norms(const zd* X, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_col_norms, dim3((n + 63) / 64), dim3(64), 0, st, X, n, out);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// y = A x (one wave per row) or y = A^H x (one thread per column)
+__global__ void k_gemv_n(const zd* A, int n, const zd* x, zd* y) {
+  int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double a = 0, b = 0;
+  for (int j = lane; j < n; j += 64) {
+    zd p = zmul(A[(long long)row * n + j], x[j]);
+    a += p.x;
+    b += p.y;
+  }
+  a = warp_sum(a);
+  b = warp_sum(b);
+  if (lane == 0) y[row] = zmk(a, b);
+}
+__global__ void k_gemv_c(const zd* A, int n, const zd* x, zd* y) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double a = 0, b = 0;
+  for (int i = 0; i < n; ++i) {
+    zd p = zcmul(A[(long long)i * n + j], x[i]);
+    a += p.x;
+    b += p.y;
+  }
+  y[j] = zmk(a, b);
+}
+int gemv(const zd* A, int n, int opA, const zd* x, zd* y, hipStream_t st) {
+  if (opA == OP_N) hipLaunchKernelGGL(k_gemv_n, dim3((n + 3) / 4), dim3(256), 0, st, A, n, x, y);
+  else hipLaunchKernelGGL(k_gemv_c, dim3((n + 63) / 64), dim3(64), 0, st, A, n, x, y);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_conj_copy(const zd* x, zd* y, long long len) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) y[i] = zconj(x[i]);
+}
+int conj_copy(const zd* x, zd* y, long long len, hipStream_t st) {
+  hipLaunchKernelGGL(k_conj_copy, dim3(grid_for(len)), dim3(RB), 0, st, x, y, len);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+__global__ void k_flip_ct(const zd* X, zd* Y, int n) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    int i = (int)(t / n), j = (int)(t - (long long)i * n);
+    Y[t] = zconj(X[(long long)(n - 1 - j) * n + (n - 1 - i)]);
+  }
+}
+__global__ void k_flip_rev(const zd* X, zd* Y, int n) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    int i = (int)(t / n), j = (int)(t - (long long)i * n);
+    Y[t] = X[(long long)(n - 1 - i) * n + (n - 1 - j)];
+  }
+}
+int flip_rev(const zd* X, zd* Y, int n, hipStream_t st) {
+  long long len = (long long)n * n;
+  hipLaunchKernelGGL(k_flip_rev, dim3(grid_for(len)), dim3(RB), 0, st, X, Y, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+int flip_conj_transpose(const zd* X, zd* Y, int n, hipStream_t st) {
+  long long len = (long long)n * n;
+  hipLaunchKernelGGL(k_flip_ct, dim3(grid_for(len)), dim3(RB), 0, st, X, Y, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+}  // namespace lindx

@@ -1,0 +1,98 @@
+// Internal definition of the lindx context and the operator layer shared by the drivers.
+#pragma once
+#include <functional>
+#include <string>
+#include <vector>
+#include <complex>
+#include "kernels.hpp"
+#include "../../include/lind.h"
+
+namespace lindx {
+
+typedef std::complex<double> cplx;
+
+struct Ctx {
+  int n = 0, d = 0;
+  long long n2 = 0;
+  lind_opts opts;
+  hipStream_t st = nullptr;
+  std::string err;
+  int route = LIND_ROUTE_EIG;
+  int prec = PREC_F64;
+  double kappa = 0.0;
+  double t_factor = 0.0, t_hess = 0.0, t_qr = 0.0;
+  double gnorm = 0.0;
+
+  // FP64 operator data
+  zd *H = nullptr, *L = nullptr, *G = nullptr, *T = nullptr, *Z = nullptr, *U = nullptr, *V = nullptr;
+  zd *s = nullptr, *sbar = nullptr;
+  zd *Lt = nullptr;    // L_j U (eigen route) or L_j Z (Schur route), stacked d x n x n
+  zd *Tadj = nullptr;  // J T^H J (upper triangular) for the adjoint Schur solve
+  std::vector<cplx> s_host;
+  // low-precision operands (complex64)
+  zf *U32 = nullptr, *V32 = nullptr, *Z32 = nullptr, *Lt32 = nullptr;
+  // work
+  zd *w1 = nullptr, *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *Ys = nullptr;
+  zf *a32 = nullptr, *b32 = nullptr, *Y32 = nullptr;
+  zd* dsc = nullptr;      // device scalars
+  double* dscr = nullptr; // reduction scratch
+  long long dscr_len = 0;
+  zd* hsc = nullptr;      // pinned host scalars
+  // Krylov bases (lazily allocated): outer and inner
+  zd* K1 = nullptr;
+  int K1cap = 0;
+  zd* K2 = nullptr;
+  int K2cap = 0;
+  // eigs: cached W = R_mu(I) and Tr W
+  bool W_valid = false;
+  cplx W_mu = 0.0, W_tr = 0.0;
+  zd* Wmu = nullptr;
+  std::vector<void*> allocs;
+
+  ~Ctx();
+  int fail(int code, const std::string& msg) { err = msg; return code; }
+  template <typename T> int alloc(T** p, size_t count) {
+    void* q = nullptr;
+    if (count == 0) { *p = nullptr; return 0; }
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return LIND_ENOMEM;
+    allocs.push_back(q);
+    *p = (T*)q;
+    return 0;
+  }
+  int ensure_krylov(int which, int slots);
+  int sync();
+  // host scalar fetch: copies `count` zd from device pointer into the pinned buffer and syncs
+  int fetch(const void* dptr, size_t bytes);
+};
+
+// operator layer (FP64 unless noted); all buffers are n x n complex128 on the device
+int op_gemm(Ctx& c, int prec, int M, int N, int K, const void* A, long long lda, int opA, const void* B,
+            long long ldb, int opB, void* C, long long ldc, cplx alpha, int beta);
+// X = (S - mu)^{-1} Y in precision prec (route of the context); adjoint: (S* - conj(mu))^{-1}
+int op_sinv(Ctx& c, const zd* Y, zd* X, cplx mu, int prec, bool adjoint);
+// out = Phi(xi) in precision prec
+int op_phi(Ctx& c, const zd* xi, zd* out, int prec);
+// out = L(rho) (FP64); hermitian_in: rho is Hermitian (fewer products)
+int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in);
+// out = L*(X) (FP64)
+int op_apply_adj(Ctx& c, const zd* X, zd* out);
+// norms of an n x n matrix to host: fro, max, colsum, max|Im diag|
+int op_norms(Ctx& c, const zd* X, double out[4]);
+int op_trace(Ctx& c, const zd* X, cplx* tr);
+int op_nrm(Ctx& c, const zd* x, double* out);
+
+// generic right-preconditioned restarted GMRES on n*n vectors, FP64 Krylov basis (K2)
+struct GmresResult {
+  int iters = 0;
+  int cycles = 0;
+  double resid = 0.0;      // final residual 2-norm (true residual at the last restart)
+  double resid0 = 0.0;
+  bool converged = false;
+};
+int gmres(Ctx& c, const std::function<int(const zd*, zd*)>& A, const std::function<int(const zd*, zd*)>* P,
+          const zd* b, zd* x, bool x_zero, int m, int max_cycles, double rtol, double atol, GmresResult& res,
+          double t_deadline);
+
+double now_s();
+
+}  // namespace lindx

@@ -1,0 +1,566 @@
+// One-time FP64 factorisation of the no-jump generator G on the GPU.
+//
+//   G = Z T Z^H    (complex Schur form, Z unitary, T upper triangular)
+//
+// 1. Householder reduction to upper Hessenberg form (one reflector per column; the reflector
+//    build is one workgroup, the two-sided updates are bandwidth-bound multi-workgroup kernels).
+// 2. Multishift QR iteration (complex single-shift bulges, up to 15 per sweep, shifts from the
+//    eigenvalues of the trailing block).  A chain of bulges is chased down the diagonal in
+//    64 x 64 windows that advance by 32 rows: each window is chased in LDS by one wave which
+//    accumulates the window's unitary U_w; the product of U_w^H with the rest of the window's
+//    rows inside the active block is applied at once (the next window reads it), while the
+//    updates of the rows above the window, of the columns right of the active block, and of Z
+//    are deferred to the end of the sweep and applied window after window by row/column-parallel
+//    kernels.  Active blocks of at most 64 rows are finished in LDS by one wave.
+// 3. Eigenvectors of T by back substitution (one wave per column) and the inverse of the unit
+//    upper-triangular eigenvector matrix, giving the eigenbasis route G = U diag(s) U^{-1}.
+#include <vector>
+#include <chrono>
+#include "kernels.hpp"
+#include "lds_qr.hpp"
+
+namespace lindx {
+
+static constexpr int WIN = 64;    // window rows
+static constexpr int STEP = 32;   // window advance
+static constexpr int NSMAX = 15;  // bulges per sweep (WIN >= STEP + 2*NSMAX + 1)
+static constexpr int MAXWIN = 256;
+
+struct WinList {
+  int nwin;
+  int r[MAXWIN];
+  int bw[MAXWIN];
+};
+
+// ------------------------------------------------------------------ Hessenberg reduction -----
+// Reflector for column k: P = I - gam u u^H with u = x + ph*||x|| e_{k+1}, P x = -ph*||x|| e_{k+1}.
+__global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, double* gam) {
+  __shared__ double sh[4];
+  __shared__ double tot;
+  double s = 0;
+  for (int i = k + 1 + threadIdx.x; i < n; i += 256) s += zabs2(A[(long long)i * n + k]);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) tot = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  double nrm2 = tot;
+  zd x0 = A[(long long)(k + 1) * n + k];
+  double tail = nrm2 - zabs2(x0);
+  double nrm = sqrt(nrm2);
+  double ax0 = sqrt(zabs2(x0));
+  zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
+  bool skip = !(tail > 0.0);
+  for (int i = threadIdx.x; i < n; i += 256) {
+    zd v = zmk(0, 0);
+    if (!skip && i > k) v = A[(long long)i * n + k];
+    if (!skip && i == k + 1) v = zadd(x0, zscale(ph, nrm));
+    u[i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // u^H u = 2 ||x|| (||x|| + |x0|)
+    gam[0] = skip ? 0.0 : 1.0 / (nrm * (nrm + ax0));
+  }
+  if (!skip) {
+    for (int i = k + 1 + threadIdx.x; i < n; i += 256)
+      A[(long long)i * n + k] = (i == k + 1) ? zscale(ph, -nrm) : zmk(0, 0);
+  }
+}
+
+// partial[rc][j] = sum_{i in chunk rc, i > k} conj(u_i) A_ij, j > k
+__global__ __launch_bounds__(256) void k_hh_left_part(const zd* A, int n, int k, const zd* u, int rchunk,
+                                                      zd* part) {
+  __shared__ zd ss[4][64];
+  int j = k + 1 + blockIdx.x * 64 + (threadIdx.x & 63);
+  int rg = threadIdx.x >> 6;
+  int r0 = k + 1 + blockIdx.y * rchunk;
+  int r1 = r0 + rchunk < n ? r0 + rchunk : n;
+  zd s = zmk(0, 0);
+  if (j < n)
+    for (int i = r0 + rg; i < r1; i += 4) s = zadd(s, zcmul(u[i], A[(long long)i * n + j]));
+  ss[rg][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (rg == 0 && j < n) {
+    zd t = zadd(zadd(ss[0][threadIdx.x], ss[1][threadIdx.x]), zadd(ss[2][threadIdx.x], ss[3][threadIdx.x]));
+    part[(long long)blockIdx.y * n + j] = t;
+  }
+}
+__global__ void k_hh_left_reduce(const zd* part, int nrc, int n, int k, const double* gam, zd* w) {
+  int j = k + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  zd s = zmk(0, 0);
+  for (int r = 0; r < nrc; ++r) s = zadd(s, part[(long long)r * n + j]);
+  w[j] = zscale(s, gam[0]);
+}
+__global__ void k_hh_left_update(zd* A, int n, int k, const zd* u, const zd* w) {
+  long long rows = n - k - 1;
+  long long tot = rows * rows;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    int i = k + 1 + (int)(t / rows);
+    int j = k + 1 + (int)(t % rows);
+    A[(long long)i * n + j] = zsub(A[(long long)i * n + j], zmul(u[i], w[j]));
+  }
+}
+// y_i = gam * sum_{j > k} X_ij u_j for the rows of A (first n waves) and Z (next n waves)
+__global__ void k_hh_right_y(const zd* A, const zd* Z, int n, int k, const zd* u, const double* gam, zd* y) {
+  int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= 2 * n) return;
+  const zd* X = row < n ? A : Z;
+  int i = row < n ? row : row - n;
+  zd s = zmk(0, 0);
+  for (int j = k + 1 + lane; j < n; j += 64) s = zadd(s, zmul(X[(long long)i * n + j], u[j]));
+  double a = s.x, b = s.y;
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  if (lane == 0) y[row] = zscale(zmk(a, b), gam[0]);
+}
+__global__ void k_hh_right_update(zd* A, zd* Z, int n, int k, const zd* u, const zd* y) {
+  long long cols = n - k - 1;
+  long long tot = 2LL * n * cols;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    long long row = t / cols;
+    int j = k + 1 + (int)(t % cols);
+    zd* X = row < n ? A : Z;
+    long long i = row < n ? row : row - n;
+    X[i * n + j] = zsub(X[i * n + j], zmul(y[row], zconj(u[j])));
+  }
+}
+
+static int gridN(long long len) {
+  long long nb = (len + 255) / 256;
+  if (nb > 16384) nb = 16384;
+  return (int)(nb < 1 ? 1 : nb);
+}
+
+static int hessenberg(zd* A, zd* Z, int n, zd* u, double* gam, zd* part, zd* w, zd* y, hipStream_t st) {
+  const int nrc = 16;
+  for (int k = 0; k + 2 < n; ++k) {
+    int rows = n - k - 1;
+    int rchunk = (rows + nrc - 1) / nrc;
+    hipLaunchKernelGGL(k_hh_vec, dim3(1), dim3(256), 0, st, A, n, k, u, gam);
+    hipLaunchKernelGGL(k_hh_left_part, dim3((rows + 63) / 64, nrc), dim3(256), 0, st, A, n, k, u, rchunk, part);
+    hipLaunchKernelGGL(k_hh_left_reduce, dim3((rows + 255) / 256), dim3(256), 0, st, part, nrc, n, k, gam, w);
+    hipLaunchKernelGGL(k_hh_left_update, dim3(gridN((long long)rows * rows)), dim3(256), 0, st, A, n, k, u, w);
+    hipLaunchKernelGGL(k_hh_right_y, dim3((2 * n + 3) / 4), dim3(256), 0, st, A, Z, n, k, u, gam, y);
+    hipLaunchKernelGGL(k_hh_right_update, dim3(gridN(2LL * n * rows)), dim3(256), 0, st, A, Z, n, k, u, y);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// ------------------------------------------------------------------ QR iteration -------------
+__global__ void k_identity(zd* Z, int n) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    long long i = t / n, j = t % n;
+    Z[t] = (i == j) ? zmk(1, 0) : zmk(0, 0);
+  }
+}
+__global__ void k_extract_diag_sub(const zd* A, int n, zd* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    out[i] = A[(long long)i * n + i];
+    out[n + i] = (i + 1 < n) ? A[(long long)(i + 1) * n + i] : zmk(0, 0);
+  }
+}
+__global__ void k_set_zero(zd* A, long long idx) { A[idx] = zmk(0, 0); }
+__global__ void k_zero_lower(zd* A, int n) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    long long i = t / n, j = t % n;
+    if (i > j) A[t] = zmk(0, 0);
+  }
+}
+__global__ void k_zero_int(int* p, int cnt) {
+  int i = threadIdx.x;
+  if (i < cnt) p[i] = 0;
+}
+
+// Shifts for a sweep: eigenvalues of the trailing ns x ns block (rows/cols [lo, lo+ns)).
+// exceptional != 0: ad hoc shifts around the last diagonal entry.
+__global__ __launch_bounds__(64) void k_shifts(const zd* A, int n, int lo, int ns, int exceptional,
+                                                zd* shifts) {
+  __shared__ zd Hs[64 * LDM];
+  const int t = threadIdx.x;
+  for (int i = 0; i < ns; ++i)
+    for (int j = t; j < ns; j += 64) Hs[i * LDM + j] = A[(long long)(lo + i) * n + lo + j];
+  __syncthreads();
+  if (exceptional) {
+    zd d = Hs[(ns - 1) * LDM + ns - 1];
+    double sc = cabs1(A[(long long)(lo + ns - 1) * n + lo + ns - 2]) + cabs1(Hs[(ns - 1) * LDM + ns - 2]);
+    if (t < ns) {
+      double th = 6.283185307179586 * (t + 0.5) / ns;
+      shifts[t] = zadd(d, zmk(0.75 * sc * cos(th), 0.75 * sc * sin(th)));
+    }
+    return;
+  }
+  int rc = qr_lds(Hs, nullptr, ns, 0);
+  if (t < ns) shifts[t] = Hs[t * LDM + t];
+  (void)rc;
+}
+
+// Chase the bulge chain through window rows/cols [r, r+bw).  One wave.
+__global__ __launch_bounds__(64) void k_chase(zd* A, int n, int ilo, int ihi, int r, int bw,
+                                               const zd* shifts, int ns, int* cnt, zd* Uout) {
+  __shared__ zd Hs[WIN * LDM];
+  __shared__ zd Us[WIN * LDM];
+  const int t = threadIdx.x;
+  for (int i = 0; i < bw; ++i)
+    for (int j = t; j < bw; j += 64) {
+      Hs[i * LDM + j] = A[(long long)(r + i) * n + r + j];
+      Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
+    }
+  __syncthreads();
+  const bool at_end = (r + bw - 1 >= ihi);
+  const int pmax = at_end ? ihi - 1 : r + bw - 3;
+  const int pmin = (r == ilo) ? ilo : r + 1;
+  int prev = 0x7fffffff;
+  for (int b = 0; b < ns; ++b) {
+    int p = ilo + cnt[b];
+    int lim = pmax;
+    // bulge b may rotate at pair q only after bulge b-1 has rotated at q+2 (the order of the
+    // interleaved chase), otherwise its column update would meet b-1's bulge entry
+    if (prev <= ihi - 1 && prev - 3 < lim) lim = prev - 3;
+    while (p <= lim && p >= pmin) {
+      const int q = p - r;
+      zd f, g;
+      if (p == ilo) {
+        f = zsub(Hs[q * LDM + q], shifts[b]);
+        g = Hs[(q + 1) * LDM + q];
+      } else {
+        f = Hs[q * LDM + q - 1];
+        g = Hs[(q + 1) * LDM + q - 1];
+      }
+      double cs;
+      zd sn, rr;
+      zlartg(f, g, cs, sn, rr);
+      __syncthreads();
+      rot_rows(Hs, LDM, q, (p == ilo) ? q : q - 1, bw - 1, cs, sn);
+      __syncthreads();
+      int r1 = q + 2 < bw - 1 ? q + 2 : bw - 1;
+      rot_cols(Hs, LDM, q, 0, r1, cs, sn);
+      rot_cols(Us, LDM, q, 0, bw - 1, cs, sn);
+      __syncthreads();
+      if (p > ilo && t == 0) Hs[(q + 1) * LDM + q - 1] = zmk(0, 0);
+      __syncthreads();
+      ++p;
+    }
+    __syncthreads();
+    if (t == 0) cnt[b] = p - ilo;
+    prev = p;
+  }
+  __syncthreads();
+  for (int i = 0; i < bw; ++i)
+    for (int j = t; j < bw; j += 64) {
+      A[(long long)(r + i) * n + r + j] = Hs[i * LDM + j];
+      Uout[i * WIN + j] = Us[i * LDM + j];
+    }
+}
+
+// Finish an active block [lo, hi] (size <= 64) in LDS: Schur form of the block, unitary to Uout.
+__global__ __launch_bounds__(64) void k_small_block(zd* A, int n, int lo, int hi, zd* Uout, int* info) {
+  __shared__ zd Hs[WIN * LDM];
+  __shared__ zd Us[WIN * LDM];
+  const int m = hi - lo + 1;
+  const int t = threadIdx.x;
+  for (int i = 0; i < m; ++i)
+    for (int j = t; j < m; j += 64) {
+      Hs[i * LDM + j] = A[(long long)(lo + i) * n + lo + j];
+      Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
+    }
+  __syncthreads();
+  int rc = qr_lds(Hs, Us, m, 1);
+  if (t == 0) info[0] = rc;
+  for (int i = 0; i < m; ++i)
+    for (int j = t; j < m; j += 64) {
+      A[(long long)(lo + i) * n + lo + j] = (i > j) ? zmk(0, 0) : Hs[i * LDM + j];
+      Uout[i * WIN + j] = Us[i * LDM + j];
+    }
+}
+
+// rows [r, r+bw) x columns [c0, c1] <- U^H (those rows).  One workgroup per 64 columns.
+__global__ __launch_bounds__(256) void k_left_apply(zd* A, int n, int r, int bw, int c0, int c1, const zd* U) {
+  __shared__ zd Ul[WIN * LDM];
+  __shared__ zd Xs[WIN * LDM];
+  const int t = threadIdx.x;
+  const int cb = c0 + blockIdx.x * 64;
+  for (int e = t; e < bw * bw; e += 256) {
+    int i = e / bw, j = e - i * bw;
+    Ul[i * LDM + j] = U[i * WIN + j];
+  }
+  for (int e = t; e < bw * 64; e += 256) {
+    int i = e / 64, c = e - i * 64;
+    int col = cb + c;
+    Xs[i * LDM + c] = (col <= c1) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
+  }
+  __syncthreads();
+  const int c = t & 63;
+  const int col = cb + c;
+  for (int i = t >> 6; i < bw; i += 4) {
+    zd acc = zmk(0, 0);
+    for (int k = 0; k < bw; ++k) acc = zadd(acc, zcmul(Ul[k * LDM + i], Xs[k * LDM + c]));
+    if (col <= c1) A[(long long)(r + i) * n + col] = acc;
+  }
+}
+
+// Deferred right updates: for each window w in order, rows i of X (i < limit_w) get
+// X[i, r_w : r_w+bw_w] <- X[i, r_w : r_w+bw_w] U_w.  limit_w = r_w (mode 1) or nrows (mode 0).
+__global__ __launch_bounds__(256) void k_right_apply_seq(zd* X, int ldx, int nrows, WinList wl, const zd* Ubuf,
+                                                         int mode) {
+  __shared__ zd Ul[WIN * LDM];
+  __shared__ zd Xs[32 * LDM];
+  const int t = threadIdx.x;
+  const int rb = blockIdx.x * 32;
+  for (int w = 0; w < wl.nwin; ++w) {
+    const int r = wl.r[w], bw = wl.bw[w];
+    const int lim = mode ? r : nrows;
+    if (rb >= lim) continue;  // uniform over the block
+    const zd* U = Ubuf + (long long)w * WIN * WIN;
+    __syncthreads();
+    for (int e = t; e < bw * bw; e += 256) {
+      int i = e / bw, j = e - i * bw;
+      Ul[i * LDM + j] = U[i * WIN + j];
+    }
+    for (int e = t; e < 32 * bw; e += 256) {
+      int i = e / bw, j = e - i * bw;
+      int row = rb + i;
+      Xs[i * LDM + j] = (row < lim) ? X[(long long)row * ldx + r + j] : zmk(0, 0);
+    }
+    __syncthreads();
+    for (int e = t; e < 32 * bw; e += 256) {
+      int i = e / bw, j = e - i * bw;
+      int row = rb + i;
+      zd acc = zmk(0, 0);
+      for (int k = 0; k < bw; ++k) acc = zadd(acc, zmul(Xs[i * LDM + k], Ul[k * LDM + j]));
+      if (row < lim) X[(long long)row * ldx + r + j] = acc;
+    }
+  }
+}
+
+// Deferred left updates of the columns right of the active block: columns (hi, n).
+__global__ __launch_bounds__(256) void k_left_apply_seq(zd* A, int n, int c0, WinList wl, const zd* Ubuf) {
+  __shared__ zd Ul[WIN * LDM];
+  __shared__ zd Xs[WIN * 33];
+  const int t = threadIdx.x;
+  const int cb = c0 + blockIdx.x * 32;
+  for (int w = 0; w < wl.nwin; ++w) {
+    const int r = wl.r[w], bw = wl.bw[w];
+    const zd* U = Ubuf + (long long)w * WIN * WIN;
+    __syncthreads();
+    for (int e = t; e < bw * bw; e += 256) {
+      int i = e / bw, j = e - i * bw;
+      Ul[i * LDM + j] = U[i * WIN + j];
+    }
+    for (int e = t; e < bw * 32; e += 256) {
+      int i = e / 32, c = e - i * 32;
+      int col = cb + c;
+      Xs[i * 33 + c] = (col < n) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
+    }
+    __syncthreads();
+    for (int e = t; e < bw * 32; e += 256) {
+      int i = e / 32, c = e - i * 32;
+      int col = cb + c;
+      zd acc = zmk(0, 0);
+      for (int k = 0; k < bw; ++k) acc = zadd(acc, zcmul(Ul[k * LDM + i], Xs[k * 33 + c]));
+      if (col < n) A[(long long)(r + i) * n + col] = acc;
+    }
+  }
+}
+
+static void apply_deferred(zd* A, zd* Z, int n, int hi, const WinList& wl, const zd* Ubuf, hipStream_t st) {
+  // Z: all rows
+  hipLaunchKernelGGL(k_right_apply_seq, dim3((n + 31) / 32), dim3(256), 0, st, Z, n, n, wl, Ubuf, 0);
+  // A: rows above each window
+  int maxr = 0;
+  for (int w = 0; w < wl.nwin; ++w) maxr = wl.r[w] > maxr ? wl.r[w] : maxr;
+  if (maxr > 0) hipLaunchKernelGGL(k_right_apply_seq, dim3((maxr + 31) / 32), dim3(256), 0, st, A, n, maxr, wl, Ubuf, 1);
+  // A: columns right of the active block
+  if (hi + 1 < n)
+    hipLaunchKernelGGL(k_left_apply_seq, dim3((n - hi - 1 + 31) / 32), dim3(256), 0, st, A, n, hi + 1, wl, Ubuf);
+}
+
+static inline double h_cabs1(zd a) { return fabs(a.x) + fabs(a.y); }
+
+int schur_factor(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr) {
+  return schur_factor_ex(A, Z, n, st, t_hess, t_qr, 0);
+}
+
+int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int stop_after_hessenberg) {
+  if (n < 1) return -1;
+  if ((n + STEP - 1) / STEP + 2 > MAXWIN) return -1;
+  zd *u = nullptr, *part = nullptr, *w = nullptr, *y = nullptr, *Ubuf = nullptr, *shifts = nullptr, *ds = nullptr;
+  double* gam = nullptr;
+  int *cnt = nullptr, *info = nullptr;
+  const int nrc = 16;
+  auto cleanup = [&]() {
+    hipFree(u); hipFree(part); hipFree(w); hipFree(y); hipFree(Ubuf); hipFree(shifts); hipFree(ds);
+    hipFree(gam); hipFree(cnt); hipFree(info);
+  };
+  if (hipMalloc(&u, sizeof(zd) * n) != hipSuccess || hipMalloc(&part, sizeof(zd) * (size_t)nrc * n) != hipSuccess ||
+      hipMalloc(&w, sizeof(zd) * n) != hipSuccess || hipMalloc(&y, sizeof(zd) * 2 * n) != hipSuccess ||
+      hipMalloc(&Ubuf, sizeof(zd) * (size_t)MAXWIN * WIN * WIN) != hipSuccess ||
+      hipMalloc(&shifts, sizeof(zd) * 64) != hipSuccess || hipMalloc(&ds, sizeof(zd) * 2 * n) != hipSuccess ||
+      hipMalloc(&gam, sizeof(double) * 4) != hipSuccess || hipMalloc(&cnt, sizeof(int) * 64) != hipSuccess ||
+      hipMalloc(&info, sizeof(int) * 4) != hipSuccess) {
+    cleanup();
+    return -5;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_identity, dim3(gridN((long long)n * n)), dim3(256), 0, st, Z, n);
+  if (n > 2) hessenberg(A, Z, n, u, gam, part, w, y, st);
+  hipStreamSynchronize(st);
+  auto t1 = std::chrono::steady_clock::now();
+  if (t_hess) *t_hess = std::chrono::duration<double>(t1 - t0).count();
+  if (stop_after_hessenberg) {
+    cleanup();
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+  }
+
+  const double ulp = 2.220446049250313e-16;
+  std::vector<zd> hds(2 * (size_t)n);
+  int ihi = n - 1;
+  int stall = 0, sweeps = 0, last_ihi = -1, last_ilo = -1;
+  int status = 0;
+  const long long max_sweeps = 20LL * n / NSMAX + 400;
+  while (ihi > 0) {
+    hipLaunchKernelGGL(k_extract_diag_sub, dim3((n + 255) / 256), dim3(256), 0, st, A, n, ds);
+    if (hipMemcpyAsync(hds.data(), ds, sizeof(zd) * 2 * n, hipMemcpyDeviceToHost, st) != hipSuccess) { status = -4; break; }
+    if (hipStreamSynchronize(st) != hipSuccess) { status = -4; break; }
+    auto negligible = [&](int i) {  // subdiagonal entry (i+1, i)
+      double tst = h_cabs1(hds[i]) + h_cabs1(hds[i + 1]);
+      return h_cabs1(hds[n + i]) <= fmax(ulp * tst, 1e-300);
+    };
+    while (ihi > 0 && negligible(ihi - 1)) {
+      hipLaunchKernelGGL(k_set_zero, dim3(1), dim3(1), 0, st, A, (long long)ihi * n + ihi - 1);
+      --ihi;
+    }
+    if (ihi <= 0) break;
+    int ilo = ihi - 1;
+    while (ilo > 0 && !negligible(ilo - 1)) --ilo;
+    if (ilo > 0) hipLaunchKernelGGL(k_set_zero, dim3(1), dim3(1), 0, st, A, (long long)ilo * n + ilo - 1);
+    if (ihi == last_ihi && ilo == last_ilo) ++stall; else stall = 0;
+    last_ihi = ihi;
+    last_ilo = ilo;
+    const int size = ihi - ilo + 1;
+    WinList wl;
+    if (size <= WIN) {
+      hipLaunchKernelGGL(k_small_block, dim3(1), dim3(64), 0, st, A, n, ilo, ihi, Ubuf, info);
+      wl.nwin = 1;
+      wl.r[0] = ilo;
+      wl.bw[0] = size;
+      apply_deferred(A, Z, n, ihi, wl, Ubuf, st);
+      int hinfo = 0;
+      hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st);
+      hipStreamSynchronize(st);
+      if (hinfo != 0) { status = -3; break; }
+      ihi = ilo - 1;
+      continue;
+    }
+    if (++sweeps > max_sweeps) { status = -3; break; }
+    int ns = size / 8;
+    if (ns > NSMAX) ns = NSMAX;
+    if (ns < 2) ns = 2;
+    const int exceptional = (stall > 0 && stall % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_shifts, dim3(1), dim3(64), 0, st, A, n, ihi - ns + 1, ns, exceptional, shifts);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, cnt, 64);
+    wl.nwin = 0;
+    for (int r = ilo;; r += STEP) {
+      int bw = ihi + 1 - r < WIN ? ihi + 1 - r : WIN;
+      zd* Uw = Ubuf + (long long)wl.nwin * WIN * WIN;
+      hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, st, A, n, ilo, ihi, r, bw, shifts, ns, cnt, Uw);
+      if (r + bw <= ihi)
+        hipLaunchKernelGGL(k_left_apply, dim3((ihi - (r + bw) + 1 + 63) / 64), dim3(256), 0, st, A, n, r, bw, r + bw,
+                           ihi, (const zd*)Uw);
+      wl.r[wl.nwin] = r;
+      wl.bw[wl.nwin] = bw;
+      ++wl.nwin;
+      if (r + bw - 1 >= ihi) break;
+    }
+    apply_deferred(A, Z, n, ihi, wl, Ubuf, st);
+  }
+  if (status == 0) hipLaunchKernelGGL(k_zero_lower, dim3(gridN((long long)n * n)), dim3(256), 0, st, A, n);
+  hipStreamSynchronize(st);
+  auto t2 = std::chrono::steady_clock::now();
+  if (t_qr) *t_qr = std::chrono::duration<double>(t2 - t1).count();
+  if (hipGetLastError() != hipSuccess && status == 0) status = -4;
+  cleanup();
+  return status;
+}
+
+// ------------------------------------------------------------------ triangular solves --------
+// mode 0 (eigenvectors of T): column j solves (T - T_jj I) y = 0, y_j = 1.
+// mode 1 (inverse of a unit upper-triangular M): column j solves M x = e_j.
+// One wave per column; y lives in LDS; x_i = -(sum_{k=i+1..j} M_ik x_k) / d_i.
+__global__ __launch_bounds__(64) void k_upper_backsolve(const zd* M, zd* X, int n, int mode) {
+  extern __shared__ zd ys[];
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double ulp = 2.220446049250313e-16;
+  zd mjj = M[(long long)j * n + j];
+  double smin = fmax(ulp * cabs1(mjj), 1e-290);
+  if (lane == 0) ys[j] = zmk(1, 0);
+  __syncthreads();
+  for (int i = j - 1; i >= 0; --i) {
+    double a = 0, b = 0;
+    const zd* row = M + (long long)i * n;
+    for (int k = i + 1 + lane; k <= j; k += 64) {
+      zd p = zmul(row[k], ys[k]);
+      a += p.x;
+      b += p.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 64);
+      b += __shfl_xor(b, o, 64);
+    }
+    zd acc = zmk(-a, -b);
+    zd xi;
+    if (mode == 0) {
+      zd den = zsub(row[i], mjj);
+      if (cabs1(den) < smin) den = zmk(smin, 0);
+      xi = zdiv(acc, den);
+    } else {
+      xi = acc;
+    }
+    if (lane == 0) ys[i] = xi;
+    __syncthreads();
+  }
+  for (int i = lane; i < n; i += 64) X[(long long)i * n + j] = (i <= j) ? ys[i] : zmk(0, 0);
+}
+
+static int backsolve_lds_attr(size_t lds) {
+  if (lds > 160 * 1024) return -1;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_upper_backsolve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+          hipSuccess)
+    return -1;
+  return 0;
+}
+int trevec(const zd* T, zd* Y, int n, hipStream_t st) {
+  size_t lds = sizeof(zd) * (size_t)n;
+  if (backsolve_lds_attr(lds)) return -1;
+  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(64), lds, st, T, Y, n, 0);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+int triinv_unit(const zd* Y, zd* Yinv, int n, hipStream_t st) {
+  size_t lds = sizeof(zd) * (size_t)n;
+  if (backsolve_lds_attr(lds)) return -1;
+  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(64), lds, st, Y, Yinv, n, 1);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+__global__ void k_diag(const zd* T, zd* s, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) s[i] = T[(long long)i * n + i];
+}
+int diag_extract(const zd* T, zd* s, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag, dim3((n + 255) / 256), dim3(256), 0, st, T, s, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+}  // namespace lindx

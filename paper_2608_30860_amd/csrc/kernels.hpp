@@ -1,0 +1,102 @@
+// Launch wrappers of the lindx device kernels.  Host-callable, all asynchronous on `st`.
+#pragma once
+#include "common.hpp"
+
+namespace lindx {
+
+// ---------------------------------------------------------------------------
+// complex matrix products  C = alpha * sum_b op(A_b) op(B_b)  (+ C)  with epilogues
+// ---------------------------------------------------------------------------
+enum { EPI_NONE = 0, EPI_DIV = 1, EPI_HERM_ADD = 2 };
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+
+struct GemmDesc {
+  int M = 0, N = 0, K = 0, nbatch = 1;       // per-batch sizes (complex entries)
+  const void* A = nullptr; long long lda = 0, sA = 0; int opA = OP_N;
+  const void* B = nullptr; long long ldb = 0, sB = 0; int opB = OP_N;
+  void* C = nullptr; long long ldc = 0;
+  double ar = 1.0, ai = 0.0;                  // alpha
+  int beta = 0;                               // 1: accumulate into C
+  int epi = EPI_NONE;
+  const zd* dr = nullptr; const zd* dc = nullptr; double dzr = 0.0, dzi = 0.0;  // EPI_DIV
+  const void* E = nullptr; long long lde = 0;                                   // EPI_HERM_ADD
+  int out64 = 0;                              // float kernels: write complex128 output
+};
+
+// prec = PREC_F64: A, B, C, E are complex128.
+// prec = PREC_F32 / PREC_BF16X3: A, B are complex64; C (and E) complex64 unless out64.
+int gemm(int prec, const GemmDesc& g, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// level-1 / elementwise kernels on complex128 vectors of length len (= n*n)
+// ---------------------------------------------------------------------------
+// h[j] = <V_j, w> = sum_i conj(V[j*ld + i]) w[i], j < k.  Result left on device (h) in FP64.
+int multi_dot(const zd* V, long long ld, int k, const zd* w, long long len, zd* h, zd* scratch,
+              hipStream_t st);
+// w -= sum_j h[j] V_j   (coeff = -1)  or  out = sum_j h[j] V_j (accumulate = 0, coeff = +1)
+int multi_axpy(const zd* V, long long ld, int k, const zd* h, zd* w, long long len, int accumulate,
+               double coeff, hipStream_t st);
+// ||w||_2 into out (device double); scratch >= 1024 doubles
+int nrm2(const zd* w, long long len, double* out, double* scratch, hipStream_t st);
+// w *= 1/s where s is a device double (scalar produced by nrm2)
+int scale_by_inv(zd* w, long long len, const double* s, hipStream_t st);
+// y = a*x + b*y with host scalars
+int axpby(zd a, const zd* x, zd b, zd* y, long long len, hipStream_t st);
+int copy(const zd* x, zd* y, long long len, hipStream_t st);
+int fill_zero(void* p, long long bytes, hipStream_t st);
+// complex128 <-> complex64
+int to_c64(const zd* x, zf* y, long long len, hipStream_t st);
+int to_c128(const zf* x, zd* y, long long len, hipStream_t st);
+// X <- scale * (X + X^H)/2 (n x n, in place); optional: divide by the real part of the trace
+// (trace taken after hermitisation).  trace_out (device zd) receives the trace before scaling.
+int hermitize(zd* X, int n, int normalize_trace, zd* trace_out, double* scratch, hipStream_t st);
+// trace of n x n X into out (device zd)
+int trace(const zd* X, int n, zd* out, double* scratch, hipStream_t st);
+// norms of an n x n matrix: out[0] = Frobenius, out[1] = max |x_ij|, out[2] = sum_j ||col_j||_2
+// (an upper bound on the trace norm), out[3] = max_i |Im x_ii|.  scratch >= 4*1024 doubles.
+int mat_norms(const zd* X, int n, double* out, double* scratch, hipStream_t st);
+// X += c * I
+int add_identity(zd* X, int n, zd c, hipStream_t st);
+// Sherman-Morrison step: Z += coef * W where coef = c*Tr(Z)/(1 - c*trW) computed on device
+int sherman_morrison(zd* Z, const zd* W, int n, zd c, zd trW, zd* scratch_tr, double* scratch,
+                     hipStream_t st);
+// D = G X (n x n) elementwise helpers for the generator: G = -iH - 1/2 W
+int make_generator(const zd* H, const zd* W, zd* G, int n, hipStream_t st);
+// scale columns: U[:, j] *= s[j], V[:, j] /= conj?  (s real) -- U and V both n x n
+int scale_cols(zd* X, int n, const double* s, int invert, hipStream_t st);
+int col_norms(const zd* X, int n, double* out, hipStream_t st);
+// y = A x for n x n A (opA = N or C), vectors of length n
+int gemv(const zd* A, int n, int opA, const zd* x, zd* y, hipStream_t st);
+// out[i] = conj(x[i]) for complex arrays (used for sigma-bar)
+int conj_copy(const zd* x, zd* y, long long len, hipStream_t st);
+// X <- J X^T J etc: reverse both indices and transpose-conjugate (adjoint triangular form)
+int flip_conj_transpose(const zd* X, zd* Y, int n, hipStream_t st);
+// Y[i][j] = X[n-1-i][n-1-j]
+int flip_rev(const zd* X, zd* Y, int n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// factorisation of G (FP64): Hessenberg reduction, Schur form by QR iteration,
+// eigenvectors of the triangular factor and the inverse of the eigenvector matrix.
+// ---------------------------------------------------------------------------
+struct SchurWork;
+// In: A (n x n, overwritten by T, upper triangular), Z (n x n) out: Schur vectors, A = Z T Z^H
+// on entry A holds G.  Returns 0 on success, -3 if the QR iteration failed to converge.
+int schur_factor(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr);
+int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int stop_after_hessenberg);
+// Y: eigenvectors of upper-triangular T (unit diagonal), Yinv = Y^{-1} (unit upper triangular)
+int trevec(const zd* T, zd* Y, int n, hipStream_t st);
+int triinv_unit(const zd* Y, zd* Yinv, int n, hipStream_t st);
+// extract diagonal of T into s
+int diag_extract(const zd* T, zd* s, int n, hipStream_t st);
+
+// small dense eigenproblem on the device (one workgroup, m <= 64):
+// in: A (m x m, leading dim lda) -- general complex.  out: w (m eigenvalues), Y (m x m right
+// eigenvectors, column j for w[j], unit 2-norm), info (device int: 0 ok, 1 no convergence).
+int small_eig(const zd* A, int lda, int m, zd* w, zd* Y, int* info, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// triangular Sylvester solve  T X + X T^H + shift*X = Y  (T upper triangular, n x n)
+// ---------------------------------------------------------------------------
+int trisylv(const zd* T, zd* X, int n, zd shift, hipStream_t st);
+
+}  // namespace lindx

@@ -1,0 +1,197 @@
+// Single-wave (64-lane) dense complex eigen-kernels on matrices held in LDS (m <= 64).
+// Used for the Krylov projections (m x m Hessenberg / Krylov-Schur matrices), for the shifts
+// of the multishift QR on G, and for the last small active blocks of that QR.
+#pragma once
+#include "common.hpp"
+
+namespace lindx {
+
+static constexpr int LDM = 65;  // LDS row stride for the <= 64 x 64 matrices
+
+__device__ inline double cabs1(zd a) { return fabs(a.x) + fabs(a.y); }
+
+// Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [f; g] = [r; 0].
+__device__ inline void zlartg(zd f, zd g, double& c, zd& s, zd& r) {
+  double af = sqrt(zabs2(f)), ag = sqrt(zabs2(g));
+  if (ag == 0.0) {
+    c = 1.0; s = zmk(0, 0); r = f;
+    return;
+  }
+  if (af == 0.0) {
+    c = 0.0;
+    s = zscale(zconj(g), 1.0 / ag);
+    r = zmk(ag, 0);
+    return;
+  }
+  double nrm = sqrt(af * af + ag * ag);
+  zd ph = zscale(f, 1.0 / af);
+  c = af / nrm;
+  s = zscale(zmul(ph, zconj(g)), 1.0 / nrm);
+  r = zscale(ph, nrm);
+}
+
+// rows (p, p+1) <- G rows, columns [c0, c1]
+__device__ inline void rot_rows(zd* H, int ld, int p, int c0, int c1, double c, zd s) {
+  int j = c0 + (int)(threadIdx.x & 63);
+  for (; j <= c1; j += 64) {
+    zd a = H[p * ld + j], b = H[(p + 1) * ld + j];
+    H[p * ld + j] = zadd(zscale(a, c), zmul(s, b));
+    H[(p + 1) * ld + j] = zsub(zscale(b, c), zmul(zconj(s), a));
+  }
+}
+// columns (p, p+1) <- columns G^H, rows [r0, r1]
+__device__ inline void rot_cols(zd* H, int ld, int p, int r0, int r1, double c, zd s) {
+  int i = r0 + (int)(threadIdx.x & 63);
+  for (; i <= r1; i += 64) {
+    zd a = H[i * ld + p], b = H[i * ld + p + 1];
+    H[i * ld + p] = zadd(zscale(a, c), zmul(zconj(s), b));
+    H[i * ld + p + 1] = zsub(zscale(b, c), zmul(s, a));
+  }
+}
+
+__device__ inline void wsync() { __syncthreads(); }
+
+// Householder reduction of a dense m x m matrix in LDS to upper Hessenberg form, A <- Q^H A Q,
+// accumulating Q (initialised by the caller).  Reflector P = I - 2 u u^H / (u^H u).
+__device__ inline void hessenberg_lds(zd* A, zd* Q, int m, zd* u) {
+  const int t = threadIdx.x & 63;
+  for (int k = 0; k + 2 < m; ++k) {
+    // column below the subdiagonal
+    double nrm2 = 0;
+    for (int i = k + 1; i < m; ++i) nrm2 += zabs2(A[i * LDM + k]);
+    double tail = nrm2 - zabs2(A[(k + 1) * LDM + k]);
+    if (tail <= 0.0) continue;  // already reduced
+    double nrm = sqrt(nrm2);
+    zd x0 = A[(k + 1) * LDM + k];
+    double ax0 = sqrt(zabs2(x0));
+    zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
+    wsync();
+    for (int i = t; i < m; i += 64) u[i] = (i > k) ? A[i * LDM + k] : zmk(0, 0);
+    wsync();
+    if (t == 0) u[k + 1] = zadd(x0, zscale(ph, nrm));
+    wsync();
+    double uu = 0;
+    for (int i = k + 1; i < m; ++i) uu += zabs2(u[i]);
+    double gam = 2.0 / uu;
+    // left: A[k+1:, :] -= gam u (u^H A)
+    for (int j = t; j < m; j += 64) {
+      zd w = zmk(0, 0);
+      for (int i = k + 1; i < m; ++i) w = zadd(w, zcmul(u[i], A[i * LDM + j]));
+      w = zscale(w, gam);
+      for (int i = k + 1; i < m; ++i) A[i * LDM + j] = zsub(A[i * LDM + j], zmul(u[i], w));
+    }
+    wsync();
+    // right: A[:, k+1:] -= gam (A u) u^H ; Q likewise
+    for (int i = t; i < m; i += 64) {
+      zd y = zmk(0, 0), yq = zmk(0, 0);
+      for (int j = k + 1; j < m; ++j) {
+        y = zadd(y, zmul(A[i * LDM + j], u[j]));
+        yq = zadd(yq, zmul(Q[i * LDM + j], u[j]));
+      }
+      y = zscale(y, gam);
+      yq = zscale(yq, gam);
+      for (int j = k + 1; j < m; ++j) {
+        A[i * LDM + j] = zsub(A[i * LDM + j], zmul(y, zconj(u[j])));
+        Q[i * LDM + j] = zsub(Q[i * LDM + j], zmul(yq, zconj(u[j])));
+      }
+    }
+    wsync();
+    for (int i = k + 2 + t; i < m; i += 64) A[i * LDM + k] = zmk(0, 0);
+    wsync();
+  }
+}
+
+// Complex single-shift QR (Wilkinson shifts, exceptional shifts every 10 stalled sweeps) on an
+// m x m upper Hessenberg matrix in LDS.  With full != 0 the whole rows/columns are updated so
+// the result is the Schur form T = Q^H H Q; Q (if non-null) accumulates the rotations.
+// Returns 0 on convergence, 1 otherwise.
+__device__ inline int qr_lds(zd* H, zd* Q, int m, int full) {
+  const double ulp = 2.220446049250313e-16;
+  const double smlnum = 1e-300;
+  int ihi = m - 1;
+  int its = 0, total = 0;
+  while (ihi > 0) {
+    wsync();
+    int l = ihi;
+    for (; l > 0; --l) {
+      zd sub = H[l * LDM + l - 1];
+      double tst = cabs1(H[(l - 1) * LDM + l - 1]) + cabs1(H[l * LDM + l]);
+      if (cabs1(sub) <= fmax(ulp * tst, smlnum)) break;
+    }
+    wsync();
+    if (l > 0 && (threadIdx.x & 63) == 0) H[l * LDM + l - 1] = zmk(0, 0);
+    wsync();
+    if (l == ihi) {
+      ihi -= 1;
+      its = 0;
+      continue;
+    }
+    if (++total > 60 * m + 200) return 1;
+    // shift
+    zd sigma;
+    zd a = H[(ihi - 1) * LDM + ihi - 1], b = H[(ihi - 1) * LDM + ihi];
+    zd c = H[ihi * LDM + ihi - 1], d = H[ihi * LDM + ihi];
+    if (its == 10 || its == 20) {
+      sigma = zadd(d, zmk(1.5 * cabs1(c), 0.0));
+    } else {
+      // eigenvalue of [[a, b], [c, d]] nearest d
+      zd hm = zscale(zsub(a, d), 0.5);
+      zd disc = zadd(zmul(hm, hm), zmul(b, c));
+      // principal sqrt
+      double r = sqrt(sqrt(zabs2(disc)));
+      double th = 0.5 * atan2(disc.y, disc.x);
+      zd sq = zmk(r * cos(th), r * sin(th));
+      zd e1 = zadd(zadd(d, hm), sq), e2 = zsub(zadd(d, hm), sq);
+      sigma = (zabs2(zsub(e1, d)) <= zabs2(zsub(e2, d))) ? e1 : e2;
+    }
+    ++its;
+    const int c0full = full ? 0 : l;
+    const int c1full = full ? m - 1 : ihi;
+    for (int p = l; p < ihi; ++p) {
+      zd f, g;
+      if (p == l) {
+        f = zsub(H[l * LDM + l], sigma);
+        g = H[(l + 1) * LDM + l];
+      } else {
+        f = H[p * LDM + p - 1];
+        g = H[(p + 1) * LDM + p - 1];
+      }
+      double cs;
+      zd sn, rr;
+      zlartg(f, g, cs, sn, rr);
+      wsync();
+      rot_rows(H, LDM, p, (p == l) ? l : p - 1, c1full, cs, sn);
+      wsync();
+      int r1 = p + 2 < ihi ? p + 2 : ihi;
+      rot_cols(H, LDM, p, c0full, r1, cs, sn);
+      if (Q) rot_cols(Q, LDM, p, 0, m - 1, cs, sn);
+      wsync();
+      if (p > l && (threadIdx.x & 63) == 0) H[(p + 1) * LDM + p - 1] = zmk(0, 0);
+    }
+  }
+  wsync();
+  return 0;
+}
+
+// Right eigenvectors of an upper-triangular T (m x m in LDS): column j of Y solves
+// (T - T_jj) y = 0 with y_j = 1 (back substitution, lane j owns column j).
+__device__ inline void trevec_lds(const zd* T, zd* Y, int m) {
+  const double ulp = 2.220446049250313e-16;
+  const int j = threadIdx.x & 63;
+  if (j < m) {
+    zd tjj = T[j * LDM + j];
+    double smin = fmax(ulp * cabs1(tjj), 1e-290);
+    for (int i = m - 1; i > j; --i) Y[i * LDM + j] = zmk(0, 0);
+    Y[j * LDM + j] = zmk(1, 0);
+    for (int i = j - 1; i >= 0; --i) {
+      zd acc = T[i * LDM + j];
+      for (int k = i + 1; k < j; ++k) acc = zadd(acc, zmul(T[i * LDM + k], Y[k * LDM + j]));
+      zd den = zsub(T[i * LDM + i], tjj);
+      if (cabs1(den) < smin) den = zmk(smin, 0);
+      Y[i * LDM + j] = zdiv(zscale(acc, -1.0), den);
+    }
+  }
+  wsync();
+}
+
+}  // namespace lindx

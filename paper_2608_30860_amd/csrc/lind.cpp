@@ -1,0 +1,537 @@
+// C ABI entry points: context creation (G and its FP64 factorisation on the GPU), the operator
+// calls, and the steady-state driver (Algorithm "Steady state as the fixed point of Phi" with
+// FP64 iterative refinement).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include "ctx.hpp"
+
+using namespace lindx;
+
+struct lind_ctx {
+  Ctx c;
+  // solver buffers
+  zd *rhoB = nullptr, *resB = nullptr, *xiB = nullptr, *zetaB = nullptr, *delB = nullptr;
+  // small projected problems
+  zd *hm = nullptr, *ev = nullptr, *Yv = nullptr, *yv = nullptr;
+  int* sinfo = nullptr;
+};
+
+static thread_local std::string g_create_err;
+
+#define TRY(x)                                           \
+  do {                                                   \
+    int rc__ = (x);                                      \
+    if (rc__) return rc__ < 0 ? rc__ : LIND_EDEVICE;     \
+  } while (0)
+
+extern "C" void lind_default_opts(lind_opts* o) {
+  if (!o) return;
+  o->prec = LIND_PREC_FP64;
+  o->route = LIND_ROUTE_AUTO;
+  o->kappa_max = 1e3;
+  o->m = 30;
+  o->p = 0;
+  o->max_restarts = 200;
+  o->refine_max = 8;
+  o->eta = 1.0;
+  o->time_limit_s = 0.0;
+  o->stream = nullptr;
+}
+
+static int prec_of(int p) {
+  if (p == LIND_PREC_FP32) return PREC_F32;
+  if (p == LIND_PREC_BF16X3) return PREC_BF16X3;
+  return PREC_F64;
+}
+
+__global__ void k_nonfinite(const double* x, long long len, int* flag) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
+    if (!isfinite(x[i])) flag[0] = 1;
+}
+__global__ void k_fill_identity_scaled(zd* X, int n, double v) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride)
+    X[t] = (t / n == t % n) ? zmk(v, 0) : zmk(0, 0);
+}
+
+static int count_nonfinite(Ctx& c, const zd* x, long long len, int* flag_dev, bool* bad) {
+  if (fill_zero(flag_dev, sizeof(int), c.st)) return LIND_EDEVICE;
+  long long nb = (2 * len + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_nonfinite, dim3((int)nb), dim3(256), 0, c.st, (const double*)x, 2 * len, flag_dev);
+  TRY(c.fetch(flag_dev, sizeof(int)));
+  *bad = ((const int*)c.hsc)[0] != 0;
+  return 0;
+}
+
+// kappa_2(M) estimate for n x n M: sqrt of the largest eigenvalue of M^H M by power iteration.
+static int power_norm(Ctx& c, const zd* M, zd* x, zd* y, int iters, double* out) {
+  const int n = c.n;
+  double nrm = 0;
+  for (int it = 0; it < iters; ++it) {
+    TRY(gemv(M, n, OP_N, x, y, c.st));
+    TRY(gemv(M, n, OP_C, y, x, c.st));
+    TRY(nrm2(x, n, (double*)c.dsc, c.dscr, c.st));
+    TRY(scale_by_inv(x, n, (const double*)c.dsc, c.st));
+    TRY(c.fetch(c.dsc, sizeof(double)));
+    nrm = ((const double*)c.hsc)[0];
+  }
+  *out = std::sqrt(nrm);
+  return 0;
+}
+
+static int ctx_factor(lind_ctx* X) {
+  Ctx& c = X->c;
+  const int n = c.n, d = c.d;
+  const long long n2 = c.n2;
+  const cplx one(1, 0);
+  double t0 = now_s();
+  // W = sum_j L_j^H L_j (one launch, reduction over j), G = -iH - W/2   (eq. G)
+  if (d > 0) {
+    GemmDesc g;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d;
+    g.A = c.L; g.lda = n; g.sA = n2; g.opA = OP_C;
+    g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_N;
+    g.C = c.w1; g.ldc = n;
+    TRY(gemm(PREC_F64, g, c.st));
+  } else {
+    TRY(fill_zero(c.w1, n2 * (long long)sizeof(zd), c.st));
+  }
+  TRY(make_generator(c.H, c.w1, c.G, n, c.st));
+  double gn[4];
+  TRY(op_norms(c, c.G, gn));
+  c.gnorm = gn[0];
+  // Schur form G = Z T Z^H
+  TRY(copy(c.G, c.T, n2, c.st));
+  int rc = schur_factor(c.T, c.Z, n, c.st, &c.t_hess, &c.t_qr);
+  if (rc == -3) return c.fail(LIND_ENOCONV, "QR iteration on G did not converge");
+  if (rc == -5) return c.fail(LIND_ENOMEM, "out of device memory in the factorisation");
+  if (rc) return c.fail(LIND_EDEVICE, "factorisation failed");
+  TRY(diag_extract(c.T, c.s, n, c.st));
+  TRY(conj_copy(c.s, c.sbar, n, c.st));
+  c.s_host.resize(n);
+  {
+    std::vector<zd> hs(n);
+    if (hipMemcpyAsync(hs.data(), c.s, sizeof(zd) * n, hipMemcpyDeviceToHost, c.st) != hipSuccess) return LIND_EDEVICE;
+    TRY(c.sync());
+    for (int i = 0; i < n; ++i) c.s_host[i] = cplx(hs[i].x, hs[i].y);
+  }
+  // Theorem 1: S invertible iff spec(G) avoids the imaginary axis
+  double minre = 1e300, maxre = -1e300;
+  for (auto& z : c.s_host) {
+    minre = std::min(minre, std::fabs(z.real()));
+    maxre = std::max(maxre, z.real());
+  }
+  if (!(minre > 1e-13 * std::max(c.gnorm, 1e-300)) || maxre >= 0)
+    return c.fail(LIND_ESINGULAR, "spec(G) meets the imaginary axis: S is not invertible");
+  // eigenvectors: Y (upper triangular), Y^{-1}; U = Z Y, V = Z Y^{-H}; unit columns of U
+  TRY(trevec(c.T, c.w2, n, c.st));
+  TRY(triinv_unit(c.w2, c.w3, n, c.st));
+  TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_N, c.w2, n, OP_N, c.U, n, one, 0));
+  TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_N, c.w3, n, OP_C, c.V, n, one, 0));
+  double* cn = (double*)c.dscr;  // n doubles
+  TRY(col_norms(c.U, n, cn, c.st));
+  TRY(scale_cols(c.U, n, cn, 1, c.st));
+  TRY(scale_cols(c.V, n, cn, 0, c.st));
+  // kappa_2(U) = ||U||_2 ||U^{-1}||_2 = ||U||_2 ||V||_2
+  {
+    std::vector<zd> x0(n);
+    std::mt19937_64 rng(12345);
+    std::normal_distribution<double> nd;
+    for (auto& z : x0) z = zmk(nd(rng), nd(rng));
+    if (hipMemcpyAsync(c.w1, x0.data(), sizeof(zd) * n, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
+    TRY(c.sync());
+    double su = 0, sv = 0;
+    TRY(power_norm(c, c.U, c.w1, c.w2, 40, &su));
+    if (hipMemcpyAsync(c.w1, x0.data(), sizeof(zd) * n, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
+    TRY(c.sync());
+    TRY(power_norm(c, c.V, c.w1, c.w2, 40, &sv));
+    c.kappa = su * sv;
+  }
+  int route = c.opts.route;
+  if (route == LIND_ROUTE_AUTO) route = (c.kappa <= c.opts.kappa_max) ? LIND_ROUTE_EIG : LIND_ROUTE_SCHUR;
+  c.route = route;
+  // fused jump operands Lt_j = L_j U (eigen route) or L_j Z (Schur route): one launch, M = d n
+  const zd* B = (route == LIND_ROUTE_EIG) ? c.U : c.Z;
+  if (d > 0) TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, B, n, OP_N, c.Lt, n, one, 0));
+  if (route == LIND_ROUTE_SCHUR) TRY(flip_conj_transpose(c.T, c.Tadj, n, c.st));
+  if (c.prec != PREC_F64) {
+    TRY(to_c64(c.U, c.U32, n2, c.st));
+    TRY(to_c64(c.V, c.V32, n2, c.st));
+    TRY(to_c64(c.Z, c.Z32, n2, c.st));
+    if (d > 0) TRY(to_c64(c.Lt, c.Lt32, (long long)d * n2, c.st));
+  }
+  TRY(c.sync());
+  c.t_factor = now_s() - t0;
+  return 0;
+}
+
+extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n, int d, const lind_opts* opts) {
+  g_create_err.clear();
+  if (!out) { g_create_err = "out is NULL"; return LIND_EINVAL; }
+  *out = nullptr;
+  if (!H || n < 1 || d < 0 || d > 64 || (d > 0 && !Ls)) {
+    g_create_err = "invalid arguments (need H, n >= 1, 0 <= d <= 64, L when d > 0)";
+    return LIND_EINVAL;
+  }
+  lind_opts o;
+  lind_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.m < 4 || o.m > 64 || !(o.eta > 0) || o.prec < 0 || o.prec > 2 || o.route < 0 || o.route > 2 ||
+      o.max_restarts < 1 || o.refine_max < 0) {
+    g_create_err = "invalid options (m in [4, 64], eta > 0, prec/route enums, max_restarts >= 1)";
+    return LIND_EINVAL;
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      std::strstr(prop.gcnArchName, "gfx950") == nullptr) {
+    g_create_err = "no gfx950 (MI355X) device available";
+    return LIND_EDEVICE;
+  }
+  lind_ctx* X = new lind_ctx();
+  Ctx& c = X->c;
+  c.n = n;
+  c.d = d;
+  c.n2 = (long long)n * n;
+  c.opts = o;
+  c.st = (hipStream_t)o.stream;
+  c.prec = prec_of(o.prec);
+  const long long n2 = c.n2;
+  const size_t nd = (size_t)std::max(d, 1) * n2;
+  c.dscr_len = std::max<long long>(2LL * 66 * 1024 + 64, 3LL * 32 * n + 4LL * n + 64);
+  int rc = 0;
+  rc |= c.alloc(&c.H, n2); rc |= c.alloc(&c.L, nd); rc |= c.alloc(&c.G, n2); rc |= c.alloc(&c.T, n2);
+  rc |= c.alloc(&c.Z, n2); rc |= c.alloc(&c.U, n2); rc |= c.alloc(&c.V, n2); rc |= c.alloc(&c.s, n);
+  rc |= c.alloc(&c.sbar, n); rc |= c.alloc(&c.Lt, nd); rc |= c.alloc(&c.Tadj, n2);
+  rc |= c.alloc(&c.w1, n2); rc |= c.alloc(&c.w2, n2); rc |= c.alloc(&c.w3, n2); rc |= c.alloc(&c.w4, n2);
+  rc |= c.alloc(&c.Ys, nd); rc |= c.alloc(&c.dsc, 1024); rc |= c.alloc(&c.dscr, (size_t)c.dscr_len);
+  rc |= c.alloc(&X->hm, 64 * 64); rc |= c.alloc(&X->ev, 64); rc |= c.alloc(&X->Yv, 64 * 64);
+  rc |= c.alloc(&X->yv, 64); rc |= c.alloc(&X->sinfo, 16);
+  if (c.prec != PREC_F64) {
+    rc |= c.alloc(&c.U32, n2); rc |= c.alloc(&c.V32, n2); rc |= c.alloc(&c.Z32, n2);
+    rc |= c.alloc(&c.Lt32, nd); rc |= c.alloc(&c.a32, n2); rc |= c.alloc(&c.b32, n2); rc |= c.alloc(&c.Y32, nd);
+  }
+  if (rc == 0 && hipHostMalloc((void**)&c.hsc, sizeof(zd) * 8192) != hipSuccess) rc = LIND_ENOMEM;
+  if (rc) {
+    delete X;
+    g_create_err = "out of device memory";
+    return LIND_ENOMEM;
+  }
+  bool bad = false;
+  int frc = 0;
+  if (hipMemcpyAsync(c.H, H, sizeof(zd) * n2, hipMemcpyDeviceToDevice, c.st) != hipSuccess ||
+      (d > 0 && hipMemcpyAsync(c.L, Ls, sizeof(zd) * (size_t)d * n2, hipMemcpyDeviceToDevice, c.st) != hipSuccess)) {
+    delete X;
+    g_create_err = "copy of H / L failed (are they device pointers?)";
+    return LIND_EDEVICE;
+  }
+  frc = count_nonfinite(c, c.H, n2, X->sinfo, &bad);
+  if (!frc && !bad && d > 0) frc = count_nonfinite(c, c.L, (long long)d * n2, X->sinfo, &bad);
+  if (frc || bad) {
+    delete X;
+    g_create_err = frc ? "device error while checking inputs" : "non-finite entries in H or L";
+    return frc ? LIND_EDEVICE : LIND_EINVAL;
+  }
+  rc = ctx_factor(X);
+  if (rc) {
+    g_create_err = c.err.empty() ? "factorisation failed" : c.err;
+    delete X;
+    return rc;
+  }
+  *out = X;
+  return LIND_OK;
+}
+
+extern "C" void lind_destroy(lind_ctx* ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->c.st);
+  delete ctx;
+}
+
+extern "C" const char* lind_last_error(const lind_ctx* ctx) {
+  if (!ctx) return g_create_err.c_str();
+  return ctx->c.err.c_str();
+}
+
+extern "C" const void* lind_factor_ptr(const lind_ctx* ctx, int which) {
+  if (!ctx) return nullptr;
+  const Ctx& c = ctx->c;
+  switch (which) {
+    case 0: return c.G;
+    case 1: return c.T;
+    case 2: return c.Z;
+    case 3: return c.U;
+    case 4: return c.V;
+    case 5: return c.s;
+    default: return nullptr;
+  }
+}
+
+extern "C" int lind_apply(lind_ctx* ctx, const void* rho, void* out) {
+  if (!ctx || !rho || !out || rho == out) return LIND_EINVAL;
+  Ctx& c = ctx->c;
+  TRY(op_apply(c, (const zd*)rho, (zd*)out, false));
+  return c.sync();
+}
+
+extern "C" int lind_apply_adjoint(lind_ctx* ctx, const void* X, void* out) {
+  if (!ctx || !X || !out || X == out) return LIND_EINVAL;
+  Ctx& c = ctx->c;
+  TRY(op_apply_adj(c, (const zd*)X, (zd*)out));
+  return c.sync();
+}
+
+static bool divisor_vanishes(const Ctx& c, cplx mu) {
+  // min_ij |s_i + conj(s_j) - mu| relative to ||G||
+  double tol = 1e-14 * std::max(c.gnorm, 1e-300);
+  for (int i = 0; i < c.n; ++i) {
+    double re = c.s_host[i].real() - mu.real();
+    double im = c.s_host[i].imag() - mu.imag();
+    for (int j = 0; j < c.n; ++j) {
+      double a = re + c.s_host[j].real();
+      if (std::fabs(a) > tol) continue;
+      double b = im - c.s_host[j].imag();
+      if (std::hypot(a, b) <= tol) return true;
+    }
+  }
+  return false;
+}
+
+extern "C" int lind_sinv(lind_ctx* ctx, const void* Y, void* Xo, double mu_re, double mu_im) {
+  if (!ctx || !Y || !Xo || !std::isfinite(mu_re) || !std::isfinite(mu_im)) return LIND_EINVAL;
+  Ctx& c = ctx->c;
+  cplx mu(mu_re, mu_im);
+  if (divisor_vanishes(c, mu)) return c.fail(LIND_ESINGULAR, "mu - s_i - conj(s_j) vanishes");
+  TRY(op_sinv(c, (const zd*)Y, (zd*)Xo, mu, PREC_F64, false));
+  return c.sync();
+}
+
+extern "C" int lind_phi(lind_ctx* ctx, const void* xi, void* out) {
+  if (!ctx || !xi || !out || xi == out) return LIND_EINVAL;
+  Ctx& c = ctx->c;
+  TRY(op_phi(c, (const zd*)xi, (zd*)out, c.prec));
+  return c.sync();
+}
+
+// ---------------------------------------------------------------------------------------------
+// steady state
+// ---------------------------------------------------------------------------------------------
+static int ensure_solver_bufs(lind_ctx* X) {
+  Ctx& c = X->c;
+  if (X->rhoB) return 0;
+  int rc = 0;
+  rc |= c.alloc(&X->rhoB, c.n2); rc |= c.alloc(&X->resB, c.n2); rc |= c.alloc(&X->xiB, c.n2);
+  rc |= c.alloc(&X->zetaB, c.n2); rc |= c.alloc(&X->delB, c.n2);
+  return rc ? LIND_ENOMEM : 0;
+}
+
+// Ritz value nearest 1 among w[0..k); ties toward real, then Im >= 0
+static int pick_nearest_one(const std::vector<cplx>& w) {
+  double best = 1e300;
+  for (auto& z : w) best = std::min(best, std::abs(z - 1.0));
+  int idx = -1;
+  for (int i = 0; i < (int)w.size(); ++i) {
+    if (std::abs(w[i] - 1.0) > best * (1 + 1e-9) + 1e-14) continue;
+    if (idx < 0) { idx = i; continue; }
+    double a = std::fabs(w[i].imag()), b = std::fabs(w[idx].imag());
+    if (a < b - 1e-14 || (std::fabs(a - b) <= 1e-14 && w[i].imag() > w[idx].imag())) idx = i;
+  }
+  return idx < 0 ? 0 : idx;
+}
+
+// small eigenproblem of the k x k leading block of the host matrix Hh (row stride ld)
+static int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std::vector<cplx>& w,
+                          std::vector<cplx>& Y) {
+  Ctx& c = X->c;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) c.hsc[i * k + j] = zmk(Hh[(size_t)i * ld + j].real(), Hh[(size_t)i * ld + j].imag());
+  if (hipMemcpyAsync(X->hm, c.hsc, sizeof(zd) * k * k, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
+  TRY(small_eig(X->hm, k, k, X->ev, X->Yv, X->sinfo, c.st));
+  if (hipMemcpyAsync(c.hsc, X->ev, sizeof(zd) * k, hipMemcpyDeviceToHost, c.st) != hipSuccess) return LIND_EDEVICE;
+  if (hipMemcpyAsync(c.hsc + 64, X->Yv, sizeof(zd) * k * k, hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return LIND_EDEVICE;
+  if (hipMemcpyAsync(c.hsc + 8000, X->sinfo, sizeof(int), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return LIND_EDEVICE;
+  TRY(c.sync());
+  w.resize(k);
+  Y.resize((size_t)k * k);
+  for (int i = 0; i < k; ++i) w[i] = cplx(c.hsc[i].x, c.hsc[i].y);
+  for (int i = 0; i < k * k; ++i) Y[i] = cplx(c.hsc[64 + i].x, c.hsc[64 + i].y);
+  int info = *(const int*)(c.hsc + 8000);
+  return info ? LIND_ENOCONV : 0;
+}
+
+static int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst) {
+  Ctx& c = X->c;
+  for (int i = 0; i < k; ++i) c.hsc[i] = zmk(v[i].real(), v[i].imag());
+  if (hipMemcpyAsync(dst, c.hsc, sizeof(zd) * k, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
+  return c.sync();
+}
+
+// rho <- hermitise, normalise (trace 1); res = L(rho); norms (colsum bound, max) to host
+static int finish_state(lind_ctx* X, zd* rho, double* colsum, double* mx, double* fro, cplx* tr_before) {
+  Ctx& c = X->c;
+  TRY(hermitize(rho, c.n, 1, c.dsc + 900, c.dscr, c.st));
+  if (tr_before) {
+    TRY(c.fetch(c.dsc + 900, sizeof(zd)));
+    *tr_before = cplx(c.hsc[0].x, c.hsc[0].y);
+  }
+  TRY(op_apply(c, rho, X->resB, true));
+  double nr[4];
+  TRY(op_norms(c, X->resB, nr));
+  *fro = nr[0];
+  *mx = nr[1];
+  *colsum = nr[2];
+  return 0;
+}
+
+extern "C" int lind_steady_state(lind_ctx* ctx, double tol, const void* rho0, void* rho_out, lind_info* info) {
+  if (!ctx || !rho_out || !(tol > 0) || !std::isfinite(tol)) return LIND_EINVAL;
+  lind_ctx* X = ctx;
+  Ctx& c = X->c;
+  const int n = c.n;
+  const long long n2 = c.n2;
+  const int m = c.opts.m;
+  const int p = c.prec;
+  const double t0 = now_s();
+  const double deadline = c.opts.time_limit_s > 0 ? t0 + c.opts.time_limit_s : 0.0;
+  TRY(ensure_solver_bufs(X));
+  TRY(c.ensure_krylov(1, m + 2));
+  zd* K = c.K1;
+  const cplx one(1, 0), mone(-1, 0);
+  lind_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.kappa_U = c.kappa;
+  inf.t_factor_s = c.t_factor;
+  inf.route_used = c.route;
+  // start state and xi_0 = -S(rho_0)
+  if (rho0) TRY(copy((const zd*)rho0, X->rhoB, n2, c.st));
+  else hipLaunchKernelGGL(k_fill_identity_scaled, dim3(1024), dim3(256), 0, c.st, X->rhoB, n, 1.0 / n);
+  TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, X->rhoB, n, OP_N, X->xiB, n, mone, 0));
+  TRY(op_gemm(c, PREC_F64, n, n, n, X->rhoB, n, OP_N, c.G, n, OP_C, X->xiB, n, mone, 1));
+  double xin = 0;
+  TRY(op_nrm(c, X->xiB, &xin));
+  if (!(xin > 0) || !std::isfinite(xin)) return c.fail(LIND_EINVAL, "start state gives xi_0 = 0 or non-finite");
+  cplx tr0;
+  TRY(op_trace(c, X->rhoB, &tr0));
+  double c_scale = std::sqrt((double)n) * xin / std::max(std::abs(tr0), 1e-300);
+  TRY(copy(X->xiB, K, n2, c.st));
+  TRY(op_nrm(c, K, &xin));
+  TRY(scale_by_inv(K, n2, (const double*)c.dsc, c.st));
+
+  const double eps_floor = (p == PREC_F64) ? 0.0 : (p == PREC_F32 ? 1e-6 : 3e-4);
+  double best = 1e300, best_max = 0;
+  bool converged = false;
+  std::vector<cplx> Hh((size_t)(m + 1) * m), w, Y;
+  double colsum = 0, mx = 0, fro = 0;
+  bool floor_hit = false;
+  for (int rs = 0; rs < c.opts.max_restarts && !converged; ++rs) {
+    std::fill(Hh.begin(), Hh.end(), cplx(0));
+    int k = 0, sel = 0;
+    double est = 1e300;
+    for (int j = 0; j < m; ++j) {
+      zd* vj = K + (long long)j * n2;
+      zd* wv = K + (long long)(j + 1) * n2;
+      TRY(op_phi(c, vj, wv, p));
+      ++inf.n_phi;
+      zd* h1 = c.dsc + 8;
+      zd* h2 = c.dsc + 80;
+      TRY(multi_dot(K, n2, j + 1, wv, n2, h1, (zd*)c.dscr, c.st));
+      TRY(multi_axpy(K, n2, j + 1, h1, wv, n2, 1, -1.0, c.st));
+      TRY(multi_dot(K, n2, j + 1, wv, n2, h2, (zd*)c.dscr, c.st));
+      TRY(multi_axpy(K, n2, j + 1, h2, wv, n2, 1, -1.0, c.st));
+      TRY(nrm2(wv, n2, (double*)(c.dsc + 4), c.dscr, c.st));
+      TRY(c.fetch(c.dsc, sizeof(zd) * 160));
+      double hn = ((const double*)(c.hsc + 4))[0];
+      for (int i = 0; i <= j; ++i)
+        Hh[(size_t)i * m + j] = cplx(c.hsc[8 + i].x + c.hsc[80 + i].x, c.hsc[8 + i].y + c.hsc[80 + i].y);
+      Hh[(size_t)(j + 1) * m + j] = hn;
+      if (hn > 0) TRY(scale_by_inv(wv, n2, (const double*)(c.dsc + 4), c.st));
+      k = j + 1;
+      bool check = (k >= 3 && (k % 2 == 1)) || k == m || hn == 0.0;
+      if (check) {
+        int rc = small_eig_host(X, Hh, m, k, w, Y);
+        if (rc && rc != LIND_ENOCONV) return rc;
+        sel = pick_nearest_one(w);
+        cplx th = w[sel];
+        cplx ylast = Y[(size_t)(k - 1) * k + sel];
+        est = std::sqrt(std::norm(th - 1.0) + hn * hn * std::norm(ylast));
+        if (c_scale * est <= std::max(0.25 * tol, eps_floor) || hn == 0.0) break;
+      }
+      if (deadline > 0 && now_s() > deadline) break;
+    }
+    // Ritz vector xi = V_k y
+    std::vector<cplx> ysel(k);
+    for (int i = 0; i < k; ++i) ysel[i] = Y[(size_t)i * k + sel];
+    TRY(upload_vec(X, ysel.data(), k, X->yv));
+    TRY(multi_axpy(K, n2, k, X->yv, X->xiB, n2, 0, 1.0, c.st));
+    // rho = -S^{-1} xi, hermitised and normalised (the sign cancels in the normalisation)
+    TRY(op_sinv(c, X->xiB, X->rhoB, cplx(0, 0), p, false));
+    cplx trb;
+    TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, &trb));
+    ++inf.n_restarts;
+    double xn = 0;
+    TRY(op_nrm(c, X->xiB, &xn));
+    if (std::abs(trb) > 0) c_scale = std::sqrt((double)n) * xn / std::abs(trb);
+    if (colsum < best) {
+      best = colsum;
+      best_max = mx;
+      TRY(copy(X->rhoB, (zd*)rho_out, n2, c.st));
+    }
+    if (colsum <= tol) { converged = true; break; }
+    if (c_scale * est <= std::max(0.25 * tol, eps_floor) || p != PREC_F64) { floor_hit = true; break; }
+    if (deadline > 0 && now_s() > deadline) break;
+    // restart from xi
+    TRY(copy(X->xiB, K, n2, c.st));
+    TRY(op_nrm(c, K, &xn));
+    TRY(scale_by_inv(K, n2, (const double*)c.dsc, c.st));
+  }
+  // FP64 iterative refinement: (I - Phi_p) zeta = L rho, rho <- rho - S_p^{-1} zeta
+  if (!converged && (floor_hit || true)) {
+    // continue from the best state
+    TRY(copy((const zd*)rho_out, X->rhoB, n2, c.st));
+    TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
+    double prev = colsum;
+    int stagn = 0;
+    const double floor_inner = (p == PREC_F64) ? 1e-13 : (p == PREC_F32 ? 3e-6 : 1e-4);
+    std::function<int(const zd*, zd*)> Aop = [&](const zd* in, zd* out) -> int {
+      int rc = op_phi(c, in, out, p);
+      if (rc) return rc;
+      ++inf.n_phi;
+      return axpby(zmk(1, 0), in, zmk(-1, 0), out, n2, c.st) ? LIND_EDEVICE : 0;
+    };
+    for (int it = 0; it < c.opts.refine_max && !converged; ++it) {
+      if (deadline > 0 && now_s() > deadline) break;
+      double rtol = std::min(0.1, std::max(floor_inner, 0.05 * tol / std::max(colsum, 1e-300)));
+      GmresResult gr;
+      TRY(gmres(c, Aop, nullptr, X->resB, X->zetaB, true, m, 2, rtol, 0.0, gr, deadline));
+      inf.n_inner += gr.iters;
+      TRY(op_sinv(c, X->zetaB, X->delB, cplx(0, 0), p, false));
+      TRY(axpby(zmk(-1, 0), X->delB, zmk(1, 0), X->rhoB, n2, c.st));
+      TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
+      ++inf.n_refine;
+      if (colsum < best) {
+        best = colsum;
+        best_max = mx;
+        TRY(copy(X->rhoB, (zd*)rho_out, n2, c.st));
+      }
+      if (colsum <= tol) { converged = true; break; }
+      if (colsum > 0.5 * prev) { if (++stagn >= 2) break; } else stagn = 0;
+      prev = colsum;
+    }
+  }
+  TRY(c.sync());
+  inf.resid_trace = best;
+  inf.resid_max = best_max;
+  inf.err_est = best;
+  inf.t_solve_s = now_s() - t0;
+  if (info) *info = inf;
+  if (!converged) return c.fail(LIND_ENOCONV, "steady state: tolerance not reached (best iterate returned)");
+  return LIND_OK;
+}

@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads and exports every symbol that
+include/lind.h declares, and the header and the binding agree on the struct layouts."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lind.h")
+LIB = os.path.join(ROOT, "paper_2608_30860_amd", "liblindx.so")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lind_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2608_30860_amd.build import build
+        build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert "lind_create" in names and "lind_steady_state" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_symbol_list_matches_header():
+    from paper_2608_30860_amd import SYMBOLS
+    assert sorted(SYMBOLS) == header_functions()
+
+
+def test_default_opts_and_struct_layout(lib):
+    from paper_2608_30860_amd.lindx import LindInfo, LindOpts
+    o = LindOpts()
+    lib.lind_default_opts(ctypes.byref(o))
+    assert (o.prec, o.route, o.m, o.max_restarts, o.refine_max) == (0, 0, 30, 200, 8)
+    assert o.kappa_max == 1e3 and o.eta == 1.0 and o.stream is None
+    # compare every field offset with the C compiler's layout of include/lind.h
+    import subprocess
+    import tempfile
+    fields = [("lind_opts", LindOpts), ("lind_info", LindInfo)]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "lind.h"', "int main(void){"]
+    for cname, cls in fields:
+        src.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            src.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    src.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        open(c, "w").write("\n".join(src))
+        exe = os.path.join(d, "layout")
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    want = []
+    for _, cls in fields:
+        want.append(ctypes.sizeof(cls))
+        want += [getattr(cls, f).offset for f, _ in cls._fields_]
+    assert got == want
+
+
+def test_create_rejects_bad_arguments_without_touching_a_device(lib):
+    h = ctypes.c_void_p()
+    lib.lind_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_void_p]
+    assert lib.lind_create(ctypes.byref(h), None, None, 4, 1, None) == -1   # NULL H
+    assert lib.lind_create(ctypes.byref(h), ctypes.c_void_p(16), None, 0, 0, None) == -1  # n < 1
+    assert lib.lind_create(None, ctypes.c_void_p(16), None, 4, 0, None) == -1
+    lib.lind_last_error.restype = ctypes.c_char_p
+    assert b"invalid" in lib.lind_last_error(None) or b"NULL" in lib.lind_last_error(None)

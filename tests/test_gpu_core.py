@@ -1,0 +1,184 @@
+"""GPU parity of the C ABI (through the ctypes binding) against the CPU FP64 oracle.
+
+Sizes span several 64/128-wide tiles and ragged tails; the oracle finishes each case in
+well under a second.  Tolerances: FP64 products are compared elementwise relative to the
+largest reference entry (the FP64 results differ from the oracle only by summation order);
+the state-level targets are the ones stated for the steady state (||L rho||_1 <= 1e-10 in FP64,
+<= 1e-8 after refinement in mixed precision, trace distance to the oracle <= 1e-8).
+"""
+import numpy as np
+import pytest
+
+import lind_inputs as li
+from oracle import krylov as ok
+from oracle import lindblad as ol
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(dev())
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def make(H, Ls, **kw):
+    from paper_2608_30860_amd import Lindblad
+    return Lindblad(T(H), T(np.stack(Ls)) if len(Ls) else torch.zeros((0,) + H.shape, dtype=torch.complex128, device=dev()), **kw)
+
+
+def system(kind, n, d, seed=0):
+    if kind == "random":
+        return li.random_dense(n, d, seed)
+    if kind == "kerr":
+        return li.kerr_cavity(n)
+    if kind == "paper":
+        return li.random_dense_paper(n, d, seed=seed)
+    raise KeyError(kind)
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+CASES = [("random", 37, 3), ("random", 130, 2), ("kerr", 32, 1), ("random", 200, 5), ("paper", 65, 3)]
+
+
+@pytest.mark.parametrize("kind,n,d", CASES)
+def test_apply_matches_definition(kind, n, d):
+    print(f"[case] apply {kind} n={n} d={d}", flush=True)
+    H, Ls = system(kind, n, d)
+    m = make(H, Ls)
+    X = li.random_state(n, seed=7, hermitian=False)
+    assert relerr(N(m.apply(T(X))), ol.lindblad_apply(H, Ls, X)) < 1e-12
+    Y = li.random_state(n, seed=8)
+    assert relerr(N(m.apply(T(Y))), ol.lindblad_apply(H, Ls, Y)) < 1e-12
+    assert relerr(N(m.apply_adjoint(T(X))), ol.lindblad_adjoint_apply(H, Ls, X)) < 1e-12
+    m.close()
+
+
+@pytest.mark.parametrize("kind,n,d", CASES)
+def test_factorisation(kind, n, d):
+    print(f"[case] factor {kind} n={n} d={d}", flush=True)
+    H, Ls = system(kind, n, d)
+    m = make(H, Ls)
+    G = ol.no_jump_generator(H, Ls)
+    Gd, Tm, Z, U, V, s = (N(m.factor(w)) for w in ["G", "T", "Z", "U", "V", "s"])
+    assert relerr(Gd, G) < 1e-14
+    assert np.max(np.abs(np.tril(Tm, -1))) == 0.0
+    assert np.max(np.abs(Z.conj().T @ Z - np.eye(n))) < 1e-12
+    assert relerr(Z @ Tm @ Z.conj().T, G) < 1e-12
+    assert np.max(np.abs(V.conj().T @ U - np.eye(n))) < 1e-9
+    assert relerr(G @ U, U * s[None, :]) < 1e-10
+    ref = np.linalg.eigvals(G)
+    for z in ref:
+        assert np.min(np.abs(s - z)) < 1e-10 * max(1.0, np.max(np.abs(ref)))
+    m.close()
+
+
+@pytest.mark.parametrize("kind,n,d", CASES)
+@pytest.mark.parametrize("mu", [0.0, 0.35 + 0.2j])
+def test_sinv_matches_lyapunov(kind, n, d, mu):
+    print(f"[case] sinv {kind} n={n} d={d} mu={mu}", flush=True)
+    H, Ls = system(kind, n, d)
+    m = make(H, Ls)
+    G = ol.no_jump_generator(H, Ls)
+    Y = li.random_state(n, seed=3, hermitian=False)
+    X = N(m.sinv(T(Y), mu))
+    ref = ol.lyap_solve(G, Y, mu) if mu.imag == 0 else None
+    # residual of the definition (S - mu) X = Y
+    res = G @ X + X @ G.conj().T - mu * X - Y
+    assert np.max(np.abs(res)) < 1e-11 * max(1.0, np.max(np.abs(Y)))
+    if ref is not None:
+        assert relerr(X, ref) < 1e-10
+    m.close()
+
+
+@pytest.mark.parametrize("kind,n,d", CASES)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 3e-5), ("bf16x3", 3e-3)])
+def test_phi_matches_oracle(kind, n, d, prec, tol):
+    print(f"[case] phi {kind} n={n} d={d} {prec}", flush=True)
+    H, Ls = system(kind, n, d)
+    m = make(H, Ls, prec=prec)
+    G = ol.no_jump_generator(H, Ls)
+    xi = li.random_state(n, seed=5)
+    out = N(m.phi(T(xi)))
+    ref = ol.phi_apply(G, Ls, xi)
+    err = relerr(out, ref)
+    print(f"  rel err {err:.2e}")
+    assert err < tol
+    # trace preservation holds to the working precision
+    assert abs(np.trace(out) - np.trace(xi)) < 10 * tol
+    m.close()
+
+
+def test_three_level_peripheral():
+    H, Ls = li.three_level_cyclic()
+    m = make(H, Ls, m=8)
+    r = m.steady_state(1e-12)
+    assert np.allclose(N(r.rho), np.eye(3) / 3, atol=1e-12)
+    m.close()
+
+
+def test_steady_state_kerr32():
+    H, Ls, _ = li.workload("kerr32")
+    m = make(H, Ls)
+    r = m.steady_state(1e-10)
+    rho = N(r.rho)
+    ref = ol.steady_state_dense(H, Ls)
+    print("info", r.info)
+    assert ol.trace_distance(rho, ref) < 1e-8
+    assert ol.trace_norm(ol.lindblad_apply(H, Ls, rho)) < 1e-10
+    assert np.allclose(rho, rho.conj().T, atol=1e-15) and abs(np.trace(rho) - 1) < 1e-13
+    assert np.min(np.linalg.eigvalsh(rho)) > -1e-9
+    m.close()
+
+
+def test_steady_state_coherent_closed_form():
+    H, Ls, _ = li.workload("kerr32_linear")
+    m = make(H, Ls)
+    rho = N(m.steady_state(1e-10).rho)
+    beta = -1j * 1.0 / (1j * 0.5 + 0.5)
+    k = np.arange(32)
+    from scipy.special import gammaln
+    amp = np.exp(-0.5 * abs(beta) ** 2 + k * np.log(abs(beta)) - 0.5 * gammaln(k + 1)) * np.exp(1j * k * np.angle(beta))
+    ref = np.outer(amp, amp.conj())
+    assert ol.trace_distance(rho, ref) < 1e-8
+    m.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-8), ("bf16x3", 1e-8)])
+@pytest.mark.parametrize("n,d", [(24, 8), (96, 3)])
+def test_steady_state_random(prec, tol, n, d):
+    print(f"[case] steady random n={n} d={d} {prec}", flush=True)
+    H, Ls = li.random_dense(n, d, 0)
+    m = make(H, Ls, prec=prec)
+    r = m.steady_state(tol)
+    rho = N(r.rho)
+    print("info", r.info)
+    r1 = ol.trace_norm(ol.lindblad_apply(H, Ls, rho))
+    assert r1 < tol
+    if n <= 24:
+        ref = ol.steady_state_dense(H, Ls)
+    else:
+        ref = ok.steady_state_phi(H, Ls, tol=1e-13)
+    assert ol.trace_distance(rho, ref) < 1e-8
+    m.close()
+
+
+def test_singular_generator_is_reported():
+    """Theorem 1, first case: n = 2, H = 0, L = |0><1| has the pure steady state |0><0| and
+    spec(G) contains 0, so S is not invertible."""
+    from paper_2608_30860_amd import LindError
+    H, Ls = li.two_level_decay(1.0)
+    with pytest.raises(LindError) as e:
+        make(H, Ls)
+    assert e.value.code == -2
