@@ -1,0 +1,273 @@
+#!/usr/bin/env python
+"""Benchmark: Phi-apps/s and steady-state time-to-1e-8 at n = 2048, mixed precision vs FP64, one MI355X.
+
+Workload: the random dense Lindbladian, n = 2048, d = 8, seed 0 (lind_inputs.random_dense): H
+Hermitian with complex-Gaussian entries (E|A_ij|^2 = 1/n, symmetrised), L_j complex Gaussian with
+E|z|^2 = 1/(n d).  Inputs are synthetic and resident in HBM before timing starts.
+
+One step = one steady-state solve to the FP64 residual bound sum_j ||col_j(L rho)||_2 <= 1e-8
+(an upper bound on ||L rho||_1) in the mixed mode: Arnoldi on Phi with BF16-split products and
+FP32 accumulation, FP64 Arnoldi orthogonalisation, FP64 residual and refinement.  The one-time
+FP64 factorisation of G is done before the warm-up steps and reported separately.
+value = Phi applications per second over the timed steps (all Phi applications inside the solves).
+
+Also reported: the FP64 path's time-to-1e-8 on the same input, pure Phi-loop rates per
+precision, the dominant kernel's roofline (event-timed inside the timed region), and the CPU
+oracle timed on the host (rank 0, bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Φ-apps/s and steady-state time-to-1e-8 at n=2048: mixed vs FP64, 1 MI355X"
+PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sha_of(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n, d, seed, budget_s=25.0):
+    """The oracle's matrix-free Phi (eigendecomposition no-jump resolvent, as used by its
+    Phi-Arnoldi reference solver) timed on the host: one eigendecomposition of G (reported) and
+    as many Phi applications as fit in the budget (at least one)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import lind_inputs as li
+    from oracle import lindblad as ol
+
+    H, Ls = li.random_dense(n, d, seed)
+    G = ol.no_jump_generator(H, Ls)
+    t0 = time.perf_counter()
+    R = ol.EigResolvent(G)
+    t_eig = time.perf_counter() - t0
+    xi = np.eye(n, dtype=np.complex128) / n
+    cnt = 0
+    t0 = time.perf_counter()
+    while True:
+        xi = -ol.K_apply(Ls, R.sinv(xi))
+        cnt += 1
+        if time.perf_counter() - t0 > budget_s or cnt >= 8:
+            break
+    t = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": cnt / t, "unit": "Phi-apps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{cnt} Phi applications of the oracle (eigendecomposition no-jump resolvent + "
+                      f"jump sum, NumPy FP64) at n={n}, d={d}; eig(G) took {t_eig:.2f} s (not in value)",
+            "eig_s": t_eig, "phi_s": t / cnt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--d", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32 comparison solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--phi-loop", type=int, default=10, help="Phi applications per precision in the pure loop")
+    ap.add_argument("--kernel-only", default=None, help="profiling mode: only run Phi loops in this precision")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the path's "
+              "multi-GPU sharding is described in DESIGN.md and is not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lind_inputs as li
+    from paper_2608_30860_amd import Lindblad
+    from paper_2608_30860_amd.lindx import load_library
+
+    lib = load_library()
+    lib.lindx_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.lindx_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                       ctypes.POINTER(ctypes.c_double)]
+
+    def prof_read(model, kind):
+        c, ms = ctypes.c_longlong(0), ctypes.c_double(0)
+        rc = lib.lindx_profile_read(model.h, kind, ctypes.byref(c), ctypes.byref(ms))
+        assert rc == 0
+        return c.value, ms.value
+
+    n, d = args.n, args.d
+    dev = torch.device("cuda:0")
+    H, Ls = li.random_dense(n, d, args.seed)
+    Ht = torch.from_numpy(H).to(dev)
+    Lt = torch.from_numpy(np.stack(Ls)).to(dev)
+    torch.cuda.synchronize()
+
+    log(f"[bench] factorising G (n={n}, d={d}) for prec={args.prec}")
+    t0 = time.perf_counter()
+    model = Lindblad(Ht, Lt, prec=args.prec)
+    t_create = time.perf_counter() - t0
+    log(f"[bench] create {t_create:.2f} s")
+
+    xi = torch.eye(n, dtype=torch.complex128, device=dev) / n
+
+    if args.kernel_only:
+        m = model if args.kernel_only == args.prec else Lindblad(Ht, Lt, prec=args.kernel_only)
+        for _ in range(args.phi_loop):
+            xi = m.phi(xi)
+        torch.cuda.synchronize()
+        log("[bench] kernel-only loop done")
+        return
+
+    # ---------------------------------------------------------------- timed steps (mixed) ----
+    for w in range(args.warmup):
+        r = model.steady_state(args.tol)
+        log(f"[bench] warmup {w}: {r.info}")
+    lib.lindx_profile(model.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for s in range(args.steps):
+        r = model.steady_state(args.tol)
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t0
+    for s, inf in enumerate(infos):
+        log(f"[bench] step {s}: {inf}")
+    n_phi = sum(i["n_phi"] for i in infos)
+    prof = {k: prof_read(model, k) for k in range(4)}
+    lib.lindx_profile(model.h, 0)
+    rho_mixed = r.rho
+    value = n_phi / t_timed
+    ms_per_step = 1000.0 * t_timed / args.steps
+
+    # dominant kernel: the stacked jump product [Lt_1; ..; Lt_d] Xh (M = d n, N = K = n)
+    cnt, ms = prof[0]
+    avg_s = ms / 1000.0 / max(cnt, 1)
+    flops = 8.0 * d * n ** 3
+    achieved = flops / avg_s / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    roof = {"kernel": f"zgemm_{args.prec} stacked jump product (M=d*n={d * n}, N=K={n})",
+            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "launches": cnt, "avg_ms": 1000 * avg_s,
+            "algorithmic_flops_per_launch": flops}
+    if args.prec == "bf16x3":
+        roof["split_products"] = 3
+        roof["frac_of_split_peak"] = achieved / (peak / 3)
+    # HBM traffic from the committed rocprofv3 counter summary, only if the kernel source matches
+    tpath = os.path.join(ROOT, "profiles", "traffic_jump_gemm.json")
+    src_hash = sha_of(["paper_2608_30860_amd/csrc/zgemm.hip"])
+    if os.path.exists(tpath):
+        try:
+            tj = json.load(open(tpath))
+            if tj.get("source_sha") == src_hash and tj.get("prec") == args.prec and tj.get("n") == n and tj.get("d") == d:
+                roof["traffic"] = tj["bytes_per_launch"]
+        except Exception:
+            pass
+    other = {}
+    for k, name in [(1, "jump_reduce"), (2, "basis_in"), (3, "phi")]:
+        c, t = prof[k]
+        if c:
+            other[name] = {"launches": c, "avg_ms": t / c}
+            if name == "jump_reduce":
+                other[name]["achieved_tflops"] = flops / (t / c / 1000) / 1e12
+
+    # ---------------------------------------------------------------- comparisons ------------
+    compare = {}
+    if not args.no_compare:
+        for p in ["fp64", "fp32"]:
+            if p == args.prec:
+                continue
+            log(f"[bench] comparison: factorising for {p}")
+            t0 = time.perf_counter()
+            mp = Lindblad(Ht, Lt, prec=p)
+            tc = time.perf_counter() - t0
+            mp.steady_state(args.tol)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rp = mp.steady_state(args.tol)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            # pure Phi loop rate
+            x = xi.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.phi_loop):
+                x = mp.phi(x)
+            torch.cuda.synchronize()
+            rate = args.phi_loop / (time.perf_counter() - t0)
+            diff = (rp.rho - rho_mixed)
+            ev = torch.linalg.eigvalsh(0.5 * (diff + diff.conj().T))
+            compare[p] = {"time_to_tol_iteration_s": ts, "create_s": tc, "t_factor_s": rp.info["t_factor_s"],
+                          "n_phi": rp.info["n_phi"], "n_refine": rp.info["n_refine"],
+                          "resid_trace_bound": rp.info["resid_trace"], "phi_loop_rate": rate,
+                          "trace_distance_to_mixed": float(0.5 * ev.abs().sum())}
+            log(f"[bench] {p}: {compare[p]}")
+            mp.close()
+    # pure Phi loop of the benchmarked precision
+    x = xi.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.phi_loop):
+        x = model.phi(x)
+    torch.cuda.synchronize()
+    loop_rate = args.phi_loop / (time.perf_counter() - t0)
+
+    it_mixed = ms_per_step / 1000.0
+    t_to_tol = {"mixed": {"prec": args.prec, "iteration_s": it_mixed, "t_factor_s": infos[-1]["t_factor_s"],
+                          "total_s": it_mixed + infos[-1]["t_factor_s"], "n_phi": infos[-1]["n_phi"],
+                          "n_refine": infos[-1]["n_refine"], "resid_trace_bound": infos[-1]["resid_trace"],
+                          "resid_max": infos[-1]["resid_max"], "phi_loop_rate": loop_rate}}
+    if "fp64" in compare:
+        f = compare["fp64"]
+        t_to_tol["fp64"] = {"iteration_s": f["time_to_tol_iteration_s"], "t_factor_s": f["t_factor_s"],
+                            "total_s": f["time_to_tol_iteration_s"] + f["t_factor_s"], "n_phi": f["n_phi"],
+                            "resid_trace_bound": f["resid_trace_bound"], "phi_loop_rate": f["phi_loop_rate"],
+                            "trace_distance_to_mixed": f["trace_distance_to_mixed"]}
+        t_to_tol["speedup_iteration_fp64_over_mixed"] = f["time_to_tol_iteration_s"] / it_mixed
+        t_to_tol["speedup_total_fp64_over_mixed"] = t_to_tol["fp64"]["total_s"] / t_to_tol["mixed"]["total_s"]
+    if "fp32" in compare:
+        t_to_tol["fp32"] = {k: compare["fp32"][k] for k in ["time_to_tol_iteration_s", "t_factor_s", "n_phi",
+                                                             "resid_trace_bound", "phi_loop_rate",
+                                                             "trace_distance_to_mixed"]}
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(n, d, args.seed)
+        log(f"[bench] cpu {cpu}")
+
+    out = {"metric": METRIC, "value": value, "unit": "Phi-apps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+           "config": {"workload": f"random dense Lindbladian n={n} d={d} seed={args.seed}: steady state to "
+                                  f"||L rho||_1 bound <= {args.tol:g}", "n": n, "d": d, "tol": args.tol,
+                      "step": "one steady-state solve (Arnoldi on Phi + FP64 refinement); factorisation once, "
+                              "reported in time_to_tol", "parallelism": "single GPU"},
+           "time_to_tol": t_to_tol, "roofline": roof, "kernels": other, "cpu_baseline": cpu,
+           "create_s": t_create}
+    model.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

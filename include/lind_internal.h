@@ -13,7 +13,7 @@ extern "C" {
 /* C = alpha * sum_{b < nbatch} op(A_b) op(B_b) (+ C if beta), op: 0 = as stored, 2 = conjugate
    transpose; A_b = A + b*sA, B_b = B + b*sB (element strides).  prec 0: complex128 operands;
    prec 1 (FP32 MFMA) / 2 (BF16 split, FP32 accumulate): complex64 operands, complex64 output
-   unless out64 != 0 (complex128 output). */
+   unless out64 != 0 (complex128 output).  Asynchronous on stream. */
 int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void* A, long long lda, long long sA, int opA,
                const void* B, long long ldb, long long sB, int opB, void* C, long long ldc, double alpha_re,
                double alpha_im, int beta, int out64, void* stream);
@@ -32,6 +32,21 @@ int lindx_triinv(const void* Y, void* Yinv, int n, void* stream);
 
 /* T X + X T^H + shift X = C in place (X holds C on entry), T upper triangular */
 int lindx_trisylv(const void* T, void* X, int n, double shift_re, double shift_im, void* stream);
+
+/* Event timing of the kernels inside a context, recorded on the context's stream.
+   lindx_profile(ctx, 1) resets the counters and starts recording, (ctx, 0) stops.
+   lindx_profile_read returns the number of timed launches and their summed duration for a kind:
+   0 = stacked jump product [Lt_1; ..; Lt_d] X (one launch, M = d n),
+   1 = jump reduction product sum_j Y_j Lt_j^H (one launch),
+   2 = basis change V^H xi V with the fused divide (two launches),
+   3 = one whole application of Phi. */
+typedef struct lind_ctx lind_ctx;
+int lindx_profile(lind_ctx* ctx, int enable);
+int lindx_profile_read(lind_ctx* ctx, int kind, long long* count, double* total_ms);
+
+/* dst = src (nbytes, a multiple of 16) with a plain vector copy kernel; used to calibrate the
+   HBM byte counters of the profiler.  Asynchronous on stream. */
+int lindx_copy(void* dst, const void* src, long long nbytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,9 @@ namespace lindx {
 
 typedef std::complex<double> cplx;
 
+// profiled kernel kinds
+enum { PROF_JUMP_STACK = 0, PROF_JUMP_REDUCE = 1, PROF_BASIS_IN = 2, PROF_PHI = 3, PROF_RESID = 4, PROF_CGS = 5 };
+
 struct Ctx {
   int n = 0, d = 0;
   long long n2 = 0;
@@ -48,6 +51,16 @@ struct Ctx {
   cplx W_mu = 0.0, W_tr = 0.0;
   zd* Wmu = nullptr;
   std::vector<void*> allocs;
+  // event timing of named kernels (enabled by lindx_profile): kinds of PROF_*
+  bool prof = false;
+  struct ProfSlot { hipEvent_t a, b; int kind; };
+  std::vector<hipEvent_t> evpool;
+  std::vector<ProfSlot> pending;
+  double prof_ms[8] = {0};
+  long long prof_cnt[8] = {0};
+  int prof_begin(int kind);
+  void prof_end(int slot);
+  int prof_collect();
 
   ~Ctx();
   int fail(int code, const std::string& msg) { err = msg; return code; }

@@ -254,6 +254,24 @@ extern "C" void lind_destroy(lind_ctx* ctx) {
   delete ctx;
 }
 
+// kernel timing (include/lind_internal.h)
+extern "C" int lindx_profile(lind_ctx* ctx, int enable) {
+  if (!ctx) return LIND_EINVAL;
+  Ctx& c = ctx->c;
+  TRY(c.prof_collect());
+  for (int i = 0; i < 8; ++i) { c.prof_ms[i] = 0; c.prof_cnt[i] = 0; }
+  c.prof = enable != 0;
+  return 0;
+}
+extern "C" int lindx_profile_read(lind_ctx* ctx, int kind, long long* count, double* total_ms) {
+  if (!ctx || kind < 0 || kind >= 8 || !count || !total_ms) return LIND_EINVAL;
+  Ctx& c = ctx->c;
+  TRY(c.prof_collect());
+  *count = c.prof_cnt[kind];
+  *total_ms = c.prof_ms[kind];
+  return 0;
+}
+
 extern "C" const char* lind_last_error(const lind_ctx* ctx) {
   if (!ctx) return g_create_err.c_str();
   return ctx->c.err.c_str();

@@ -13,8 +13,42 @@ double now_s() {
 }
 
 Ctx::~Ctx() {
+  for (auto& sl : pending) { hipEventDestroy(sl.a); hipEventDestroy(sl.b); }
+  for (auto e : evpool) hipEventDestroy(e);
   for (void* p : allocs) hipFree(p);
   if (hsc) hipHostFree(hsc);
+}
+
+int Ctx::prof_begin(int kind) {
+  if (!prof || pending.size() >= 200000) return -1;
+  ProfSlot sl;
+  sl.kind = kind;
+  for (hipEvent_t* e : {&sl.a, &sl.b}) {
+    if (!evpool.empty()) { *e = evpool.back(); evpool.pop_back(); }
+    else if (hipEventCreate(e) != hipSuccess) return -1;
+  }
+  hipEventRecord(sl.a, st);
+  pending.push_back(sl);
+  return (int)pending.size() - 1;
+}
+void Ctx::prof_end(int slot) {
+  if (slot < 0 || slot >= (int)pending.size()) return;
+  hipEventRecord(pending[slot].b, st);
+}
+int Ctx::prof_collect() {
+  if (pending.empty()) return 0;
+  if (hipStreamSynchronize(st) != hipSuccess) return LIND_EDEVICE;
+  for (auto& sl : pending) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, sl.a, sl.b) == hipSuccess && sl.kind >= 0 && sl.kind < 8) {
+      prof_ms[sl.kind] += ms;
+      prof_cnt[sl.kind] += 1;
+    }
+    evpool.push_back(sl.a);
+    evpool.push_back(sl.b);
+  }
+  pending.clear();
+  return 0;
 }
 
 int Ctx::sync() { return hipStreamSynchronize(st) == hipSuccess ? 0 : LIND_EDEVICE; }
@@ -166,7 +200,9 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     TRY(gemm(prec, g, c.st));
     return 0;
   }
+  const int sp = c.prof_begin(PROF_PHI);
   if (prec == PREC_F64) {
+    int s0 = c.prof_begin(PROF_BASIS_IN);
     TRY(op_gemm(c, PREC_F64, n, n, n, c.V, n, OP_C, xi, n, OP_N, c.w1, n, one, 0));
     GemmDesc g;
     g.M = n; g.N = n; g.K = n;
@@ -175,16 +211,23 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     g.C = c.w2; g.ldc = n;
     g.epi = EPI_DIV; g.dr = c.s; g.dc = c.sbar;
     TRY(gemm(PREC_F64, g, c.st));
+    c.prof_end(s0);
+    int s1 = c.prof_begin(PROF_JUMP_STACK);
     TRY(op_gemm(c, PREC_F64, d * n, n, n, c.Lt, n, OP_N, c.w2, n, OP_N, c.Ys, n, one, 0));
+    c.prof_end(s1);
     GemmDesc h;
     h.M = n; h.N = n; h.K = n; h.nbatch = d;
     h.A = c.Ys; h.lda = n; h.sA = n2; h.opA = OP_N;
     h.B = c.Lt; h.ldb = n; h.sB = n2; h.opB = OP_C;
     h.C = out; h.ldc = n; h.ar = -1.0;
+    int s2 = c.prof_begin(PROF_JUMP_REDUCE);
     TRY(gemm(PREC_F64, h, c.st));
+    c.prof_end(s2);
+    c.prof_end(sp);
     (void)mone;
     return 0;
   }
+  int s0 = c.prof_begin(PROF_BASIS_IN);
   TRY(to_c64(xi, c.a32, n2, c.st));
   TRY(op_gemm(c, prec, n, n, n, c.V32, n, OP_C, c.a32, n, OP_N, c.b32, n, one, 0));
   GemmDesc g;
@@ -194,13 +237,19 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
   g.C = c.a32; g.ldc = n;
   g.epi = EPI_DIV; g.dr = c.s; g.dc = c.sbar;
   TRY(gemm(prec, g, c.st));
+  c.prof_end(s0);
+  int s1 = c.prof_begin(PROF_JUMP_STACK);
   TRY(op_gemm(c, prec, d * n, n, n, c.Lt32, n, OP_N, c.a32, n, OP_N, c.Y32, n, one, 0));
+  c.prof_end(s1);
   GemmDesc h;
   h.M = n; h.N = n; h.K = n; h.nbatch = d;
   h.A = c.Y32; h.lda = n; h.sA = n2; h.opA = OP_N;
   h.B = c.Lt32; h.ldb = n; h.sB = n2; h.opB = OP_C;
   h.C = out; h.ldc = n; h.ar = -1.0; h.out64 = 1;
+  int s2 = c.prof_begin(PROF_JUMP_REDUCE);
   TRY(gemm(prec, h, c.st));
+  c.prof_end(s2);
+  c.prof_end(sp);
   return 0;
 }
 

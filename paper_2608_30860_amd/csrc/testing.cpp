@@ -15,9 +15,7 @@ extern "C" int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void*
   g.B = B; g.ldb = ldb; g.sB = sB; g.opB = opB;
   g.C = C; g.ldc = ldc;
   g.ar = alpha_re; g.ai = alpha_im; g.beta = beta; g.out64 = out64;
-  int rc = gemm(prec, g, (hipStream_t)stream);
-  if (rc) return rc;
-  return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -4;
+  return gemm(prec, g, (hipStream_t)stream);
 }
 
 namespace lindx {
@@ -55,4 +53,17 @@ extern "C" int lindx_trisylv(const void* T, void* X, int n, double sr, double si
   int rc = trisylv((const zd*)T, (zd*)X, n, zmk(sr, si), (hipStream_t)stream);
   if (rc) return rc;
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -4;
+}
+
+__global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+extern "C" int lindx_copy(void* dst, const void* src, long long nbytes, void* stream) {
+  if (!dst || !src || nbytes <= 0 || (nbytes % 16)) return -1;
+  long long n = nbytes / 16;
+  long long nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_copy16, dim3((int)nb), dim3(256), 0, (hipStream_t)stream, (const uint4*)src, (uint4*)dst, n);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
 }

@@ -62,6 +62,7 @@ def test_gemm(prec, tol, M, N, K, nb, opA, opB):
             rc = lib().lindx_gemm(prec, M, N, K, nb, P(At), lda, Ash[1] * Ash[2], opA, P(Bt), ldb, Bsh[1] * Bsh[2],
                                   opB, P(Ct), N, alpha.real, alpha.imag, beta, out64, None)
             assert rc == 0
+            torch.cuda.synchronize()
             got = Ct.cpu().numpy().astype(np.complex128)
             want = alpha * ref + (C0 if beta else 0)
             if prec > 0 and not (prec == 0 or out64):
