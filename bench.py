@@ -122,6 +122,31 @@ def main():
     Lt = torch.from_numpy(np.stack(Ls)).to(dev)
     torch.cuda.synchronize()
 
+    if args.kernel_only:
+        # counter runs: the stacked jump product alone at the benchmarked shape (random operands
+        # of the same size and type), then one plain copy of 512 MiB for calibration
+        pk = {"fp64": 0, "fp32": 1, "bf16x3": 2}[args.kernel_only]
+        dt = torch.complex128 if pk == 0 else torch.complex64
+        A = torch.randn(d * n, n, dtype=dt, device=dev)
+        B = torch.randn(n, n, dtype=dt, device=dev)
+        C = torch.empty(d * n, n, dtype=dt, device=dev)
+        lib.lindx_gemm.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_void_p]
+        lib.lindx_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for _ in range(args.phi_loop):
+            rc = lib.lindx_gemm(pk, d * n, n, n, 1, ctypes.c_void_p(A.data_ptr()), n, 0, 0, ctypes.c_void_p(B.data_ptr()),
+                                n, 0, 0, ctypes.c_void_p(C.data_ptr()), n, 1.0, 0.0, 0, 0, stream)
+            assert rc == 0
+        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        assert lib.lindx_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), src.numel(), stream) == 0
+        torch.cuda.synchronize()
+        log("[bench] kernel-only: stacked jump product x", args.phi_loop, "and one 512 MiB copy")
+        return
+
     log(f"[bench] factorising G (n={n}, d={d}) for prec={args.prec}")
     t0 = time.perf_counter()
     model = Lindblad(Ht, Lt, prec=args.prec)
@@ -129,14 +154,6 @@ def main():
     log(f"[bench] create {t_create:.2f} s")
 
     xi = torch.eye(n, dtype=torch.complex128, device=dev) / n
-
-    if args.kernel_only:
-        m = model if args.kernel_only == args.prec else Lindblad(Ht, Lt, prec=args.kernel_only)
-        for _ in range(args.phi_loop):
-            xi = m.phi(xi)
-        torch.cuda.synchronize()
-        log("[bench] kernel-only loop done")
-        return
 
     # ---------------------------------------------------------------- timed steps (mixed) ----
     for w in range(args.warmup):

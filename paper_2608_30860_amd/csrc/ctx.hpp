@@ -109,3 +109,20 @@ int gmres(Ctx& c, const std::function<int(const zd*, zd*)>& A, const std::functi
 double now_s();
 
 }  // namespace lindx
+
+// the C ABI handle: operator context plus solver buffers
+struct lind_ctx {
+  lindx::Ctx c;
+  lindx::zd *rhoB = nullptr, *resB = nullptr, *xiB = nullptr, *zetaB = nullptr, *delB = nullptr;
+  lindx::zd *hm = nullptr, *ev = nullptr, *Yv = nullptr, *yv = nullptr;
+  int* sinfo = nullptr;
+};
+
+namespace lindx {
+// helpers shared by the drivers (lind.cpp)
+int ensure_solver_bufs(lind_ctx* X);
+int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std::vector<cplx>& w,
+                   std::vector<cplx>& Y);
+int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst);
+int steady_state_impl(lind_ctx* X, double tol, const zd* rho0, zd* rho_out, lind_info* info);
+}  // namespace lindx

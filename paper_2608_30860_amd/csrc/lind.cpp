@@ -9,14 +9,6 @@
 
 using namespace lindx;
 
-struct lind_ctx {
-  Ctx c;
-  // solver buffers
-  zd *rhoB = nullptr, *resB = nullptr, *xiB = nullptr, *zetaB = nullptr, *delB = nullptr;
-  // small projected problems
-  zd *hm = nullptr, *ev = nullptr, *Yv = nullptr, *yv = nullptr;
-  int* sinfo = nullptr;
-};
 
 static thread_local std::string g_create_err;
 
@@ -340,7 +332,7 @@ extern "C" int lind_phi(lind_ctx* ctx, const void* xi, void* out) {
 // ---------------------------------------------------------------------------------------------
 // steady state
 // ---------------------------------------------------------------------------------------------
-static int ensure_solver_bufs(lind_ctx* X) {
+int lindx::ensure_solver_bufs(lind_ctx* X) {
   Ctx& c = X->c;
   if (X->rhoB) return 0;
   int rc = 0;
@@ -364,7 +356,7 @@ static int pick_nearest_one(const std::vector<cplx>& w) {
 }
 
 // small eigenproblem of the k x k leading block of the host matrix Hh (row stride ld)
-static int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std::vector<cplx>& w,
+int lindx::small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std::vector<cplx>& w,
                           std::vector<cplx>& Y) {
   Ctx& c = X->c;
   for (int i = 0; i < k; ++i)
@@ -385,7 +377,7 @@ static int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int 
   return info ? LIND_ENOCONV : 0;
 }
 
-static int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst) {
+int lindx::upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst) {
   Ctx& c = X->c;
   for (int i = 0; i < k; ++i) c.hsc[i] = zmk(v[i].real(), v[i].imag());
   if (hipMemcpyAsync(dst, c.hsc, sizeof(zd) * k, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
@@ -411,6 +403,10 @@ static int finish_state(lind_ctx* X, zd* rho, double* colsum, double* mx, double
 
 extern "C" int lind_steady_state(lind_ctx* ctx, double tol, const void* rho0, void* rho_out, lind_info* info) {
   if (!ctx || !rho_out || !(tol > 0) || !std::isfinite(tol)) return LIND_EINVAL;
+  return steady_state_impl(ctx, tol, (const zd*)rho0, (zd*)rho_out, info);
+}
+
+int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_out, lind_info* info) {
   lind_ctx* X = ctx;
   Ctx& c = X->c;
   const int n = c.n;
