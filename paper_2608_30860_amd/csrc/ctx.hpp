@@ -37,6 +37,7 @@ struct Ctx {
   // work
   zd *w1 = nullptr, *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *Ys = nullptr;
   zf *a32 = nullptr, *b32 = nullptr, *Y32 = nullptr;
+  void* gws = nullptr;    // split-K workspace of the batch-reduction products
   zd* dsc = nullptr;      // device scalars
   double* dscr = nullptr; // reduction scratch
   long long dscr_len = 0;

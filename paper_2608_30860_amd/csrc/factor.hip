@@ -206,62 +206,143 @@ __global__ __launch_bounds__(64) void k_shifts(const zd* A, int n, int lo, int n
   (void)rc;
 }
 
-// Chase the bulge chain through window rows/cols [r, r+bw).  One wave.
-__global__ __launch_bounds__(64) void k_chase(zd* A, int n, int ilo, int ihi, int r, int bw,
-                                               const zd* shifts, int ns, int* cnt, zd* Uout) {
+// Chase the bulge chain through window rows/cols [r, r+bw).  All bulges move in lockstep: at
+// step t bulge b rotates at pair P0 + t - 2b (front bulge first in the equivalent sequential
+// order).  Rotations of one step act on disjoint row pairs and disjoint column pairs, and a
+// bulge's parameters only read entries that the other bulges of the same step do not touch, so
+// each step is three phases: parameters (one thread per bulge), row rotations, column rotations
+// (with the accumulated window unitary).
+__global__ __launch_bounds__(256) void k_chase(zd* A, int n, int ilo, int ihi, int r, int bw,
+                                                const zd* shifts, int ns, int* cnt, zd* Uout) {
   __shared__ zd Hs[WIN * LDM];
   __shared__ zd Us[WIN * LDM];
+  __shared__ double cs_s[NSMAX];
+  __shared__ zd sn_s[NSMAX];
+  __shared__ int q_s[NSMAX];
+  __shared__ int c0_s[NSMAX];
+  __shared__ int nxt_s[NSMAX];
   const int t = threadIdx.x;
-  for (int i = 0; i < bw; ++i)
-    for (int j = t; j < bw; j += 64) {
-      Hs[i * LDM + j] = A[(long long)(r + i) * n + r + j];
-      Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
-    }
+  for (int e = t; e < bw * bw; e += 256) {
+    int i = e / bw, j = e - i * bw;
+    Hs[i * LDM + j] = A[(long long)(r + i) * n + r + j];
+    Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
+  }
+  if (t < ns) nxt_s[t] = ilo + cnt[t];
   __syncthreads();
   const bool at_end = (r + bw - 1 >= ihi);
   const int pmax = at_end ? ihi - 1 : r + bw - 3;
   const int pmin = (r == ilo) ? ilo : r + 1;
-  int prev = 0x7fffffff;
-  for (int b = 0; b < ns; ++b) {
-    int p = ilo + cnt[b];
-    int lim = pmax;
-    // bulge b may rotate at pair q only after bulge b-1 has rotated at q+2 (the order of the
-    // interleaved chase), otherwise its column update would meet b-1's bulge entry
-    if (prev <= ihi - 1 && prev - 3 < lim) lim = prev - 3;
-    while (p <= lim && p >= pmin) {
-      const int q = p - r;
-      zd f, g;
-      if (p == ilo) {
-        f = zsub(Hs[q * LDM + q], shifts[b]);
-        g = Hs[(q + 1) * LDM + q];
+  const int plim = pmax < ihi - 1 ? pmax : ihi - 1;
+  const int P0 = nxt_s[0];
+  const int t_end = at_end ? (ihi - 1 - (P0 - 2 * (ns - 1))) : (pmax - P0);
+  for (int step = 0; step <= t_end; ++step) {
+    // phase A: rotation parameters
+    if (t < ns) {
+      const int p = P0 + step - 2 * t;
+      if (p >= ilo && p >= pmin && p <= plim) {
+        const int q = p - r;
+        zd f, g;
+        if (p == ilo) {
+          f = zsub(Hs[q * LDM + q], shifts[t]);
+          g = Hs[(q + 1) * LDM + q];
+        } else {
+          f = Hs[q * LDM + q - 1];
+          g = Hs[(q + 1) * LDM + q - 1];
+        }
+        double cs;
+        zd sn, rr;
+        zlartg(f, g, cs, sn, rr);
+        cs_s[t] = cs;
+        sn_s[t] = sn;
+        q_s[t] = q;
+        c0_s[t] = (p == ilo) ? q : q - 1;
+        nxt_s[t] = p + 1;
       } else {
-        f = Hs[q * LDM + q - 1];
-        g = Hs[(q + 1) * LDM + q - 1];
+        q_s[t] = -1;
       }
-      double cs;
-      zd sn, rr;
-      zlartg(f, g, cs, sn, rr);
-      __syncthreads();
-      rot_rows(Hs, LDM, q, (p == ilo) ? q : q - 1, bw - 1, cs, sn);
-      __syncthreads();
-      int r1 = q + 2 < bw - 1 ? q + 2 : bw - 1;
-      rot_cols(Hs, LDM, q, 0, r1, cs, sn);
-      rot_cols(Us, LDM, q, 0, bw - 1, cs, sn);
-      __syncthreads();
-      if (p > ilo && t == 0) Hs[(q + 1) * LDM + q - 1] = zmk(0, 0);
-      __syncthreads();
-      ++p;
     }
     __syncthreads();
-    if (t == 0) cnt[b] = p - ilo;
-    prev = p;
-  }
-  __syncthreads();
-  for (int i = 0; i < bw; ++i)
-    for (int j = t; j < bw; j += 64) {
-      A[(long long)(r + i) * n + r + j] = Hs[i * LDM + j];
-      Uout[i * WIN + j] = Us[i * LDM + j];
+    // phase B: row rotations (rows q, q+1 of each active bulge), zero the chased entry.  The
+    // items of one thread belong to different bulges (disjoint rows), so all loads are issued
+    // before the stores.
+    {
+      constexpr int NB = (NSMAX * 64 + 255) / 256;
+      zd x[NB], y[NB];
+      int off[NB];
+      bool ok[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int item = t + 256 * u;
+        const int b = item >> 6, col = item & 63;
+        ok[u] = false;
+        off[u] = 0;
+        if (b < ns) {
+          const int q = q_s[b];
+          if (q >= 0 && col >= c0_s[b] && col < bw) {
+            ok[u] = true;
+            off[u] = q * LDM + col;
+            x[u] = Hs[off[u]];
+            y[u] = Hs[off[u] + LDM];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        if (!ok[u]) continue;
+        const int item = t + 256 * u;
+        const int b = item >> 6, col = item & 63;
+        const int q = q_s[b];
+        const double c = cs_s[b];
+        const zd sv = sn_s[b];
+        Hs[off[u]] = zadd(zscale(x[u], c), zmul(sv, y[u]));
+        Hs[off[u] + LDM] = (col == q - 1 && c0_s[b] == q - 1) ? zmk(0, 0) : zsub(zscale(y[u], c), zmul(zconj(sv), x[u]));
+      }
     }
+    __syncthreads();
+    // phase C: column rotations (columns q, q+1) of the window and of the window unitary
+    {
+      constexpr int NC = (NSMAX * 128 + 255) / 256;
+      zd x[NC], y[NC];
+      zd* ptr[NC];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        const int item = t + 256 * u;
+        const int b = item >> 7, rr = item & 127;
+        ptr[u] = nullptr;
+        if (b < ns) {
+          const int q = q_s[b];
+          if (q >= 0) {
+            if (rr < 64) {
+              const int r1 = q + 2 < bw - 1 ? q + 2 : bw - 1;
+              if (rr <= r1) ptr[u] = &Hs[rr * LDM + q];
+            } else if (rr - 64 < bw) {
+              ptr[u] = &Us[(rr - 64) * LDM + q];
+            }
+          }
+        }
+        if (ptr[u]) {
+          x[u] = ptr[u][0];
+          y[u] = ptr[u][1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        if (!ptr[u]) continue;
+        const int b = (t + 256 * u) >> 7;
+        const double c = cs_s[b];
+        const zd sv = sn_s[b];
+        ptr[u][0] = zadd(zscale(x[u], c), zmul(zconj(sv), y[u]));
+        ptr[u][1] = zsub(zscale(y[u], c), zmul(sv, x[u]));
+      }
+    }
+    __syncthreads();
+  }
+  if (t < ns) cnt[t] = nxt_s[t] - ilo;
+  for (int e = t; e < bw * bw; e += 256) {
+    int i = e / bw, j = e - i * bw;
+    A[(long long)(r + i) * n + r + j] = Hs[i * LDM + j];
+    Uout[i * WIN + j] = Us[i * LDM + j];
+  }
 }
 
 // Finish an active block [lo, hi] (size <= 64) in LDS: Schur form of the block, unitary to Uout.
@@ -285,105 +366,139 @@ __global__ __launch_bounds__(64) void k_small_block(zd* A, int n, int lo, int hi
     }
 }
 
-// rows [r, r+bw) x columns [c0, c1] <- U^H (those rows).  One workgroup per 64 columns.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+// One wave accumulates a 16 x 16 complex tile C = sum_k A(i, k) B(k, j) over k < K (K padded
+// to a multiple of 4 with zeros by the caller) with FP64 MFMA; A(i, k) and B(k, j) are read from
+// LDS through the accessors.  Accumulator layout: lane l, register r holds row 4r + l/16,
+// column l % 16.
+template <typename FA, typename FB>
+__device__ inline void tile16_mfma(FA getA, FB getB, int K, v4d_t& cr, v4d_t& ci) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kk = lane >> 4;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    zd a = getA(i, k0 + kk);
+    zd b = getB(k0 + kk, i);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+  }
+}
+
+// rows [r, r+bw) x columns [c0, c1] <- U^H (those rows).  One workgroup per 16 columns; wave w
+// owns output rows 16w .. 16w+15.
 __global__ __launch_bounds__(256) void k_left_apply(zd* A, int n, int r, int bw, int c0, int c1, const zd* U) {
   __shared__ zd Ul[WIN * LDM];
-  __shared__ zd Xs[WIN * LDM];
+  __shared__ zd Xs[WIN * 17];
   const int t = threadIdx.x;
-  const int cb = c0 + blockIdx.x * 64;
-  for (int e = t; e < bw * bw; e += 256) {
-    int i = e / bw, j = e - i * bw;
-    Ul[i * LDM + j] = U[i * WIN + j];
+  const int cb = c0 + blockIdx.x * 16;
+  for (int e = t; e < WIN * WIN; e += 256) {
+    int i = e >> 6, j = e & 63;
+    Ul[i * LDM + j] = (i < bw && j < bw) ? U[i * WIN + j] : zmk(0, 0);
   }
-  for (int e = t; e < bw * 64; e += 256) {
-    int i = e / 64, c = e - i * 64;
+  for (int e = t; e < WIN * 16; e += 256) {
+    int i = e >> 4, c = e & 15;
     int col = cb + c;
-    Xs[i * LDM + c] = (col <= c1) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
+    Xs[i * 17 + c] = (i < bw && col <= c1) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
   }
   __syncthreads();
-  const int c = t & 63;
-  const int col = cb + c;
-  for (int i = t >> 6; i < bw; i += 4) {
-    zd acc = zmk(0, 0);
-    for (int k = 0; k < bw; ++k) acc = zadd(acc, zcmul(Ul[k * LDM + i], Xs[k * LDM + c]));
-    if (col <= c1) A[(long long)(r + i) * n + col] = acc;
+  const int w = t >> 6, lane = t & 63;
+  if (16 * w >= bw) return;
+  v4d_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  const int Kp = (bw + 3) & ~3;
+  tile16_mfma([&](int i, int k) { return zconj(Ul[k * LDM + 16 * w + i]); },
+              [&](int k, int j) { return Xs[k * 17 + j]; }, Kp, cr, ci);
+  for (int q = 0; q < 4; ++q) {
+    const int row = 16 * w + 4 * q + (lane >> 4), col = cb + (lane & 15);
+    if (row < bw && col <= c1) A[(long long)(r + row) * n + col] = zmk(cr[q], ci[q]);
   }
 }
 
 // Deferred right updates: for each window w in order, rows i of X (i < limit_w) get
 // X[i, r_w : r_w+bw_w] <- X[i, r_w : r_w+bw_w] U_w.  limit_w = r_w (mode 1) or nrows (mode 0).
+// One workgroup per 16 rows; wave w owns output columns 16w .. 16w+15.
 __global__ __launch_bounds__(256) void k_right_apply_seq(zd* X, int ldx, int nrows, WinList wl, const zd* Ubuf,
                                                          int mode) {
   __shared__ zd Ul[WIN * LDM];
-  __shared__ zd Xs[32 * LDM];
+  __shared__ zd Xs[16 * LDM];
   const int t = threadIdx.x;
-  const int rb = blockIdx.x * 32;
-  for (int w = 0; w < wl.nwin; ++w) {
-    const int r = wl.r[w], bw = wl.bw[w];
+  const int w = t >> 6, lane = t & 63;
+  const int rb = blockIdx.x * 16;
+  for (int win = 0; win < wl.nwin; ++win) {
+    const int r = wl.r[win], bw = wl.bw[win];
     const int lim = mode ? r : nrows;
     if (rb >= lim) continue;  // uniform over the block
-    const zd* U = Ubuf + (long long)w * WIN * WIN;
+    const zd* U = Ubuf + (long long)win * WIN * WIN;
     __syncthreads();
-    for (int e = t; e < bw * bw; e += 256) {
-      int i = e / bw, j = e - i * bw;
-      Ul[i * LDM + j] = U[i * WIN + j];
+    for (int e = t; e < WIN * WIN; e += 256) {
+      int i = e >> 6, j = e & 63;
+      Ul[i * LDM + j] = (i < bw && j < bw) ? U[i * WIN + j] : zmk(0, 0);
     }
-    for (int e = t; e < 32 * bw; e += 256) {
-      int i = e / bw, j = e - i * bw;
+    for (int e = t; e < 16 * WIN; e += 256) {
+      int i = e >> 6, j = e & 63;
       int row = rb + i;
-      Xs[i * LDM + j] = (row < lim) ? X[(long long)row * ldx + r + j] : zmk(0, 0);
+      Xs[i * LDM + j] = (row < lim && j < bw) ? X[(long long)row * ldx + r + j] : zmk(0, 0);
     }
     __syncthreads();
-    for (int e = t; e < 32 * bw; e += 256) {
-      int i = e / bw, j = e - i * bw;
-      int row = rb + i;
-      zd acc = zmk(0, 0);
-      for (int k = 0; k < bw; ++k) acc = zadd(acc, zmul(Xs[i * LDM + k], Ul[k * LDM + j]));
-      if (row < lim) X[(long long)row * ldx + r + j] = acc;
+    if (16 * w < bw) {
+      v4d_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      const int Kp = (bw + 3) & ~3;
+      tile16_mfma([&](int i, int k) { return Xs[i * LDM + k]; },
+                  [&](int k, int j) { return Ul[k * LDM + 16 * w + j]; }, Kp, cr, ci);
+      for (int q = 0; q < 4; ++q) {
+        const int row = rb + 4 * q + (lane >> 4), col = 16 * w + (lane & 15);
+        if (row < lim && col < bw) X[(long long)row * ldx + r + col] = zmk(cr[q], ci[q]);
+      }
     }
   }
 }
 
 // Deferred left updates of the columns right of the active block: columns (hi, n).
+// One workgroup per 16 columns; wave w owns output rows 16w .. 16w+15 of each window.
 __global__ __launch_bounds__(256) void k_left_apply_seq(zd* A, int n, int c0, WinList wl, const zd* Ubuf) {
   __shared__ zd Ul[WIN * LDM];
-  __shared__ zd Xs[WIN * 33];
+  __shared__ zd Xs[WIN * 17];
   const int t = threadIdx.x;
-  const int cb = c0 + blockIdx.x * 32;
-  for (int w = 0; w < wl.nwin; ++w) {
-    const int r = wl.r[w], bw = wl.bw[w];
-    const zd* U = Ubuf + (long long)w * WIN * WIN;
+  const int w = t >> 6, lane = t & 63;
+  const int cb = c0 + blockIdx.x * 16;
+  for (int win = 0; win < wl.nwin; ++win) {
+    const int r = wl.r[win], bw = wl.bw[win];
+    const zd* U = Ubuf + (long long)win * WIN * WIN;
     __syncthreads();
-    for (int e = t; e < bw * bw; e += 256) {
-      int i = e / bw, j = e - i * bw;
-      Ul[i * LDM + j] = U[i * WIN + j];
+    for (int e = t; e < WIN * WIN; e += 256) {
+      int i = e >> 6, j = e & 63;
+      Ul[i * LDM + j] = (i < bw && j < bw) ? U[i * WIN + j] : zmk(0, 0);
     }
-    for (int e = t; e < bw * 32; e += 256) {
-      int i = e / 32, c = e - i * 32;
+    for (int e = t; e < WIN * 16; e += 256) {
+      int i = e >> 4, c = e & 15;
       int col = cb + c;
-      Xs[i * 33 + c] = (col < n) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
+      Xs[i * 17 + c] = (i < bw && col < n) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
     }
     __syncthreads();
-    for (int e = t; e < bw * 32; e += 256) {
-      int i = e / 32, c = e - i * 32;
-      int col = cb + c;
-      zd acc = zmk(0, 0);
-      for (int k = 0; k < bw; ++k) acc = zadd(acc, zcmul(Ul[k * LDM + i], Xs[k * 33 + c]));
-      if (col < n) A[(long long)(r + i) * n + col] = acc;
+    if (16 * w < bw) {
+      v4d_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      const int Kp = (bw + 3) & ~3;
+      tile16_mfma([&](int i, int k) { return zconj(Ul[k * LDM + 16 * w + i]); },
+                  [&](int k, int j) { return Xs[k * 17 + j]; }, Kp, cr, ci);
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * w + 4 * q + (lane >> 4), col = cb + (lane & 15);
+        if (row < bw && col < n) A[(long long)(r + row) * n + col] = zmk(cr[q], ci[q]);
+      }
     }
   }
 }
 
 static void apply_deferred(zd* A, zd* Z, int n, int hi, const WinList& wl, const zd* Ubuf, hipStream_t st) {
   // Z: all rows
-  hipLaunchKernelGGL(k_right_apply_seq, dim3((n + 31) / 32), dim3(256), 0, st, Z, n, n, wl, Ubuf, 0);
+  hipLaunchKernelGGL(k_right_apply_seq, dim3((n + 15) / 16), dim3(256), 0, st, Z, n, n, wl, Ubuf, 0);
   // A: rows above each window
   int maxr = 0;
   for (int w = 0; w < wl.nwin; ++w) maxr = wl.r[w] > maxr ? wl.r[w] : maxr;
-  if (maxr > 0) hipLaunchKernelGGL(k_right_apply_seq, dim3((maxr + 31) / 32), dim3(256), 0, st, A, n, maxr, wl, Ubuf, 1);
+  if (maxr > 0) hipLaunchKernelGGL(k_right_apply_seq, dim3((maxr + 15) / 16), dim3(256), 0, st, A, n, maxr, wl, Ubuf, 1);
   // A: columns right of the active block
   if (hi + 1 < n)
-    hipLaunchKernelGGL(k_left_apply_seq, dim3((n - hi - 1 + 31) / 32), dim3(256), 0, st, A, n, hi + 1, wl, Ubuf);
+    hipLaunchKernelGGL(k_left_apply_seq, dim3((n - hi - 1 + 15) / 16), dim3(256), 0, st, A, n, hi + 1, wl, Ubuf);
 }
 
 static inline double h_cabs1(zd a) { return fabs(a.x) + fabs(a.y); }
@@ -474,9 +589,9 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
     for (int r = ilo;; r += STEP) {
       int bw = ihi + 1 - r < WIN ? ihi + 1 - r : WIN;
       zd* Uw = Ubuf + (long long)wl.nwin * WIN * WIN;
-      hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, st, A, n, ilo, ihi, r, bw, shifts, ns, cnt, Uw);
+      hipLaunchKernelGGL(k_chase, dim3(1), dim3(256), 0, st, A, n, ilo, ihi, r, bw, shifts, ns, cnt, Uw);
       if (r + bw <= ihi)
-        hipLaunchKernelGGL(k_left_apply, dim3((ihi - (r + bw) + 1 + 63) / 64), dim3(256), 0, st, A, n, r, bw, r + bw,
+        hipLaunchKernelGGL(k_left_apply, dim3((ihi - (r + bw) + 1 + 15) / 16), dim3(256), 0, st, A, n, r, bw, r + bw,
                            ihi, (const zd*)Uw);
       wl.r[wl.nwin] = r;
       wl.bw[wl.nwin] = bw;

@@ -21,7 +21,14 @@ struct GemmDesc {
   const zd* dr = nullptr; const zd* dc = nullptr; double dzr = 0.0, dzi = 0.0;  // EPI_DIV
   const void* E = nullptr; long long lde = 0;                                   // EPI_HERM_ADD
   int out64 = 0;                              // float kernels: write complex128 output
+  // split-K over the batch dimension: nsplit blocks per output tile each reduce nbatch/nsplit
+  // batches into ws (FP32 or FP64 complex partials), a second kernel sums them and applies the
+  // epilogue.  nsplit = 1: single pass.  ws must hold nsplit * M * N complex accumulators.
+  int nsplit = 1;
+  void* ws = nullptr;
 };
+// workspace bytes gemm() needs for a split-K launch of this shape (0 if it would not split)
+long long gemm_ws_bytes(int prec, int M, int N, int nbatch);
 
 // prec = PREC_F64: A, B, C, E are complex128.
 // prec = PREC_F32 / PREC_BF16X3: A, B are complex64; C (and E) complex64 unless out64.

@@ -12,21 +12,24 @@ __device__ inline double cabs1(zd a) { return fabs(a.x) + fabs(a.y); }
 
 // Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [f; g] = [r; 0].
 __device__ inline void zlartg(zd f, zd g, double& c, zd& s, zd& r) {
-  double af = sqrt(zabs2(f)), ag = sqrt(zabs2(g));
-  if (ag == 0.0) {
+  const double f2 = zabs2(f), g2 = zabs2(g);
+  if (g2 == 0.0) {
     c = 1.0; s = zmk(0, 0); r = f;
     return;
   }
-  if (af == 0.0) {
+  if (f2 == 0.0) {
+    const double ag = sqrt(g2);
     c = 0.0;
     s = zscale(zconj(g), 1.0 / ag);
     r = zmk(ag, 0);
     return;
   }
-  double nrm = sqrt(af * af + ag * ag);
-  zd ph = zscale(f, 1.0 / af);
-  c = af / nrm;
-  s = zscale(zmul(ph, zconj(g)), 1.0 / nrm);
+  const double af = sqrt(f2);
+  const double nrm = sqrt(f2 + g2);
+  const double inv_af = 1.0 / af, inv_n = 1.0 / nrm;
+  const zd ph = zscale(f, inv_af);
+  c = af * inv_n;
+  s = zscale(zmul(ph, zconj(g)), inv_n);
   r = zscale(ph, nrm);
 }
 

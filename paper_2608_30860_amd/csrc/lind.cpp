@@ -86,7 +86,7 @@ static int ctx_factor(lind_ctx* X) {
   // W = sum_j L_j^H L_j (one launch, reduction over j), G = -iH - W/2   (eq. G)
   if (d > 0) {
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
     g.A = c.L; g.lda = n; g.sA = n2; g.opA = OP_C;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_N;
     g.C = c.w1; g.ldc = n;
@@ -208,6 +208,10 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
   if (c.prec != PREC_F64) {
     rc |= c.alloc(&c.U32, n2); rc |= c.alloc(&c.V32, n2); rc |= c.alloc(&c.Z32, n2);
     rc |= c.alloc(&c.Lt32, nd); rc |= c.alloc(&c.a32, n2); rc |= c.alloc(&c.b32, n2); rc |= c.alloc(&c.Y32, nd);
+  }
+  {
+    long long wsb = std::max(gemm_ws_bytes(PREC_F64, n, n, std::max(d, 1)), gemm_ws_bytes(c.prec, n, n, std::max(d, 1)));
+    if (wsb > 0) rc |= c.alloc((char**)&c.gws, (size_t)wsb);
   }
   if (rc == 0 && hipHostMalloc((void**)&c.hsc, sizeof(zd) * 8192) != hipSuccess) rc = LIND_ENOMEM;
   if (rc) {

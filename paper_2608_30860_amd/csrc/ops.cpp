@@ -183,7 +183,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     if (prec == PREC_F64) {
       TRY(op_gemm(c, PREC_F64, d * n, n, n, c.Lt, n, OP_N, c.w2, n, OP_N, c.Ys, n, one, 0));
       GemmDesc g;
-      g.M = n; g.N = n; g.K = n; g.nbatch = d;
+      g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
       g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
       g.B = c.Lt; g.ldb = n; g.sB = n2; g.opB = OP_C;
       g.C = out; g.ldc = n; g.ar = -1.0;
@@ -193,7 +193,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     TRY(to_c64(c.w2, c.a32, n2, c.st));
     TRY(op_gemm(c, prec, d * n, n, n, c.Lt32, n, OP_N, c.a32, n, OP_N, c.Y32, n, one, 0));
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
     g.A = c.Y32; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.Lt32; g.ldb = n; g.sB = n2; g.opB = OP_C;
     g.C = out; g.ldc = n; g.ar = -1.0; g.out64 = 1;
@@ -216,7 +216,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     TRY(op_gemm(c, PREC_F64, d * n, n, n, c.Lt, n, OP_N, c.w2, n, OP_N, c.Ys, n, one, 0));
     c.prof_end(s1);
     GemmDesc h;
-    h.M = n; h.N = n; h.K = n; h.nbatch = d;
+    h.M = n; h.N = n; h.K = n; h.nbatch = d; h.ws = c.gws;
     h.A = c.Ys; h.lda = n; h.sA = n2; h.opA = OP_N;
     h.B = c.Lt; h.ldb = n; h.sB = n2; h.opB = OP_C;
     h.C = out; h.ldc = n; h.ar = -1.0;
@@ -242,7 +242,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
   TRY(op_gemm(c, prec, d * n, n, n, c.Lt32, n, OP_N, c.a32, n, OP_N, c.Y32, n, one, 0));
   c.prof_end(s1);
   GemmDesc h;
-  h.M = n; h.N = n; h.K = n; h.nbatch = d;
+  h.M = n; h.N = n; h.K = n; h.nbatch = d; h.ws = c.gws;
   h.A = c.Y32; h.lda = n; h.sA = n2; h.opA = OP_N;
   h.B = c.Lt32; h.ldb = n; h.sB = n2; h.opB = OP_C;
   h.C = out; h.ldc = n; h.ar = -1.0; h.out64 = 1;
@@ -265,7 +265,7 @@ int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in) {
     TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, rho, n, OP_N, c.w4, n, one, 0));
     TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, rho, n, OP_N, c.Ys, n, one, 0));
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
     g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_C;
     g.C = out; g.ldc = n;
@@ -278,7 +278,7 @@ int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in) {
   if (d > 0) {
     TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, rho, n, OP_N, c.Ys, n, one, 0));
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
     g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_C;
     g.C = out; g.ldc = n; g.beta = 1;
@@ -298,7 +298,7 @@ int op_apply_adj(Ctx& c, const zd* X, zd* out) {
     TRY(op_gemm(c, PREC_F64, n, n, n, c.L + j * n2, n, OP_C, X, n, OP_N, c.Ys + j * n2, n, one, 0));
   if (d > 0) {
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
     g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_N;
     g.C = out; g.ldc = n; g.beta = 1;

@@ -15,7 +15,19 @@ extern "C" int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void*
   g.B = B; g.ldb = ldb; g.sB = sB; g.opB = opB;
   g.C = C; g.ldc = ldc;
   g.ar = alpha_re; g.ai = alpha_im; g.beta = beta; g.out64 = out64;
-  return gemm(prec, g, (hipStream_t)stream);
+  // a batch reduction that would split over K gets its workspace here (tests only)
+  long long wsb = gemm_ws_bytes(prec, M, N, nbatch);
+  void* ws = nullptr;
+  if (wsb > 0) {
+    if (hipMalloc(&ws, (size_t)wsb) != hipSuccess) return -5;
+    g.ws = ws;
+  }
+  int rc = gemm(prec, g, (hipStream_t)stream);
+  if (ws) {
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = -4;
+    hipFree(ws);
+  }
+  return rc;
 }
 
 namespace lindx {

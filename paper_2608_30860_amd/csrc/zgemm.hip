@@ -111,18 +111,23 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
   const int wm0 = (wave >> 1) * WM;
   const int wn0 = (wave & 1) * WN;
   const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const int tiles = tm * tn;
+  const int split = blockIdx.x / tiles;
   int bm, bn;
-  tile_of(blockIdx.x, tm, tn, bm, bn);
+  tile_of(blockIdx.x - split * tiles, tm, tn, bm, bn);
   const int m0 = bm * BM, n0 = bn * BN;
 
   const CplxT* Ag = (const CplxT*)g.A;
   const CplxT* Bg = (const CplxT*)g.B;
   const int ktiles = (g.K + BK - 1) / BK;
-  const int total = ktiles * g.nbatch;
+  const int bps = g.nbatch / g.nsplit;
+  const int it_begin = split * bps * ktiles;
+  const int total = bps * ktiles;
 
   CplxT ra[EA], rb[EB];
 
-  auto gload = [&](int it) {
+  auto gload = [&](int itl) {
+    const int it = it_begin + itl;
     const int b = it / ktiles;
     const int k0 = (it - b * ktiles) * BK;
     const CplxT* Ab = Ag + (long long)b * g.sA;
@@ -214,17 +219,27 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
         br[j] = Bs[buf][kr][wn0 + j * 16 + (lane & 15)];
         bi[j] = Bi_s[buf][kr][wn0 + j * 16 + (lane & 15)];
       }
+      T nai[TM];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        T nai = -ai[i];
+      for (int i = 0; i < TM; ++i) nai[i] = -ai[i];
+      // four real products per complex tile product, grouped so consecutive MFMAs use
+      // independent accumulators
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = mfma(ar[i], br[j], cr[i][j]);
-          cr[i][j] = mfma(nai, bi[j], cr[i][j]);
-          ci[i][j] = mfma(ar[i], bi[j], ci[i][j]);
-          ci[i][j] = mfma(ai[i], br[j], ci[i][j]);
-        }
-      }
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) cr[i][j] = mfma(ar[i], br[j], cr[i][j]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) ci[i][j] = mfma(ar[i], bi[j], ci[i][j]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) cr[i][j] = mfma(nai[i], bi[j], cr[i][j]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) ci[i][j] = mfma(ai[i], br[j], ci[i][j]);
     }
     if (it + 1 < total) store_stage(buf ^ 1);
     __syncthreads();
@@ -241,7 +256,17 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
         const int rr = (sizeof(T) == 8) ? (4 * r + (lane >> 4)) : (4 * (lane >> 4) + r);
         int row = m0 + wm0 + i * 16 + rr;
         int col = n0 + wn0 + j * 16 + (lane & 15);
-        epilogue_store<CplxOut>(g, row, col, (double)cr[i][j][r], (double)ci[i][j][r]);
+        if (g.nsplit > 1) {
+          if (row < g.M && col < g.N) {
+            CplxT* W = (CplxT*)g.ws + ((long long)split * g.M + row) * g.N + col;
+            CplxT v;
+            v.x = cr[i][j][r];
+            v.y = ci[i][j][r];
+            *W = v;
+          }
+        } else {
+          epilogue_store<CplxOut>(g, row, col, (double)cr[i][j][r], (double)ci[i][j][r]);
+        }
       }
 }
 
@@ -264,16 +289,103 @@ __device__ inline v4f mfma_bf(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-template <int BM, int BN, typename CplxOut>
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
+
+// Staging of one operand tile (R rows x 32 k, complex64) into four bf16 planes [plane][row][k]:
+// each thread owns chunks of 8 consecutive k of one row.  KC: the k index is contiguous in
+// memory (A as stored, B conjugate-transposed); otherwise the row index is (A^H, B as stored).
+// CONJ: the operand is a conjugate transpose (A^H or B^H).
+// Interior tiles take an unpredicated path (16-byte loads when KC and the rows are 16-byte
+// aligned); edge tiles predicate every element.
+// LDS rows hold 32 bf16 (64 bytes) with the four 16-byte k chunks XOR-swizzled by row bits 2..3,
+// so 16 lanes reading one chunk of 16 consecutive rows (an MFMA operand) hit 16 distinct bank groups
+__device__ inline int swz(int row, int k8) { return ((k8 ^ ((row >> 2) & 3)) << 3); }
+
+template <int R, bool KC, bool CONJ>
+struct Stage {
+  static constexpr int CH = R * 4 / 256;  // chunks per thread (R * 32 / 8 / 256)
+  float2 v[CH][8];
+  __device__ inline void chunk(int c, int tid, int& row, int& k8) const {
+    const int id = tid + c * 256;
+    if (KC) { row = id >> 2; k8 = id & 3; }
+    else { row = id % R; k8 = id / R; }
+  }
+  __device__ inline void load(const float2* __restrict__ base, long long ld, int rows_valid, int k_valid, int r0,
+                              int k0, bool vec_ok, int tid) {
+    const bool full = (r0 + R <= rows_valid) && (k0 + 32 <= k_valid);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      int row, k8;
+      chunk(c, tid, row, k8);
+      const int gr = r0 + row;
+      const int gk0 = k0 + k8 * 8;
+      if (full) {
+        if (KC) {
+          const float2* p = base + (long long)gr * ld + gk0;
+          if (vec_ok) {
+            const float4* q = (const float4*)p;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+              float4 x = q[h];
+              v[c][2 * h] = make_float2(x.x, x.y);
+              v[c][2 * h + 1] = make_float2(x.z, x.w);
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[c][i] = p[i];
+          }
+        } else {
+          const float2* p = base + (long long)gk0 * ld + gr;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) v[c][i] = p[(long long)i * ld];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int gk = gk0 + i;
+          float2 x = make_float2(0.f, 0.f);
+          if (gr < rows_valid && gk < k_valid) x = KC ? base[(long long)gr * ld + gk] : base[(long long)gk * ld + gr];
+          v[c][i] = x;
+        }
+      }
+      if (CONJ) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[c][i].y = -v[c][i].y;
+      }
+    }
+  }
+  __device__ inline void store(__bf16 (*S)[R][32], int tid) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      int row, k8;
+      chunk(c, tid, row, k8);
+      v8bf_t rh, rl, ih, il;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        __bf16 h = (__bf16)v[c][i].x;
+        rh[i] = h;
+        rl[i] = (__bf16)(v[c][i].x - (float)h);
+        h = (__bf16)v[c][i].y;
+        ih[i] = h;
+        il[i] = (__bf16)(v[c][i].y - (float)h);
+      }
+      const int ko = swz(row, k8);
+      *(v8bf_t*)&S[0][row][ko] = rh;
+      *(v8bf_t*)&S[1][row][ko] = rl;
+      *(v8bf_t*)&S[2][row][ko] = ih;
+      *(v8bf_t*)&S[3][row][ko] = il;
+    }
+  }
+};
+
+template <int BM, int BN, bool AKC, bool BKC, typename CplxOut>
 __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc g) {
   constexpr int BK = 32;
-  constexpr int KP = BK + 8;  // padded row length (bf16 elements), keeps 16-byte alignment
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int EA = BM * BK / 256, EB = BK * BN / 256;
-  // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
-  __shared__ __attribute__((aligned(16))) __bf16 As[4][BM][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[4][BN][KP];
+  // planes (0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo) x rows x 32 bf16
+  __shared__ __attribute__((aligned(16))) __bf16 As[4][BM][32];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[4][BN][32];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -281,75 +393,29 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc g) {
   const int wm0 = (wave >> 1) * WM;
   const int wn0 = (wave & 1) * WN;
   const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const int tiles = tm * tn;
+  const int split = blockIdx.x / tiles;
   int bm, bn;
-  tile_of(blockIdx.x, tm, tn, bm, bn);
+  tile_of(blockIdx.x - split * tiles, tm, tn, bm, bn);
   const int m0 = bm * BM, n0 = bn * BN;
 
   const float2* Ag = (const float2*)g.A;
   const float2* Bg = (const float2*)g.B;
   const int ktiles = (g.K + BK - 1) / BK;
-  const int total = ktiles * g.nbatch;
+  const int bps = g.nbatch / g.nsplit;
+  const int it_begin = split * bps * ktiles;
+  const int total = bps * ktiles;
+  const bool vec_a = ((g.lda & 1) == 0) && ((g.sA & 1) == 0) && ((((unsigned long long)g.A) & 15) == 0);
+  const bool vec_b = ((g.ldb & 1) == 0) && ((g.sB & 1) == 0) && ((((unsigned long long)g.B) & 15) == 0);
 
-  float2 ra[EA], rb[EB];
-  auto gload = [&](int it) {
+  Stage<BM, AKC, !AKC> sa;  // A^H: rows of A^H are columns of A (not k-contiguous), conjugated
+  Stage<BN, BKC, BKC> sb;   // B^H: k-contiguous, conjugated
+  auto gload = [&](int itl) {
+    const int it = it_begin + itl;
     const int b = it / ktiles;
     const int k0 = (it - b * ktiles) * BK;
-    const float2* Ab = Ag + (long long)b * g.sA;
-    const float2* Bb = Bg + (long long)b * g.sB;
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int idx = tid + e * 256;
-      int m, k;
-      if (g.opA == OP_N) { m = idx / BK; k = idx - m * BK; }
-      else { k = idx / BM; m = idx - k * BM; }
-      int gm = m0 + m, gk = k0 + k;
-      float2 v = make_float2(0.f, 0.f);
-      if (gm < g.M && gk < g.K) {
-        if (g.opA == OP_N) v = Ab[(long long)gm * g.lda + gk];
-        else { v = Ab[(long long)gk * g.lda + gm]; v.y = -v.y; }
-      }
-      ra[e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int idx = tid + e * 256;
-      int n, k;
-      if (g.opB == OP_N) { k = idx / BN; n = idx - k * BN; }
-      else { n = idx / BK; k = idx - n * BK; }
-      int gn = n0 + n, gk = k0 + k;
-      float2 v = make_float2(0.f, 0.f);
-      if (gn < g.N && gk < g.K) {
-        if (g.opB == OP_N) v = Bb[(long long)gk * g.ldb + gn];
-        else { v = Bb[(long long)gn * g.ldb + gk]; v.y = -v.y; }
-      }
-      rb[e] = v;
-    }
-  };
-  auto store_stage = [&]() {
-#pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      int idx = tid + e * 256;
-      int m, k;
-      if (g.opA == OP_N) { m = idx / BK; k = idx - m * BK; }
-      else { k = idx / BM; m = idx - k * BM; }
-      __bf16 h, l;
-      split_bf16(ra[e].x, h, l);
-      As[0][m][k] = h; As[1][m][k] = l;
-      split_bf16(ra[e].y, h, l);
-      As[2][m][k] = h; As[3][m][k] = l;
-    }
-#pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      int idx = tid + e * 256;
-      int n, k;
-      if (g.opB == OP_N) { k = idx / BN; n = idx - k * BN; }
-      else { n = idx / BK; k = idx - n * BK; }
-      __bf16 h, l;
-      split_bf16(rb[e].x, h, l);
-      Bs[0][n][k] = h; Bs[1][n][k] = l;
-      split_bf16(rb[e].y, h, l);
-      Bs[2][n][k] = h; Bs[3][n][k] = l;
-    }
+    sa.load(Ag + (long long)b * g.sA, g.lda, g.M, g.K, m0, k0, vec_a, tid);
+    sb.load(Bg + (long long)b * g.sB, g.ldb, g.N, g.K, n0, k0, vec_b, tid);
   };
 
   v4f cr[TM][TN], ci[TM][TN];
@@ -361,42 +427,46 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc g) {
       ci[i][j] = v4f{0, 0, 0, 0};
     }
 
-  const int kofs = 8 * (lane >> 4);
+  const int kq = lane >> 4;  // which 8-wide k chunk this lane feeds to the MFMA
+  if (total > 0) gload(0);
   for (int it = 0; it < total; ++it) {
-    gload(it);
     __syncthreads();
-    store_stage();
+    sa.store(As, tid);
+    sb.store(Bs, tid);
     __syncthreads();
-    v8bf br[TN][4];
+    // prefetch the next stage into registers; the loads stay in flight during the MFMAs below
+    if (it + 1 < total) gload(it + 1);
+    v8bf br[TN][4], ar[TM][4], an[TM][2];
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int p = 0; p < 4; ++p)
-        br[j][p] = *(const v8bf*)&Bs[p][wn0 + j * 16 + (lane & 15)][kofs];
+        br[j][p] = *(const v8bf*)&Bs[p][wn0 + j * 16 + (lane & 15)][swz(wn0 + j * 16 + (lane & 15), kq)];
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-      v8bf a[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) a[p] = *(const v8bf*)&As[p][wm0 + i * 16 + (lane & 15)][kofs];
-      v8bf nih = negate8(a[2]), nil = negate8(a[3]);
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        // re: Ar Br - Ai Bi
-        cr[i][j] = mfma_bf(a[0], br[j][0], cr[i][j]);
-        cr[i][j] = mfma_bf(a[0], br[j][1], cr[i][j]);
-        cr[i][j] = mfma_bf(a[1], br[j][0], cr[i][j]);
-        cr[i][j] = mfma_bf(nih, br[j][2], cr[i][j]);
-        cr[i][j] = mfma_bf(nih, br[j][3], cr[i][j]);
-        cr[i][j] = mfma_bf(nil, br[j][2], cr[i][j]);
-        // im: Ar Bi + Ai Br
-        ci[i][j] = mfma_bf(a[0], br[j][2], ci[i][j]);
-        ci[i][j] = mfma_bf(a[0], br[j][3], ci[i][j]);
-        ci[i][j] = mfma_bf(a[1], br[j][2], ci[i][j]);
-        ci[i][j] = mfma_bf(a[2], br[j][0], ci[i][j]);
-        ci[i][j] = mfma_bf(a[2], br[j][1], ci[i][j]);
-        ci[i][j] = mfma_bf(a[3], br[j][0], ci[i][j]);
-      }
+      for (int p = 0; p < 4; ++p) ar[i][p] = *(const v8bf*)&As[p][wm0 + i * 16 + (lane & 15)][swz(wm0 + i * 16 + (lane & 15), kq)];
+      an[i][0] = negate8(ar[i][2]);
+      an[i][1] = negate8(ar[i][3]);
     }
+    // twelve bf16 products per complex tile product; each group below issues TM*TN independent
+    // MFMAs so that no accumulator is used by two consecutive instructions
+#define LX_GROUP(ACC, AOP, BP)                                        \
+  _Pragma("unroll") for (int i = 0; i < TM; ++i)                      \
+    _Pragma("unroll") for (int j = 0; j < TN; ++j) ACC[i][j] = mfma_bf(AOP, br[j][BP], ACC[i][j]);
+    LX_GROUP(cr, ar[i][0], 0)   // re += Ar_hi Br_hi
+    LX_GROUP(ci, ar[i][0], 2)   // im += Ar_hi Bi_hi
+    LX_GROUP(cr, ar[i][0], 1)   // re += Ar_hi Br_lo
+    LX_GROUP(ci, ar[i][0], 3)   // im += Ar_hi Bi_lo
+    LX_GROUP(cr, ar[i][1], 0)   // re += Ar_lo Br_hi
+    LX_GROUP(ci, ar[i][1], 2)   // im += Ar_lo Bi_hi
+    LX_GROUP(cr, an[i][0], 2)   // re -= Ai_hi Bi_hi
+    LX_GROUP(ci, ar[i][2], 0)   // im += Ai_hi Br_hi
+    LX_GROUP(cr, an[i][0], 3)   // re -= Ai_hi Bi_lo
+    LX_GROUP(ci, ar[i][2], 1)   // im += Ai_hi Br_lo
+    LX_GROUP(cr, an[i][1], 2)   // re -= Ai_lo Bi_hi
+    LX_GROUP(ci, ar[i][3], 0)   // im += Ai_lo Br_hi
+#undef LX_GROUP
   }
 
 #pragma unroll
@@ -407,8 +477,30 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc g) {
       for (int r = 0; r < 4; ++r) {
         int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
         int col = n0 + wn0 + j * 16 + (lane & 15);
-        epilogue_store<CplxOut>(g, row, col, (double)cr[i][j][r], (double)ci[i][j][r]);
+        if (g.nsplit > 1) {
+          if (row < g.M && col < g.N)
+            ((float2*)g.ws)[((long long)split * g.M + row) * g.N + col] = make_float2(cr[i][j][r], ci[i][j][r]);
+        } else {
+          epilogue_store<CplxOut>(g, row, col, (double)cr[i][j][r], (double)ci[i][j][r]);
+        }
       }
+}
+
+// sum the split-K partials and apply the epilogue
+template <typename CplxAcc, typename CplxOut>
+__global__ __launch_bounds__(256) void k_splitk_reduce(GemmDesc g) {
+  const long long tot = (long long)g.M * g.N;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    double re = 0, im = 0;
+    for (int s = 0; s < g.nsplit; ++s) {
+      CplxAcc v = ((const CplxAcc*)g.ws)[(long long)s * tot + t];
+      re += v.x;
+      im += v.y;
+    }
+    const int row = (int)(t / g.N), col = (int)(t - (long long)row * g.N);
+    epilogue_store<CplxOut>(g, row, col, re, im);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -418,26 +510,82 @@ template <typename K>
 static int launch(K kern, int BM, int BN, const GemmDesc& g, hipStream_t st) {
   int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
   if (tm <= 0 || tn <= 0) return 0;
-  hipLaunchKernelGGL(kern, dim3(tm * tn), dim3(256), 0, st, g);
+  hipLaunchKernelGGL(kern, dim3(tm * tn * g.nsplit), dim3(256), 0, st, g);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
-int gemm(int prec, const GemmDesc& g, hipStream_t st) {
-  if (g.M <= 0 || g.N <= 0) return 0;
-  if (g.K <= 0 || g.nbatch <= 0) return -1;  // callers never ask for an empty reduction
+template <int BM, int BN, typename Out>
+static int launch_bf16(const GemmDesc& g, hipStream_t st) {
+  const bool akc = g.opA == OP_N, bkc = g.opB != OP_N;
+  if (akc && bkc) return launch(zgemm_bf16x3_kernel<BM, BN, true, true, Out>, BM, BN, g, st);
+  if (akc && !bkc) return launch(zgemm_bf16x3_kernel<BM, BN, true, false, Out>, BM, BN, g, st);
+  if (!akc && bkc) return launch(zgemm_bf16x3_kernel<BM, BN, false, true, Out>, BM, BN, g, st);
+  return launch(zgemm_bf16x3_kernel<BM, BN, false, false, Out>, BM, BN, g, st);
+}
+
+template <typename Acc, typename Out>
+static int launch_reduce(const GemmDesc& g, hipStream_t st) {
+  long long tot = (long long)g.M * g.N;
+  long long nb = (tot + 255) / 256;
+  if (nb > 16384) nb = 16384;
+  hipLaunchKernelGGL((k_splitk_reduce<Acc, Out>), dim3((int)nb), dim3(256), 0, st, g);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// split count for a batch-reduction product: enough blocks to cover the chip twice
+static int choose_split(int prec, int M, int N, int nbatch) {
+  if (nbatch < 2) return 1;
+  const int bm = 128, bn = (prec == PREC_F64) ? 64 : 128;
+  long long tiles = (long long)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+  int s = 1;
+  while (s * 2 <= nbatch && (nbatch % (s * 2)) == 0 && tiles * s < 1024) s *= 2;
+  return s;
+}
+
+long long gemm_ws_bytes(int prec, int M, int N, int nbatch) {
+  int s = choose_split(prec, M, N, nbatch);
+  if (s <= 1) return 0;
+  return (long long)s * M * N * (prec == PREC_F64 ? 16 : 8);
+}
+
+int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
+  if (g0.M <= 0 || g0.N <= 0) return 0;
+  if (g0.K <= 0 || g0.nbatch <= 0) return -1;  // callers never ask for an empty reduction
+  GemmDesc g = g0;
+  g.nsplit = 1;
+  if (g0.ws) {
+    int s = choose_split(prec, g.M, g.N, g.nbatch);
+    if (s > 1) g.nsplit = s;
+  }
+  int rc = 0;
   if (prec == PREC_F64) {
-    if (g.M >= 1024 && g.N >= 1024) return launch(zgemm_kernel<double, 128, 64, 16, double2>, 128, 64, g, st);
-    return launch(zgemm_kernel<double, 64, 64, 16, double2>, 64, 64, g, st);
+    if (g.nsplit > 1 || (g.M >= 1024 && g.N >= 1024)) rc = launch(zgemm_kernel<double, 128, 64, 16, double2>, 128, 64, g, st);
+    else rc = launch(zgemm_kernel<double, 64, 64, 16, double2>, 64, 64, g, st);
+    if (!rc && g.nsplit > 1) rc = launch_reduce<double2, double2>(g, st);
+    return rc;
   }
   if (prec == PREC_F32) {
-    if (g.out64) return launch(zgemm_kernel<float, 64, 64, 16, double2>, 64, 64, g, st);
+    if (g.nsplit > 1) {
+      rc = launch(zgemm_kernel<float, 128, 128, 16, float2>, 128, 128, g, st);
+      if (!rc) rc = g.out64 ? launch_reduce<float2, double2>(g, st) : launch_reduce<float2, float2>(g, st);
+      return rc;
+    }
+    if (g.out64) {
+      if (g.M >= 1024 && g.N >= 1024) return launch(zgemm_kernel<float, 128, 128, 16, double2>, 128, 128, g, st);
+      return launch(zgemm_kernel<float, 64, 64, 16, double2>, 64, 64, g, st);
+    }
     if (g.M >= 1024 && g.N >= 1024) return launch(zgemm_kernel<float, 128, 128, 16, float2>, 128, 128, g, st);
     return launch(zgemm_kernel<float, 64, 64, 16, float2>, 64, 64, g, st);
   }
   if (prec == PREC_BF16X3) {
-    if (g.out64) return launch(zgemm_bf16x3_kernel<64, 64, double2>, 64, 64, g, st);
-    if (g.M >= 1024 && g.N >= 1024) return launch(zgemm_bf16x3_kernel<128, 128, float2>, 128, 128, g, st);
-    return launch(zgemm_bf16x3_kernel<64, 64, float2>, 64, 64, g, st);
+    if (g.nsplit > 1) {
+      rc = launch_bf16<128, 128, float2>(g, st);
+      if (!rc) rc = g.out64 ? launch_reduce<float2, double2>(g, st) : launch_reduce<float2, float2>(g, st);
+      return rc;
+    }
+    const bool big = g.M >= 1024 && g.N >= 1024;
+    if (g.out64) return big ? launch_bf16<128, 128, double2>(g, st) : launch_bf16<64, 64, double2>(g, st);
+    return big ? launch_bf16<128, 128, float2>(g, st) : launch_bf16<64, 64, float2>(g, st);
   }
   return -1;
 }

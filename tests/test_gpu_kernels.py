@@ -40,7 +40,7 @@ def op(X, o):
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 2e-5), (2, 3e-4)])
 @pytest.mark.parametrize("M,N,K,nb", [(37, 45, 29, 1), (130, 70, 200, 1), (64, 64, 64, 3), (200, 200, 200, 2),
-                                      (1, 1, 1, 1), (1024, 1024, 96, 1)])
+                                      (1, 1, 1, 1), (1024, 1024, 96, 1), (300, 260, 72, 8), (1024, 1024, 64, 4)])
 @pytest.mark.parametrize("opA,opB", [(0, 0), (2, 0), (0, 2), (2, 2)])
 def test_gemm(prec, tol, M, N, K, nb, opA, opB):
     print(f"[case] gemm prec={prec} {M}x{N}x{K} nb={nb} ops={opA},{opB}", flush=True)
