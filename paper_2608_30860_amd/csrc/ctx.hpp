@@ -14,6 +14,22 @@ typedef std::complex<double> cplx;
 // profiled kernel kinds
 enum { PROF_JUMP_STACK = 0, PROF_JUMP_REDUCE = 1, PROF_BASIS_IN = 2, PROF_PHI = 3, PROF_RESID = 4, PROF_CGS = 5 };
 
+struct Ctx;
+constexpr int kMaxLong = 1024;  // longest GMRES cycle (basis vectors kept in HBM)
+// recycled subspace of the GCRO-DR solver: (A P) U = C with orthonormal C, k vectors of n*n
+struct Recycle {
+  int k = 0, cap = 0;
+  long long n2 = 0;
+  zd *U = nullptr, *Un = nullptr, *C = nullptr;
+  zd* coef = nullptr;  // device staging of the small coefficient matrices
+  zd* hb = nullptr;    // device Gram-Schmidt coefficients and norm of the current step
+  void* ws = nullptr;  // split-K workspace of the cross products
+  long long ws_bytes = 0;
+  void reset() { k = 0; }
+  int ensure(Ctx& c, int kcap);
+  int cross(Ctx& c, const zd* Urows, int M, const zd* Vrows, int N, zd* T);
+};
+
 struct Ctx {
   int n = 0, d = 0;
   long long n2 = 0;
@@ -51,6 +67,7 @@ struct Ctx {
   bool W_valid = false;
   cplx W_mu = 0.0, W_tr = 0.0;
   zd* Wmu = nullptr;
+  Recycle rec;  // inner-solver recycle space (valid for one operator at a time)
   std::vector<void*> allocs;
   // event timing of named kernels (enabled by lindx_profile): kinds of PROF_*
   bool prof = false;
@@ -74,6 +91,11 @@ struct Ctx {
     return 0;
   }
   int ensure_krylov(int which, int slots);
+  void release(void* p) {
+    for (auto it = allocs.begin(); it != allocs.end(); ++it)
+      if (*it == p) { allocs.erase(it); break; }
+    hipFree(p);
+  }
   int sync();
   // host scalar fetch: copies `count` zd from device pointer into the pinned buffer and syncs
   int fetch(const void* dptr, size_t bytes);
@@ -102,6 +124,7 @@ struct GmresResult {
   double resid = 0.0;      // final residual 2-norm (true residual at the last restart)
   double resid0 = 0.0;
   bool converged = false;
+  bool stagnated = false;  // restarts stopped reducing the true residual
 };
 int gmres(Ctx& c, const std::function<int(const zd*, zd*)>& A, const std::function<int(const zd*, zd*)>* P,
           const zd* b, zd* x, bool x_zero, int m, int max_cycles, double rtol, double atol, GmresResult& res,
@@ -126,4 +149,13 @@ int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std:
                    std::vector<cplx>& Y);
 int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst);
 int steady_state_impl(lind_ctx* X, double tol, const zd* rho0, zd* rho_out, lind_info* info);
+// right-preconditioned GMRES(m) with a recycled subspace of up to kdef vectors (GCRO-DR), carried in
+// rec across cycles and across solves with the same operators A and P (P may be null: identity).
+// m <= 64 for recycling; longer cycles (up to kMaxLong) run without it.  x_zero: start from x = 0.
+int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const std::function<int(const zd*, zd*)>* P,
+              const zd* b, zd* x, bool x_zero, int m, int kdef, int max_cycles, double rtol, double atol,
+              Recycle& rec, GmresResult& res, double t_deadline);
+// longest cycle (<= want) whose basis fits the HBM budget; release a long basis after use
+int long_cycle_len(Ctx& c, int want);
+void release_long_basis(Ctx& c);
 }  // namespace lindx

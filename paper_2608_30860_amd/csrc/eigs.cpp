@@ -2,7 +2,7 @@
 // gradients (Remark "Differentiating the steady state").
 //
 // eigs: Krylov-Schur Arnoldi on OP = (mu - L~_eta)^{-1}, L~_eta = L + eta |I><I|.  Each OP
-// application is a right-preconditioned GMRES solve of (mu - L~_eta) x = b with the deflated
+// application is a right-preconditioned recycled GMRES solve of (mu - L~_eta) x = b with the deflated
 // no-jump preconditioner P_mu (Algorithm "Precond": Z = R^S_mu(X), W = R^S_mu(I) precomputed,
 // P = Z + eta Tr(Z) / (1 - eta Tr W) W, eq. ShermanMorr).  Thick restart keeps an orthonormal basis
 // of the invariant subspace of the p dominant Ritz values; eigenvalues of L are mu - 1/nu.
@@ -12,6 +12,7 @@
 // eigenvalues), then g_H = i[rho, w], g_Lj = L_j {rho, w} - 2 w L_j rho.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <random>
 #include "ctx.hpp"
@@ -25,6 +26,9 @@ using namespace lindx;
   } while (0)
 
 namespace {
+
+constexpr int kInnerM = 40;  // inner GMRES cycle length
+constexpr int kInnerK = 20;  // recycled harmonic Ritz vectors
 
 // A(x) = mu x - L(x) - eta Tr(x) I   (or the adjoint: conj(mu) x - L*(x) - eta Tr(x) I)
 int apply_shifted_deflated(Ctx& c, const zd* x, zd* out, cplx mu, double eta, bool adjoint) {
@@ -135,10 +139,14 @@ extern "C" int lind_eigs(lind_ctx* ctx, int k, double mu_re, double mu_im, doubl
     ++inf.n_phi;
     return apply_precond(c, P, in, out, c.prec);
   };
-  const int m_in = std::min(40, std::max(10, m));
+  // inner solves: recycled GMRES(40) keeping 20 harmonic Ritz vectors, threaded through every
+  // application of OP (same operator and preconditioner throughout); the inner tolerance follows
+  // the outer one (the eigen-residual of a Ritz pair is about |lambda| times the inner residual)
+  const double rtol_in = std::min(1e-8, std::max(1e-12, 0.1 * tol));
+  c.rec.reset();
   auto OP = [&](const zd* b, zd* x) -> int {
     GmresResult gr;
-    TRY(gmres(c, Aop, &Pop, b, x, true, m_in, 20, 1e-12, 0.0, gr, deadline));
+    TRY(gmres_rec(X, Aop, &Pop, b, x, true, kInnerM, kInnerK, 60, rtol_in, 0.0, c.rec, gr, deadline));
     inf.n_inner += gr.iters;
     return 0;
   };
@@ -378,9 +386,26 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
     ++inf.n_phi;
     return apply_precond(c, P, in, out, c.prec);
   };
+  // recycled GMRES(40) first; if it has not converged after a dozen cycles the preconditioned adjoint
+  // is strongly non-normal (long chains of levels), and one long cycle (up to 1024 steps, basis in
+  // HBM) continues from the current iterate
+  const double rtol_adj = std::min(1e-9, std::max(1e-13, 0.01 * tol));
   GmresResult gr;
-  TRY(gmres(c, Aop, &Pop, rhs, wadj, true, std::min(40, std::max(10, c.opts.m)), 30, 1e-13, 0.0, gr, 0.0));
+  c.rec.reset();
+  TRY(gmres_rec(X, Aop, &Pop, rhs, wadj, true, kInnerM, kInnerK, 12, rtol_adj, 0.0, c.rec, gr, 0.0));
+  c.rec.reset();
   inf.n_inner += gr.iters;
+  if (!gr.converged && !gr.stagnated) {
+    const double r0 = gr.resid0;
+    GmresResult g2;
+    const int ml = long_cycle_len(c, kMaxLong);
+    int rc2 = gmres_rec(X, Aop, &Pop, rhs, wadj, false, ml, 0, 4, rtol_adj, 0.0, c.rec, g2, 0.0);
+    release_long_basis(c);
+    TRY(rc2);
+    inf.n_inner += g2.iters;
+    g2.resid0 = r0;  // relative to ||rhs||, as for the first attempt
+    gr = g2;
+  }
   // hermitise w (exact adjoint state is Hermitian for Hermitian O)
   TRY(hermitize(wadj, n, 0, nullptr, c.dscr, c.st));
   // g_H = i (rho w - w rho); M = rho w + w rho
@@ -411,6 +436,14 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
   inf.t_solve_s = now_s() - t0;
   if (info) *info = inf;
   if (status) return c.fail(status, "steady state for the gradient did not reach the tolerance");
-  if (!gr.converged) return c.fail(LIND_ENOCONV, "adjoint GMRES did not converge");
+  // a solve stopped at its rounding floor (restarts no longer reduce the true residual) is accepted
+  // when that floor is far below what the gradient needs
+  const bool adj_ok = gr.converged || (gr.stagnated && gr.resid <= 1e-10 * std::max(gr.resid0, 1e-300));
+  if (!adj_ok) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "adjoint GMRES did not converge (relative residual %.2e after %d iterations)",
+                  gr.resid / std::max(gr.resid0, 1e-300), gr.iters);
+    return c.fail(LIND_ENOCONV, msg);
+  }
   return LIND_OK;
 }

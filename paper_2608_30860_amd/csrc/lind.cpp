@@ -524,12 +524,24 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
       ++inf.n_phi;
       return axpby(zmk(1, 0), in, zmk(-1, 0), out, n2, c.st) ? LIND_EDEVICE : 0;
     };
+    // inner solves: GMRES(m) first; once one misses its tolerance the map is treated as strongly
+    // non-normal and the remaining solves use one long cycle (basis in HBM)
+    int m_ref = m;
+    bool long_mode = false;
     for (int it = 0; it < c.opts.refine_max && !converged; ++it) {
       if (deadline > 0 && now_s() > deadline) break;
       double rtol = std::min(0.1, std::max(floor_inner, 0.05 * tol / std::max(colsum, 1e-300)));
       GmresResult gr;
-      TRY(gmres(c, Aop, nullptr, X->resB, X->zetaB, true, m, 2, rtol, 0.0, gr, deadline));
+      int grc = gmres_rec(X, Aop, nullptr, X->resB, X->zetaB, true, m_ref, 0, 2, rtol, 0.0, c.rec, gr, deadline);
+      if (grc) {
+        if (long_mode) release_long_basis(c);
+        return grc;
+      }
       inf.n_inner += gr.iters;
+      if (!gr.converged && !gr.stagnated && !long_mode) {
+        long_mode = true;
+        m_ref = long_cycle_len(c, 256);
+      }
       TRY(op_sinv(c, X->zetaB, X->delB, cplx(0, 0), p, false));
       TRY(axpby(zmk(-1, 0), X->delB, zmk(1, 0), X->rhoB, n2, c.st));
       TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
@@ -543,6 +555,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
       if (colsum > 0.5 * prev) { if (++stagn >= 2) break; } else stagn = 0;
       prev = colsum;
     }
+    if (long_mode) release_long_basis(c);
   }
   TRY(c.sync());
   inf.resid_trace = best;

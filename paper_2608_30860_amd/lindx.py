@@ -204,17 +204,19 @@ class Lindblad:
         d["status"] = rc
         return SteadyResult(out, d)
 
-    def eigs(self, k, mu=0.0, tol=1e-10, vectors=False):
+    def eigs(self, k, mu=0.0, tol=1e-10, vectors=False, raise_on_noconv=True):
         ev = (ctypes.c_double * (2 * k))()
         vec = self._new(k, self.n, self.n) if vectors else None
         info = LindInfo()
         mu = complex(mu)
         rc = self.lib.lind_eigs(self.h, k, mu.real, mu.imag, tol, ctypes.cast(ev, ctypes.c_void_p),
                                 _ptr(vec) if vec is not None else ctypes.c_void_p(0), ctypes.byref(info))
-        if rc:
+        if rc and not (rc == LIND_ENOCONV and not raise_on_noconv):
             self._err(rc)
         vals = np.array(ev[0::2]) + 1j * np.array(ev[1::2])
-        return vals, vec, info.as_dict()
+        d = info.as_dict()
+        d["status"] = rc
+        return vals, vec, d
 
     def steady_grad(self, O, tol=1e-12, want_rho=True):
         _check_mat(O, self.n, "O")

@@ -1,0 +1,265 @@
+"""The named workloads at their full sizes on the GPU, checked against the CPU oracle.
+
+Where the dense oracle cannot run (n >= 64) the checks are properties that hold at any size and
+that the oracle evaluates independently of the GPU: the FP64 residual L(rho) and its trace norm
+computed on the host from H and L_j, Hermiticity, positivity and unit trace, the Lyapunov
+residual G X + X G^+ - Y of the GPU solve, Phi = -K(S^{-1} xi) against the host jump sum, and
+eigenpair residuals L v - lambda v.  Truncation-converged dense references are used for the
+bosonic two-photon workload.
+"""
+import numpy as np
+import pytest
+
+import lind_inputs as li
+from oracle import gradient as og
+from oracle import lindblad as ol
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda:0")
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def make(H, Ls, **kw):
+    from paper_2608_30860_amd import Lindblad
+    return Lindblad(T(H), T(np.stack(Ls)), **kw)
+
+
+def certify_state(H, Ls, rho, tol):
+    """host-side certificate: Hermitian, unit trace, PSD (to 10 tol), ||L rho||_1 <= tol."""
+    assert np.max(np.abs(rho - rho.conj().T)) < 1e-14
+    assert abs(np.trace(rho) - 1) < 1e-12
+    ev = np.linalg.eigvalsh(rho)
+    assert ev.min() > -10 * tol
+    r = ol.lindblad_apply(H, Ls, rho)
+    r = 0.5 * (r + r.conj().T)
+    r1 = float(np.sum(np.abs(np.linalg.eigvalsh(r))))
+    assert r1 <= tol, r1
+    return r1
+
+
+# ------------------------------------------------------------------- Kerr n = 32 -------------
+def test_kerr32_fp64_matches_dense():
+    H, Ls, _ = li.workload("kerr32")
+    m = make(H, Ls, prec="fp64")
+    rho = N(m.steady_state(1e-10).rho)
+    certify_state(H, Ls, rho, 1e-10)
+    assert ol.trace_distance(rho, ol.steady_state_dense(H, Ls)) < 1e-8
+    m.close()
+
+
+# ------------------------------------------------------------------- two-photon n = 256 ------
+def parity_even(rho):
+    n = rho.shape[0]
+    P = np.diag((-1.0) ** np.arange(n))
+    return 0.5 * (rho + P @ rho @ P)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-8)])
+def test_two_photon256_steady_state(prec, tol):
+    print(f"[case] two-photon n=256 {prec}", flush=True)
+    H, Ls, rho0 = li.workload("two_photon256")
+    m = make(H, Ls, prec=prec)
+    r = m.steady_state(tol, rho0=T(rho0))
+    rho = N(r.rho)
+    print("info", r.info)
+    certify_state(H, Ls, rho, tol)
+    # truncation-converged dense reference at n = 48, zero-padded; compared in the parity-even
+    # sector (the bit-flip mode makes the odd sector ill-conditioned)
+    Hs, Lss = li.two_photon_cavity(48)
+    ref = np.zeros_like(rho)
+    ref[:48, :48] = ol.steady_state_dense(Hs, Lss)
+    assert ol.trace_distance(parity_even(rho), parity_even(ref)) < 1e-8
+    m.close()
+
+
+def test_two_photon256_low_spectrum():
+    """Six eigenvalues nearest the shift mu = -0.004, which sits between the bit-flip mode
+    (|lambda| ~ 1e-9) and the parity-decay pair (lambda ~ -8e-3): at mu = 0 the bit-flip mode would
+    amplify OP by ~1e9 and push the inner solves to their rounding floor (same eigenvalues, slower)."""
+    print("[case] two-photon n=256 eigs", flush=True)
+    H, Ls, _ = li.workload("two_photon256")
+    m = make(H, Ls, m=40, time_limit_s=120)
+    vals, vecs, info = m.eigs(6, mu=-0.004, tol=1e-8, vectors=True)
+    print("eigs", vals, info)
+    Hs, Lss = li.two_photon_cavity(48)
+    ref = ol.low_spectrum_dense(Hs, Lss, 6)
+    scale = np.max(np.abs(ref))
+    got = list(vals)
+    for z in ref[:5]:  # the 6th (and 5th) are a near-tie of modulus ~6.545; either is correct
+        j = int(np.argmin([abs(g - z) for g in got]))
+        # the n = 48 reference is converged in the truncation to ~1e-10 for |lambda| < 5 but only
+        # to ~2e-8 relative for the |lambda| ~ 6.5 modes (n = 40 vs n = 48 differ by that much)
+        tol_z = 1e-8 * scale + 1e-10 if abs(z) < 5 else 1e-7 * abs(z)
+        assert abs(got[j] - z) <= tol_z, (z, got)
+        got.pop(j)
+    for lam, V in zip(vals, N(vecs)):
+        res = ol.max_norm(ol.lindblad_apply(H, Ls, V) - lam * V)
+        assert res <= 1e-8 * max(1, abs(lam))
+    m.close()
+
+
+# ------------------------------------------------------------------- coupled Kerr n = 1600 ---
+def test_coupled_kerr1600_schur_route_mixed():
+    print("[case] coupled Kerr n=1600 fp32 + refinement", flush=True)
+    H, Ls, _ = li.workload("coupled_kerr1600")
+    m = make(H, Ls, prec="fp32")
+    r = m.steady_state(1e-8)
+    print("info", r.info)
+    assert r.info["route_used"] == 2  # kappa_2(U) ~ 2.6e4 -> triangular Sylvester route
+    rho = N(r.rho)
+    certify_state(H, Ls, rho, 1e-8)
+    # the same state by the eigenbasis route in FP64
+    m2 = make(H, Ls, prec="fp64", route="eig")
+    rho2 = N(m2.steady_state(1e-9).rho)
+    assert ol.trace_distance(rho, rho2) < 1e-7
+    m.close()
+    m2.close()
+
+
+# ------------------------------------------------------------------- random n = 2048 ---------
+@pytest.fixture(scope="module")
+def random2048():
+    H, Ls, _ = li.workload("random2048")
+    return H, Ls
+
+
+def test_random2048_sinv_and_phi(random2048):
+    """Full size, bench launch configuration: S^{-1} residual and Phi against the host jump sum."""
+    print("[case] random n=2048 sinv/phi", flush=True)
+    H, Ls = random2048
+    G = ol.no_jump_generator(H, Ls)
+    xi = li.random_state(2048, seed=5)
+    # max-entry-relative tolerances: rounding of the working precision (2^-24 for FP32, about 2^-16
+    # per product for BF16x3) through K = 2048 and d n = 16384 long sums and the basis change with
+    # kappa_2(U) ~ 470; FP64 is compared with the oracle's own Lyapunov residual
+    for prec, tol in [("fp64", 1e-11), ("fp32", 3e-4), ("bf16x3", 3e-3)]:
+        m = make(H, Ls, prec=prec)
+        X = N(m.sinv(T(xi)))
+        res = G @ X + X @ G.conj().T - xi
+        assert np.max(np.abs(res)) < 1e-12 * np.max(np.abs(xi)) * 10
+        phi = N(m.phi(T(xi)))
+        ref = -ol.K_apply(Ls, X)
+        err = np.max(np.abs(phi - ref)) / np.max(np.abs(ref))
+        print(prec, "phi rel err", err)
+        assert err < tol
+        m.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-8), ("fp64", 1e-10)])
+def test_random2048_steady_state(random2048, prec, tol):
+    print(f"[case] random n=2048 steady {prec}", flush=True)
+    H, Ls = random2048
+    m = make(H, Ls, prec=prec)
+    r = m.steady_state(tol)
+    print("info", r.info)
+    certify_state(H, Ls, N(r.rho), tol)
+    m.close()
+
+
+def test_random2048_low_spectrum(random2048):
+    """Three smallest-magnitude nonzero eigenvalues at the eigen-residual of the paper's low-lying
+    benchmark (max-norm 1e-4 on unit-norm eigenvectors): the low edge of a random Lindbladian's
+    spectrum is a dense cluster (|lambda| ~ 0.78, spacing ~1e-2), which shift-invert at mu = 0
+    barely separates.  Parity unpinned (no dense reference at n = 2048): certified by the host
+    residual of every returned eigenvector, Re(lambda) < 0, and ordering."""
+    print("[case] random n=2048 eigs", flush=True)
+    H, Ls = random2048
+    m = make(H, Ls, prec="bf16x3", m=30, time_limit_s=140)
+    vals, vecs, info = m.eigs(3, tol=1e-4, vectors=True)
+    print("eigs", vals, info)
+    V = N(vecs)
+    for t in range(3):
+        res = ol.max_norm(ol.lindblad_apply(H, Ls, V[t]) - vals[t] * V[t])
+        assert res <= 1e-4 * max(1, abs(vals[t]))
+    assert np.all(vals.real < 0)
+    assert np.all(np.diff(np.abs(vals)) >= -1e-6)
+    m.close()
+
+
+# ------------------------------------------------------------------- gradients ---------------
+def test_kerr512_dephasing_steady_state():
+    """Kerr cavity with dephasing at n = 512: FP64 steady state certified on the host."""
+    print("[case] Kerr + dephasing n=512 steady", flush=True)
+    H, Ls, _ = li.workload("kerr512_dephasing")
+    m = make(H, Ls)
+    r = m.steady_state(1e-10)
+    print("info", r.info)
+    certify_state(H, Ls, N(r.rho), 1e-10)
+    m.close()
+
+
+def test_kerr_dephasing_scalar_gradients_fd():
+    """d<a^dag a>/d(Delta, eps, K, kappa) through SteadyExpect against central differences of the
+    GPU FP64 steady state (step 1e-6), Kerr + dephasing at n = 48 (truncation-converged for these
+    parameters).  At n = 512 the preconditioned adjoint is so non-normal (each Fock level adds a
+    step to a chain that GMRES must traverse; the plateau lasts ~1.6 n steps at n = 64 and 128)
+    that the adjoint solve does not converge within 4096 steps."""
+    from paper_2608_30860_amd import Lindblad, steady_expectation
+    n = 48
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(li.destroy(n)).to(dev)
+    ad = a.conj().T.contiguous()
+    Nop = (ad @ a).contiguous()
+
+    def build(th):
+        D, e, K, k = th[0], th[1], th[2], th[3]
+        H = (D * Nop + e * (a + ad) + K * (ad @ ad @ a @ a)).contiguous()
+        Ls = torch.stack([torch.sqrt(k) * a, np.sqrt(0.05) * Nop]).contiguous()
+        return H, Ls
+
+    th = torch.tensor([0.5, 1.0, 0.1, 1.0], dtype=torch.float64, device=dev, requires_grad=True)
+    H, Ls = build(th)
+    J = steady_expectation(H, Ls, Nop, 1e-13)
+    J.backward()
+    g = th.grad.cpu().numpy()
+
+    def Jof(v):
+        Hh, Lh = build(torch.tensor(v, dtype=torch.float64, device=dev))
+        m = Lindblad(Hh.detach(), Lh.detach())
+        rho = m.steady_state(1e-13, raise_on_noconv=False).rho
+        m.close()
+        return float(torch.trace(Nop @ rho).real)
+
+    h = 1e-6
+    base = th.detach().cpu().numpy()
+    fd = []
+    for i in range(4):
+        e = np.zeros(4)
+        e[i] = h
+        fd.append((Jof(base + e) - Jof(base - e)) / (2 * h))
+    fd = np.array(fd)
+    print("grad", g, "fd", fd)
+    assert np.linalg.norm(g - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_random1024_full_matrix_gradients_fd():
+    """dJ/dH, dJ/dL_j at n = 1024, d = 4 (random O) against central differences along random
+    directions (Hermitian for H, complex for L_j, jointly normalised), FD of the GPU FP64 solve."""
+    from paper_2608_30860_amd import Lindblad
+    H, Ls, _ = li.workload("random1024_d4")
+    O = li.random_observable(1024, seed=1)
+    m = make(H, Ls)
+    J, gH, gL, rho, info = m.steady_grad(T(O), 1e-13)
+    m.close()
+    gH, gL = N(gH), [N(x) for x in gL]
+    dirs = og.random_directions(1024, 4, 8, seed=2)
+    h = 1e-6
+
+    def Jof(Hh, Lh):
+        mm = make(Hh, Lh)
+        rho = N(mm.steady_state(1e-13, raise_on_noconv=False).rho)
+        mm.close()
+        return og.expectation(O, rho)
+
+    fd = og.grad_fd(Jof, H, Ls, dirs, h)
+    ad = np.array([og.directional(gH, gL, dH, dL) for dH, dL in dirs])
+    err = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    print("fd rel err", err, ad[:3], fd[:3])
+    assert err < 1e-6
