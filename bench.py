@@ -136,9 +136,22 @@ def main():
                                    ctypes.c_int, ctypes.c_void_p]
         lib.lindx_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]
         stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if pk == 2:
+            # BF16x3: the pre-split product of the map Phi (operands split into bf16 planes, product
+            # written as planes), exactly the launch configuration of the stacked jump product
+            lib.lindx_p4_test.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 7 + [ctypes.c_void_p] * 4
+            A64 = A.to(torch.complex128)
+            B64 = B.to(torch.complex128)
+            C64 = torch.empty(d * n, n, dtype=torch.complex128, device=dev)
+            torch.cuda.synchronize()
         for _ in range(args.phi_loop):
-            rc = lib.lindx_gemm(pk, d * n, n, n, 1, ctypes.c_void_p(A.data_ptr()), n, 0, 0, ctypes.c_void_p(B.data_ptr()),
-                                n, 0, 0, ctypes.c_void_p(C.data_ptr()), n, 1.0, 0.0, 0, 0, stream)
+            if pk == 2:
+                rc = lib.lindx_p4_test(ctypes.c_void_p(A64.data_ptr()), ctypes.c_void_p(B64.data_ptr()), d * n, n, n, 1,
+                                       0, 0, 0, None, None, ctypes.c_void_p(C64.data_ptr()), stream)
+            else:
+                rc = lib.lindx_gemm(pk, d * n, n, n, 1, ctypes.c_void_p(A.data_ptr()), n, 0, 0,
+                                    ctypes.c_void_p(B.data_ptr()), n, 0, 0, ctypes.c_void_p(C.data_ptr()), n, 1.0, 0.0,
+                                    0, 0, stream)
             assert rc == 0
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -183,7 +196,8 @@ def main():
     flops = 8.0 * d * n ** 3
     achieved = flops / avg_s / 1e12
     peak = PEAK_TFLOPS[args.prec]
-    roof = {"kernel": f"zgemm_{args.prec} stacked jump product (M=d*n={d * n}, N=K={n})",
+    kname = "k_p4_gemm (pre-split BF16 planes)" if args.prec == "bf16x3" else f"zgemm_{args.prec}"
+    roof = {"kernel": f"{kname} stacked jump product (M=d*n={d * n}, N=K={n})",
             "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": None, "launches": cnt, "avg_ms": 1000 * avg_s,
             "algorithmic_flops_per_launch": flops}
@@ -192,7 +206,8 @@ def main():
         roof["frac_of_split_peak"] = achieved / (peak / 3)
     # HBM traffic from the committed rocprofv3 counter summary, only if the kernel source matches
     tpath = os.path.join(ROOT, "profiles", "traffic_jump_gemm.json")
-    src_hash = sha_of(["paper_2608_30860_amd/csrc/zgemm.hip"])
+    src_hash = sha_of(["paper_2608_30860_amd/csrc/zgemm_p4.hip" if args.prec == "bf16x3"
+                       else "paper_2608_30860_amd/csrc/zgemm.hip"])
     if os.path.exists(tpath):
         try:
             tj = json.load(open(tpath))

@@ -44,6 +44,16 @@ typedef struct lind_ctx lind_ctx;
 int lindx_profile(lind_ctx* ctx, int enable);
 int lindx_profile_read(lind_ctx* ctx, int kind, long long* count, double* total_ms);
 
+/* C = sum_b op(A_b) op(B_b) through the pre-split BF16 product used by the BF16x3 map Phi
+   (complex128 device arrays in and out, synchronous).  op(A) = A_b (M x K) or A_b^H (A_b stored
+   K x M); op(B) = B_b (K x N) or B_b^H (B_b stored N x K); the nbatch blocks are consecutive.
+   out_mode 0: planes, 1: transposed planes (both read back as complex128), 2: FP32 split-K
+   partials reduced to complex128 (the only mode that takes nbatch > 1).  dr, dc (device
+   complex128 of length M and N, or null; modes 0 and 1): entry (m, n) is divided by dr_m + dc_n.
+   Returns 0, or -1 for invalid arguments, -4 for a device error, -5 out of memory. */
+int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch, int opA, int opB, int out_mode,
+                  const void* dr, const void* dc, void* C, void* stream);
+
 /* dst = src (nbytes, a multiple of 16) with a plain vector copy kernel; used to calibrate the
    HBM byte counters of the profiler.  Asynchronous on stream. */
 int lindx_copy(void* dst, const void* src, long long nbytes, void* stream);

@@ -54,6 +54,12 @@ struct Ctx {
   zd *w1 = nullptr, *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *Ys = nullptr;
   zf *a32 = nullptr, *b32 = nullptr, *Y32 = nullptr;
   void* gws = nullptr;    // split-K workspace of the batch-reduction products
+  // BF16x3 eigen route: pre-split bf16 planes of V^H, V^T, the stacked L_j U (constants) and of
+  // the intermediates of Phi; FP32 split-K partials of the jump reduction
+  bool p4_ready = false;
+  P4 p4_VH, p4_VT, p4_Lt, p4_xiT, p4_C1, p4_XhT, p4_Y;
+  float2* p4_ws = nullptr;
+  int p4_nsplit = 1;
   zd* dsc = nullptr;      // device scalars
   double* dscr = nullptr; // reduction scratch
   long long dscr_len = 0;

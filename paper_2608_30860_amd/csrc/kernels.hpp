@@ -35,6 +35,38 @@ long long gemm_ws_bytes(int prec, int M, int N, int nbatch);
 int gemm(int prec, const GemmDesc& g, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// complex products on pre-split BF16 operands (BF16x3 mode): four bf16 planes
+// [re_hi, re_lo, im_hi, im_lo], each rows x ld with k contiguous, zero-padded to whole tiles
+// ---------------------------------------------------------------------------
+struct P4 {
+  __bf16* p = nullptr;
+  long long rows = 0, ld = 0, pstride = 0;  // allocated rows, k stride, plane stride (elements)
+};
+enum { P4OUT_PLANES = 0, P4OUT_PLANES_T = 1, P4OUT_WS = 2 };
+struct P4Desc {
+  int M = 0, N = 0, K = 0, nbatch = 1, nsplit = 1;
+  // op(A) row m, k at A[pl * pA + b * sA + m * lda + k]; op(B) column n, k at B[pl * pB + b * sB + n * ldb + k]
+  const __bf16* A = nullptr; long long lda = 0, pA = 0, sA = 0;
+  const __bf16* B = nullptr; long long ldb = 0, pB = 0, sB = 0;
+  int conjA = 0, conjB = 0;
+  int out = P4OUT_PLANES;
+  __bf16* C = nullptr; long long ldc = 0, pC = 0;   // planes out: [m][n] or (transposed) [n][m]
+  const zd* dr = nullptr; const zd* dc = nullptr;   // optional divide by dr_m + dc_n (planes out)
+  float2* ws = nullptr;                             // P4OUT_WS: nsplit * M * N partials
+  void* out64 = nullptr; long long ldo = 0; double alpha = 1.0;  // P4OUT_WS: complex128 result
+};
+long long p4_rows_alloc(long long rows);
+long long p4_ld(long long k);
+// allocate zeroed planes for a rows x k operand (rows padded to whole tiles plus one spare tile)
+int p4_alloc(P4& p, long long rows, long long k);
+// planes of X (rows x cols, complex128 if is64 else complex64), transposed and/or conjugated
+int p4_split(const void* X, int is64, long long ldx, int rows, int cols, int trans, int conj, const P4& out,
+             hipStream_t st);
+int p4_gemm(const P4Desc& g, hipStream_t st);
+// complex128 X (rows x cols) from planes, reading P[r][c] (or P[c][r] when trans)
+int p4_join(const P4& P, int rows, int cols, int trans, zd* X, long long ldx, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // level-1 / elementwise kernels on complex128 vectors of length len (= n*n)
 // ---------------------------------------------------------------------------
 // h[j] = <V_j, w> = sum_i conj(V[j*ld + i]) w[i], j < k.  Result left on device (h) in FP64.

@@ -18,6 +18,31 @@ static thread_local std::string g_create_err;
     if (rc__) return rc__ < 0 ? rc__ : LIND_EDEVICE;     \
   } while (0)
 
+// BF16x3 eigen route: split the constant operands of Phi into bf16 planes once, and allocate the
+// planes of its intermediates (all zero-padded to whole tiles)
+static int setup_p4(Ctx& c) {
+  const int n = c.n, d = c.d;
+  P4* bufs[7] = {&c.p4_VH, &c.p4_VT, &c.p4_Lt, &c.p4_xiT, &c.p4_C1, &c.p4_XhT, &c.p4_Y};
+  const long long rows[7] = {n, n, (long long)d * n, n, n, n, (long long)d * n};
+  for (int i = 0; i < 7; ++i) {
+    if (bufs[i]->p) continue;
+    if (p4_alloc(*bufs[i], rows[i], n)) return c.fail(LIND_ENOMEM, "out of device memory (bf16 planes)");
+    c.allocs.push_back(bufs[i]->p);
+  }
+  // V^H (rows m, k: conj V[k][m]), V^T (rows j, k: V[k][j]), L_j U stacked (rows, k)
+  if (p4_split(c.V, 1, n, n, n, 1, 1, c.p4_VH, c.st)) return LIND_EDEVICE;
+  if (p4_split(c.V, 1, n, n, n, 1, 0, c.p4_VT, c.st)) return LIND_EDEVICE;
+  if (p4_split(c.Lt, 1, n, d * n, n, 0, 0, c.p4_Lt, c.st)) return LIND_EDEVICE;
+  // split-K over the d jump operators: enough workgroups to cover the chip four times
+  const long long tiles = (long long)((n + 127) / 128) * ((n + 127) / 128);
+  int s = 1;
+  while (s * 2 <= d && d % (s * 2) == 0 && tiles * s < 1024) s *= 2;
+  c.p4_nsplit = s;
+  if (!c.p4_ws && c.alloc(&c.p4_ws, (size_t)s * c.n2)) return c.fail(LIND_ENOMEM, "out of device memory (split-K)");
+  c.p4_ready = true;
+  return 0;
+}
+
 extern "C" void lind_default_opts(lind_opts* o) {
   if (!o) return;
   o->prec = LIND_PREC_FP64;
@@ -158,6 +183,7 @@ static int ctx_factor(lind_ctx* X) {
     TRY(to_c64(c.Z, c.Z32, n2, c.st));
     if (d > 0) TRY(to_c64(c.Lt, c.Lt32, (long long)d * n2, c.st));
   }
+  if (c.prec == PREC_BF16X3 && route == LIND_ROUTE_EIG && d > 0) TRY(setup_p4(c));
   TRY(c.sync());
   c.t_factor = now_s() - t0;
   return 0;

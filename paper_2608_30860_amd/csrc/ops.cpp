@@ -227,6 +227,45 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     (void)mone;
     return 0;
   }
+  if (prec == PREC_BF16X3 && c.p4_ready) {
+    // pre-split BF16 products: xi^T planes, C1 = V^H xi, Xh^T = ((C1 V) / (s_i + conj s_j))^T,
+    // Y = [Lt_1; ..; Lt_d] Xh, Phi = -sum_j Y_j Lt_j^H (split-K partials, complex128 result)
+    int s0 = c.prof_begin(PROF_BASIS_IN);
+    TRY(p4_split(xi, 1, n, n, n, 1, 0, c.p4_xiT, c.st));
+    P4Desc g;
+    g.M = n; g.N = n; g.K = n;
+    g.A = c.p4_VH.p; g.lda = c.p4_VH.ld; g.pA = c.p4_VH.pstride;
+    g.B = c.p4_xiT.p; g.ldb = c.p4_xiT.ld; g.pB = c.p4_xiT.pstride;
+    g.out = P4OUT_PLANES; g.C = c.p4_C1.p; g.ldc = c.p4_C1.ld; g.pC = c.p4_C1.pstride;
+    TRY(p4_gemm(g, c.st));
+    P4Desc h;
+    h.M = n; h.N = n; h.K = n;
+    h.A = c.p4_C1.p; h.lda = c.p4_C1.ld; h.pA = c.p4_C1.pstride;
+    h.B = c.p4_VT.p; h.ldb = c.p4_VT.ld; h.pB = c.p4_VT.pstride;
+    h.dr = c.s; h.dc = c.sbar;
+    h.out = P4OUT_PLANES_T; h.C = c.p4_XhT.p; h.ldc = c.p4_XhT.ld; h.pC = c.p4_XhT.pstride;
+    TRY(p4_gemm(h, c.st));
+    c.prof_end(s0);
+    int s1 = c.prof_begin(PROF_JUMP_STACK);
+    P4Desc y;
+    y.M = d * n; y.N = n; y.K = n;
+    y.A = c.p4_Lt.p; y.lda = c.p4_Lt.ld; y.pA = c.p4_Lt.pstride;
+    y.B = c.p4_XhT.p; y.ldb = c.p4_XhT.ld; y.pB = c.p4_XhT.pstride;
+    y.out = P4OUT_PLANES; y.C = c.p4_Y.p; y.ldc = c.p4_Y.ld; y.pC = c.p4_Y.pstride;
+    TRY(p4_gemm(y, c.st));
+    c.prof_end(s1);
+    P4Desc r;
+    r.M = n; r.N = n; r.K = n; r.nbatch = d; r.nsplit = c.p4_nsplit;
+    r.A = c.p4_Y.p; r.lda = c.p4_Y.ld; r.pA = c.p4_Y.pstride; r.sA = (long long)n * c.p4_Y.ld;
+    r.B = c.p4_Lt.p; r.ldb = c.p4_Lt.ld; r.pB = c.p4_Lt.pstride; r.sB = (long long)n * c.p4_Lt.ld;
+    r.conjB = 1;
+    r.out = P4OUT_WS; r.ws = c.p4_ws; r.out64 = out; r.ldo = n; r.alpha = -1.0;
+    int s2 = c.prof_begin(PROF_JUMP_REDUCE);
+    TRY(p4_gemm(r, c.st));
+    c.prof_end(s2);
+    c.prof_end(sp);
+    return 0;
+  }
   int s0 = c.prof_begin(PROF_BASIS_IN);
   TRY(to_c64(xi, c.a32, n2, c.st));
   TRY(op_gemm(c, prec, n, n, n, c.V32, n, OP_C, c.a32, n, OP_N, c.b32, n, one, 0));

@@ -79,3 +79,58 @@ extern "C" int lindx_copy(void* dst, const void* src, long long nbytes, void* st
   hipLaunchKernelGGL(k_copy16, dim3((int)nb), dim3(256), 0, (hipStream_t)stream, (const uint4*)src, (uint4*)dst, n);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
+
+// C = sum_b op(A_b) op(B_b) through the pre-split BF16 product (complex128 in and out).
+// op(A) = A_b (M x K, row-major) or A_b^H (A_b stored K x M); op(B) = B_b (K x N) or B_b^H
+// (B_b stored N x K); batches are consecutive blocks.  out_mode: 0 planes, 1 transposed planes
+// (both read back as complex128), 2 split-K partials reduced to complex128.  dr, dc (optional,
+// planes modes): divide entry (m, n) by dr_m + dc_n.
+extern "C" int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch, int opA, int opB,
+                             int out_mode, const void* dr, const void* dc, void* C, void* stream) {
+  if (!A || !B || !C || M < 1 || N < 1 || K < 1 || nbatch < 1 || out_mode < 0 || out_mode > 2) return -1;
+  if ((opA != OP_N && opA != OP_C) || (opB != OP_N && opB != OP_C)) return -1;
+  if (out_mode != 2 && nbatch != 1) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  P4 pa, pb, pc;
+  int rc = p4_alloc(pa, (long long)nbatch * M, K);
+  if (!rc) rc = p4_alloc(pb, (long long)nbatch * N, K);
+  if (!rc && out_mode != 2) rc = (out_mode == 0) ? p4_alloc(pc, M, N) : p4_alloc(pc, N, M);
+  float2* ws = nullptr;
+  int nsplit = 1;
+  if (!rc && out_mode == 2) {
+    while (nsplit * 2 <= nbatch && nbatch % (nsplit * 2) == 0) nsplit *= 2;
+    if (hipMalloc((void**)&ws, sizeof(float2) * (size_t)nsplit * M * N) != hipSuccess) rc = -5;
+  }
+  const zd* Ad = (const zd*)A;
+  const zd* Bd = (const zd*)B;
+  for (int b = 0; b < nbatch && !rc; ++b) {
+    P4 sa = pa, sb = pb;
+    sa.p = pa.p + (long long)b * M * pa.ld;
+    sb.p = pb.p + (long long)b * N * pb.ld;
+    // A planes: rows m, k contiguous
+    if (opA == OP_N) rc = p4_split(Ad + (long long)b * M * K, 1, K, M, K, 0, 0, sa, st);
+    else rc = p4_split(Ad + (long long)b * M * K, 1, M, K, M, 1, 0, sa, st);  // conjugated in the kernel
+    if (rc) break;
+    // B planes: rows n, k contiguous
+    if (opB == OP_N) rc = p4_split(Bd + (long long)b * N * K, 1, N, K, N, 1, 0, sb, st);
+    else rc = p4_split(Bd + (long long)b * N * K, 1, K, N, K, 0, 0, sb, st);  // conjugated in the kernel
+  }
+  if (!rc) {
+    P4Desc g;
+    g.M = M; g.N = N; g.K = K; g.nbatch = nbatch; g.nsplit = nsplit;
+    g.A = pa.p; g.lda = pa.ld; g.pA = pa.pstride; g.sA = (long long)M * pa.ld;
+    g.B = pb.p; g.ldb = pb.ld; g.pB = pb.pstride; g.sB = (long long)N * pb.ld;
+    g.conjA = opA == OP_C;
+    g.conjB = opB == OP_C;
+    g.out = out_mode == 0 ? P4OUT_PLANES : (out_mode == 1 ? P4OUT_PLANES_T : P4OUT_WS);
+    g.C = pc.p; g.ldc = pc.ld; g.pC = pc.pstride;
+    g.dr = (const zd*)dr; g.dc = (const zd*)dc;
+    g.ws = ws; g.out64 = C; g.ldo = N; g.alpha = 1.0;
+    rc = p4_gemm(g, st);
+    if (!rc && out_mode != 2) rc = p4_join(pc, M, N, out_mode == 1, (zd*)C, N, st);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = -4;
+  for (void* p : {(void*)pa.p, (void*)pb.p, (void*)pc.p, (void*)ws})
+    if (p) hipFree(p);
+  return rc;
+}

@@ -1,0 +1,408 @@
+// Complex products on pre-split BF16 operands (BF16x3 mode of the map Phi).
+//
+// An FP32-accurate complex operand Z is kept in HBM as four bf16 planes
+//   [re_hi, re_lo, im_hi, im_lo],  hi = bf16(x), lo = bf16(x - hi)   (round to nearest even),
+// each a rows x ld matrix with the reduction index k contiguous, rows and k zero-padded to the
+// tile sizes.  Splitting once (constants at set-up, the Krylov vector once per Phi, every
+// intermediate in the epilogue of the product that makes it) removes the per-tile conversion work
+// of an on-the-fly split, and makes each stage a plain byte copy: global_load_lds_dwordx4 moves
+// 16 bytes per lane straight into LDS, double-buffered, so the next stage streams in while the
+// matrix cores work on the current one.
+//
+// Every real product is hi*hi + hi*lo + lo*hi with FP32 accumulation (v_mfma_f32_16x16x32_bf16):
+// twelve MFMAs per complex 16 x 16 x 32 step.  Block tile 128 x 128, 4 waves of 64 x 64.
+//
+// Outputs: planes (the next product's A operand, row-major), transposed planes (the next
+// product's B operand), or FP32 split-K partials reduced to complex128 by a second kernel.
+#include "kernels.hpp"
+
+namespace lindx {
+
+typedef float v4f_p __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf_p __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf_p __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u_p __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+namespace {
+
+constexpr int TB = 128;  // block tile (both dimensions)
+constexpr int KS = 32;   // k per stage
+
+__device__ inline v8bf_p neg8(v8bf_p v) {
+  v4u_p u = __builtin_bit_cast(v4u_p, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(v8bf_p, u);
+}
+
+__device__ inline v4f_p mfma16(v8bf_p a, v8bf_p b, v4f_p c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// 16-byte k chunk q of local row r sits in slot (q ^ ((r >> 2) & 3)) of the 64-byte LDS row, so
+// that the 16 rows an MFMA operand read touches fall in distinct bank groups
+__device__ inline int slot_of(int r, int q) { return q ^ ((r >> 2) & 3); }
+
+// XCD-aware tile order: consecutive workgroup ids go to different XCDs (round robin over 8), so
+// ids congruent mod 8 get a contiguous run of row-major tiles and share A panels in one L2
+__device__ inline void tile_xcd(int bid, int tm, int tn, int& bm, int& bn) {
+  const int T = tm * tn;
+  int t = bid;
+  if ((T & 7) == 0) t = (bid & 7) * (T >> 3) + (bid >> 3);
+  bm = t / tn;
+  bn = t - bm * tn;
+}
+
+__device__ inline void split_bf16(float x, __bf16& h, __bf16& l) {
+  h = (__bf16)x;
+  l = (__bf16)(x - (float)h);
+}
+
+template <bool SWAP, bool CONJ_A, bool CONJ_B, int OUT>
+__global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
+  // [stage][operand][plane][row][k]
+  __shared__ __attribute__((aligned(1024))) __bf16 S[2][2][4][TB][KS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  // wave-uniform values live in scalar registers: the stage loader's selections and addresses do
+  // not go through vector memory (whose waits would also wait for the loads in flight)
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave >> 1) * 64;
+  const int wn0 = (wave & 1) * 64;
+  const int tm = (g.M + TB - 1) / TB, tn = (g.N + TB - 1) / TB;
+  const int tiles = tm * tn;
+  const int split = blockIdx.x / tiles;
+  int bm, bn;
+  tile_xcd(blockIdx.x - split * tiles, tm, tn, bm, bn);
+  const int m0 = bm * TB, n0 = bn * TB;
+  const int ktiles = (g.K + KS - 1) / KS;
+  const int bps = g.nbatch / g.nsplit;
+  const int it_begin = split * bps * ktiles;
+  const int total = bps * ktiles;
+
+  // stage loader: 64 wave-loads of 1 KB (operand, plane, 16-row group).  Waves 0, 1 stage A and
+  // waves 2, 3 stage B, two planes each, all eight row groups.  Lane l of a wave-load writes LDS
+  // bytes [16 l, 16 l + 16) of the group: row l / 4, slot l % 4, i.e. k chunk slot_of(row, l % 4).
+  const int lrow = lane >> 2;
+  const int lslot = lane & 3;
+  const int lop = wave >> 1;
+  const int pl0 = 2 * (wave & 1);
+  const __bf16* Xs = lop ? g.B : g.A;
+  const long long xld = lop ? g.ldb : g.lda;
+  const long long xp = lop ? g.pB : g.pA;
+  const long long xs = lop ? g.sB : g.sA;
+  const long long lane_off = (long long)((lop ? n0 : m0) + lrow) * xld + slot_of(lrow, lslot) * 8;
+  auto issue = [&](int itl, int buf) {
+    const int it = it_begin + itl;
+    const int b = it / ktiles;
+    const int k0 = (it - b * ktiles) * KS;
+    const __bf16* base = Xs + (long long)b * xs + k0 + lane_off;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int pl = pl0 + (u >> 3);
+      const int q = u & 7;
+      const __bf16* src = base + (long long)pl * xp + (long long)q * 16 * xld;
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)&S[buf][lop][pl][q * 16][0], 16, 0, 0);
+    }
+  };
+
+  v4f_p cr[4][4], ci[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cr[i][j] = v4f_p{0, 0, 0, 0};
+      ci[i][j] = v4f_p{0, 0, 0, 0};
+    }
+
+  const int kq = lane >> 4;
+  if (total > 0) issue(0, 0);
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    // the loads of this stage have landed (the barrier waits for every outstanding load), and
+    // every wave is done with the other buffer, which the next stage may now overwrite
+    __syncthreads();
+    if (it + 1 < total) issue(it + 1, buf ^ 1);
+    v8bf_p a[4][4], bb[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm0 + i * 16 + (lane & 15);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) a[i][p] = *(const v8bf_p*)&S[buf][0][p][r][slot_of(r, kq) * 8];
+      if (CONJ_A) { a[i][2] = neg8(a[i][2]); a[i][3] = neg8(a[i][3]); }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = wn0 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) bb[j][p] = *(const v8bf_p*)&S[buf][1][p][r][slot_of(r, kq) * 8];
+      if (CONJ_B) { bb[j][2] = neg8(bb[j][2]); bb[j][3] = neg8(bb[j][3]); }
+    }
+    // -Ai for the real part
+    v8bf_p an[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { an[i][0] = neg8(a[i][2]); an[i][1] = neg8(a[i][3]); }
+    // re += Ar Br - Ai Bi, im += Ar Bi + Ai Br; each group issues 16 independent MFMAs.
+    // SWAP computes the transposed tile (B fragment as the MFMA row operand), so that a lane's
+    // four accumulator entries run along n instead of m.
+#define P4_GROUP(ACC, AF, BP)                                                          \
+  _Pragma("unroll") for (int i = 0; i < 4; ++i)                                        \
+    _Pragma("unroll") for (int j = 0; j < 4; ++j) ACC[i][j] =                          \
+        SWAP ? mfma16(bb[j][BP], AF, ACC[i][j]) : mfma16(AF, bb[j][BP], ACC[i][j]);
+    P4_GROUP(cr, a[i][0], 0)
+    P4_GROUP(ci, a[i][0], 2)
+    P4_GROUP(cr, a[i][0], 1)
+    P4_GROUP(ci, a[i][0], 3)
+    P4_GROUP(cr, a[i][1], 0)
+    P4_GROUP(ci, a[i][1], 2)
+    P4_GROUP(cr, an[i][0], 2)
+    P4_GROUP(ci, a[i][2], 0)
+    P4_GROUP(cr, an[i][0], 3)
+    P4_GROUP(ci, a[i][2], 1)
+    P4_GROUP(cr, an[i][1], 2)
+    P4_GROUP(ci, a[i][3], 0)
+#undef P4_GROUP
+  }
+
+  // epilogue.  Normal: lane holds rows m = ..+4*(lane>>4)+r at column n = ..+(lane&15).
+  // SWAP: lane holds columns n = ..+4*(lane>>4)+r at row m = ..+(lane&15).
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int mb = m0 + wm0 + i * 16, nb = n0 + wn0 + j * 16;
+      const int m_l = SWAP ? mb + (lane & 15) : mb + 4 * (lane >> 4);
+      const int n_l = SWAP ? nb + 4 * (lane >> 4) : nb + (lane & 15);
+      float re[4], im[4];
+      int mm[4], nn[4];
+      bool ok[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        mm[r] = SWAP ? m_l : m_l + r;
+        nn[r] = SWAP ? n_l + r : n_l;
+        ok[r] = mm[r] < g.M && nn[r] < g.N;
+        re[r] = cr[i][j][r];
+        im[r] = ci[i][j][r];
+      }
+      if (OUT == P4OUT_WS) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (ok[r]) g.ws[((long long)split * g.M + mm[r]) * g.N + nn[r]] = make_float2(re[r], im[r]);
+        continue;
+      }
+      if (g.dr) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (!ok[r]) continue;
+          const zd den = zmk(g.dr[mm[r]].x + g.dc[nn[r]].x, g.dr[mm[r]].y + g.dc[nn[r]].y);
+          const zd q = zdiv(zmk(re[r], im[r]), den);
+          re[r] = (float)q.x;
+          im[r] = (float)q.y;
+        }
+      }
+      v4bf_p h0, l0, h1, l1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        __bf16 h, l;
+        split_bf16(re[r], h, l);
+        h0[r] = h; l0[r] = l;
+        split_bf16(im[r], h, l);
+        h1[r] = h; l1[r] = l;
+      }
+      // planes row-major [m][n] (P4OUT_PLANES, SWAP: four consecutive n) or transposed [n][m]
+      // (P4OUT_PLANES_T, normal: four consecutive m)
+      const long long base = (OUT == P4OUT_PLANES) ? (long long)m_l * g.ldc + n_l : (long long)n_l * g.ldc + m_l;
+      const bool all = ok[0] && ok[1] && ok[2] && ok[3];
+      if (all) {
+        *(v4bf_p*)(g.C + base) = h0;
+        *(v4bf_p*)(g.C + g.pC + base) = l0;
+        *(v4bf_p*)(g.C + 2 * g.pC + base) = h1;
+        *(v4bf_p*)(g.C + 3 * g.pC + base) = l1;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (!ok[r]) continue;
+          g.C[base + r] = h0[r];
+          g.C[g.pC + base + r] = l0[r];
+          g.C[2 * g.pC + base + r] = h1[r];
+          g.C[3 * g.pC + base + r] = l1[r];
+        }
+      }
+    }
+}
+
+// sum of the FP32 split-K partials, scaled by alpha, into complex128 (row-major, ldo)
+__global__ __launch_bounds__(256) void k_p4_reduce(const float2* __restrict__ ws, int nsplit, int M, int N,
+                                                   double alpha, zd* __restrict__ out, long long ldo) {
+  const long long tot = (long long)M * N;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    double re = 0, im = 0;
+    for (int s = 0; s < nsplit; ++s) {
+      const float2 v = ws[(long long)s * tot + t];
+      re += v.x;
+      im += v.y;
+    }
+    const int row = (int)(t / N), col = (int)(t - (long long)row * N);
+    out[(long long)row * ldo + col] = zmk(alpha * re, alpha * im);
+  }
+}
+
+// planes of op(X): out[r][k] = X[r][k] (or X[k][r] when transposed), conjugated on request;
+// complex128 or complex64 input.  32 x 32 tiles through LDS so both sides stay coalesced.
+template <typename Cplx, bool TRANS, bool CONJ>
+__global__ __launch_bounds__(256) void k_p4_split(const Cplx* __restrict__ X, long long ldx, int rows, int cols,
+                                                  __bf16* __restrict__ P, long long ld, long long pstride) {
+  __shared__ float2 tile[32][33];
+  // output extent: R rows x C k-columns
+  const int R = TRANS ? cols : rows, C = TRANS ? rows : cols;
+  const int tr = (R + 31) / 32;
+  const int br = blockIdx.x % tr, bc = blockIdx.x / tr;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int r0 = br * 32, c0 = bc * 32;
+  if (TRANS) {
+    // X rows c0.., columns r0..: read X[c][r] coalesced along r, write out[r][c] along c
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int c = c0 + yy, r = r0 + tx;
+      float2 v = make_float2(0.f, 0.f);
+      if (c < C && r < R) {
+        const Cplx x = X[(long long)c * ldx + r];
+        v = make_float2((float)x.x, (float)x.y);
+      }
+      tile[yy][tx] = v;
+    }
+    __syncthreads();
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int r = r0 + yy, c = c0 + tx;
+      if (r < R && c < C) {
+        float2 v = tile[tx][yy];
+        if (CONJ) v.y = -v.y;
+        __bf16 h, l;
+        const long long o = (long long)r * ld + c;
+        split_bf16(v.x, h, l);
+        P[o] = h;
+        P[pstride + o] = l;
+        split_bf16(v.y, h, l);
+        P[2 * pstride + o] = h;
+        P[3 * pstride + o] = l;
+      }
+    }
+  } else {
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int r = r0 + yy, c = c0 + tx;
+      if (r < R && c < C) {
+        const Cplx x = X[(long long)r * ldx + c];
+        float2 v = make_float2((float)x.x, (float)x.y);
+        if (CONJ) v.y = -v.y;
+        __bf16 h, l;
+        const long long o = (long long)r * ld + c;
+        split_bf16(v.x, h, l);
+        P[o] = h;
+        P[pstride + o] = l;
+        split_bf16(v.y, h, l);
+        P[2 * pstride + o] = h;
+        P[3 * pstride + o] = l;
+      }
+    }
+  }
+}
+
+// complex128 value of planes: X[r][c] = (re_hi + re_lo, im_hi + im_lo) of P[r][c] (or of P[c][r])
+__global__ __launch_bounds__(256) void k_p4_join(const __bf16* __restrict__ P, long long ld, long long pstride,
+                                                 int rows, int cols, int trans, zd* __restrict__ X, long long ldx) {
+  const long long tot = (long long)rows * cols;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    const int r = (int)(t / cols), c = (int)(t - (long long)r * cols);
+    const long long o = trans ? (long long)c * ld + r : (long long)r * ld + c;
+    const double re = (double)(float)P[o] + (double)(float)P[pstride + o];
+    const double im = (double)(float)P[2 * pstride + o] + (double)(float)P[3 * pstride + o];
+    X[(long long)r * ldx + c] = zmk(re, im);
+  }
+}
+
+template <bool SWAP, int OUT>
+int launch_p4_out(const P4Desc& g, int blocks, hipStream_t st) {
+  if (g.conjA && g.conjB) hipLaunchKernelGGL((k_p4_gemm<SWAP, true, true, OUT>), dim3(blocks), dim3(256), 0, st, g);
+  else if (g.conjA) hipLaunchKernelGGL((k_p4_gemm<SWAP, true, false, OUT>), dim3(blocks), dim3(256), 0, st, g);
+  else if (g.conjB) hipLaunchKernelGGL((k_p4_gemm<SWAP, false, true, OUT>), dim3(blocks), dim3(256), 0, st, g);
+  else hipLaunchKernelGGL((k_p4_gemm<SWAP, false, false, OUT>), dim3(blocks), dim3(256), 0, st, g);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+}  // namespace
+
+long long p4_rows_alloc(long long rows) { return (rows + TB - 1) / TB * TB + TB; }
+long long p4_ld(long long k) { return (k + KS - 1) / KS * KS; }
+
+int p4_alloc(P4& p, long long rows, long long k) {
+  p.rows = p4_rows_alloc(rows);
+  p.ld = p4_ld(k);
+  p.pstride = p.rows * p.ld;
+  const size_t bytes = (size_t)(4 * p.pstride) * sizeof(__bf16);
+  if (hipMalloc((void**)&p.p, bytes) != hipSuccess) { p.p = nullptr; return -5; }
+  if (hipMemset(p.p, 0, bytes) != hipSuccess) return -4;  // zero padding in rows and k
+  return 0;
+}
+
+int p4_split(const void* X, int is64, long long ldx, int rows, int cols, int trans, int conj, const P4& out,
+             hipStream_t st) {
+  const int R = trans ? cols : rows, C = trans ? rows : cols;
+  if (R > out.rows || C > out.ld || rows <= 0 || cols <= 0) return -1;
+  const int blocks = ((R + 31) / 32) * ((C + 31) / 32);
+#define P4_SPLIT(T, TR, CJ) \
+  hipLaunchKernelGGL((k_p4_split<T, TR, CJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, ldx, rows, cols, out.p, out.ld, out.pstride)
+  if (is64) {
+    if (trans) { if (conj) P4_SPLIT(zd, true, true); else P4_SPLIT(zd, true, false); }
+    else { if (conj) P4_SPLIT(zd, false, true); else P4_SPLIT(zd, false, false); }
+  } else {
+    if (trans) { if (conj) P4_SPLIT(zf, true, true); else P4_SPLIT(zf, true, false); }
+    else { if (conj) P4_SPLIT(zf, false, true); else P4_SPLIT(zf, false, false); }
+  }
+#undef P4_SPLIT
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int p4_join(const P4& P, int rows, int cols, int trans, zd* X, long long ldx, hipStream_t st) {
+  long long tot = (long long)rows * cols;
+  long long nb = (tot + 255) / 256;
+  if (nb > 16384) nb = 16384;
+  if (nb < 1) return 0;
+  hipLaunchKernelGGL(k_p4_join, dim3((int)nb), dim3(256), 0, st, P.p, P.ld, P.pstride, rows, cols, trans, X, ldx);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+long long p4_ws_elems(int M, int N, int nsplit) { return (long long)nsplit * M * N; }
+
+int p4_gemm(const P4Desc& g0, hipStream_t st) {
+  P4Desc g = g0;
+  if (g.M <= 0 || g.N <= 0) return 0;
+  if (g.K <= 0 || g.nbatch <= 0 || g.nsplit <= 0 || g.nbatch % g.nsplit) return -1;
+  // every stage reads whole 128-row tiles and 32-wide k chunks: the planes must hold them
+  const long long kpad = p4_ld(g.K);
+  if (g.lda < kpad || g.ldb < kpad) return -1;
+  const long long mt = (g.M + TB - 1) / TB * TB, nt = (g.N + TB - 1) / TB * TB;
+  if ((g.nbatch - 1) * g.sA + (mt - 1) * g.lda + kpad > g.pA) return -1;
+  if ((g.nbatch - 1) * g.sB + (nt - 1) * g.ldb + kpad > g.pB) return -1;
+  if ((g.lda % 8) || (g.ldb % 8) || (g.sA % 8) || (g.sB % 8) || (g.pA % 8) || (g.pB % 8)) return -1;
+  if ((((unsigned long long)g.A) & 15) || (((unsigned long long)g.B) & 15)) return -1;
+  const int tiles = (int)((mt / TB) * (nt / TB));
+  const int blocks = tiles * g.nsplit;
+  if (g.out == P4OUT_WS) {
+    if (!g.ws) return -1;
+    int rc = launch_p4_out<true, P4OUT_WS>(g, blocks, st);
+    if (rc) return rc;
+    long long tot = (long long)g.M * g.N;
+    long long nbk = (tot + 255) / 256;
+    if (nbk > 16384) nbk = 16384;
+    hipLaunchKernelGGL(k_p4_reduce, dim3((int)nbk), dim3(256), 0, st, (const float2*)g.ws, g.nsplit, g.M, g.N,
+                       g.alpha, (zd*)g.out64, g.ldo);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+  }
+  if (!g.C || (g.ldc % 4) || (g.pC % 4)) return -1;
+  if (g.out == P4OUT_PLANES) return launch_p4_out<true, P4OUT_PLANES>(g, blocks, st);
+  if (g.out == P4OUT_PLANES_T) return launch_p4_out<false, P4OUT_PLANES_T>(g, blocks, st);
+  return -1;
+}
+
+}  // namespace lindx

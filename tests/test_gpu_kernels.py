@@ -19,6 +19,7 @@ def lib():
     L.lindx_trevec.argtypes = [vp, vp, ci, vp]
     L.lindx_triinv.argtypes = [vp, vp, ci, vp]
     L.lindx_trisylv.argtypes = [vp, vp, ci, cd, cd, vp]
+    L.lindx_p4_test.argtypes = [vp, vp, ci, ci, ci, ci, ci, ci, ci, vp, vp, vp, vp]
     return L
 
 
@@ -69,6 +70,38 @@ def test_gemm(prec, tol, M, N, K, nb, opA, opB):
                 want = want  # complex64 output
             err = np.max(np.abs(got - want)) / np.max(np.abs(want))
             assert err < tol, (beta, out64, err)
+
+
+@pytest.mark.parametrize("M,N,K,nb", [(37, 45, 29, 1), (130, 70, 200, 1), (128, 128, 64, 1), (300, 260, 72, 1),
+                                      (1, 1, 1, 1), (256, 384, 1000, 1), (64, 64, 64, 3), (300, 260, 72, 8),
+                                      (1024, 1024, 64, 4)])
+@pytest.mark.parametrize("opA,opB", [(0, 0), (2, 0), (0, 2), (2, 2)])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_p4_gemm(M, N, K, nb, opA, opB, mode):
+    """pre-split BF16 product: planes out (row-major / transposed), split-K partials out, and the
+    fused divide; relative to the largest entry, 3e-4 as for the on-the-fly BF16x3 product"""
+    if mode != 2 and nb != 1:
+        pytest.skip("batched products only reduce into split-K partials")
+    print(f"[case] p4 {M}x{N}x{K} nb={nb} ops={opA},{opB} mode={mode}", flush=True)
+    rng = np.random.default_rng(M * 5 + N + 3 * K + nb + 11 * mode)
+    Ash = (nb, M, K) if opA == 0 else (nb, K, M)
+    Bsh = (nb, K, N) if opB == 0 else (nb, N, K)
+    A = crand(rng, *Ash)
+    B = crand(rng, *Bsh)
+    ref = sum(op(A[b], opA) @ op(B[b], opB) for b in range(nb))
+    for div in ((False, True) if mode != 2 else (False,)):
+        dr = crand(rng, M) + 3.0 if div else None
+        dc = crand(rng, N) + 3.0 if div else None
+        want = ref / (dr[:, None] + dc[None, :]) if div else ref
+        Ct = T(np.zeros((M, N)))
+        At, Bt = T(A), T(B)  # keep the device copies alive across the call
+        drt, dct = (T(dr), T(dc)) if div else (None, None)
+        rc = lib().lindx_p4_test(P(At), P(Bt), M, N, K, nb, opA, opB, mode,
+                                 P(drt) if div else None, P(dct) if div else None, P(Ct), None)
+        assert rc == 0
+        got = Ct.cpu().numpy()
+        err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        assert err < 3e-4, (div, err)
 
 
 @pytest.mark.parametrize("n", [3, 37, 130, 257])
