@@ -486,6 +486,147 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc g) {
       }
 }
 
+// ---------------------------------------------------------------------------------------------
+// FP64 kernel with direct-to-LDS staging.  Block tile 128 x 128, 16 complex k per stage, two LDS
+// stages (2 x 64 KB): buffer_load_dwordx4 ... lds moves one complex128 per lane straight into LDS
+// while the matrix cores work on the other stage.  Out-of-range rows and k come back as zeros from
+// the bounds check of the buffer resource, so ragged edges need no separate path.
+// Per operand the tile is held either "row-k" (rows = m or n, 16 k per 256-byte row, slot of k
+// XOR-swizzled by the row's low four bits) when k is contiguous in memory (A as stored, B^H), or
+// "k-row" (rows = k, 128 m or n per row) otherwise (A^H, B as stored); both give the 16 lanes of
+// an MFMA operand read 16 distinct bank groups.  8 waves in a 2 x 4 grid of 64 x 32 sub-tiles.
+// ---------------------------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+constexpr int Z64_TB = 128, Z64_BK = 16;
+
+template <bool AN, bool BN>
+__global__ __launch_bounds__(512) void zgemm64_dma(GemmDesc g, int a_bytes, int b_bytes) {
+  __shared__ __attribute__((aligned(1024))) double2 S[2][2][Z64_TB * Z64_BK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 32;
+  const int tm = (g.M + Z64_TB - 1) / Z64_TB, tn = (g.N + Z64_TB - 1) / Z64_TB;
+  const int tiles = tm * tn;
+  const int split = blockIdx.x / tiles;
+  int bm, bn;
+  tile_of(blockIdx.x - split * tiles, tm, tn, bm, bn);
+  const int m0 = bm * Z64_TB, n0 = bn * Z64_TB;
+  const int ktiles = (g.K + Z64_BK - 1) / Z64_BK;
+  const int bps = g.nbatch / g.nsplit;
+  const int it_begin = split * bps * ktiles;
+  const int total = bps * ktiles;
+
+  // loader: waves 0-3 stage A, 4-7 stage B, 8 wave-loads of 64 elements (1 KB) each.  Lane l of
+  // wave-load q writes LDS element 64 q + l of the operand's tile.
+  const int lop = wave >> 2;
+  const bool rk = lop ? !BN : AN;
+  const long long ld = lop ? g.ldb : g.lda;
+  const long long bstride = lop ? g.sB : g.sA;
+  const int x0 = lop ? n0 : m0;
+  const int xvalid = lop ? g.N : g.M;
+  __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(lop ? g.B : g.A), (short)0,
+                                                                   lop ? b_bytes : a_bytes, 0x00020000);
+  long long eoff[8];  // element offset of this lane's element for k0 = 0, batch 0
+  int kk[8];          // its k within the stage
+  bool rowok[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = (wave & 3) * 8 + u;
+    if (rk) {
+      const int r = 4 * q + (lane >> 4);
+      const int k = (lane & 15) ^ (r & 15);
+      kk[u] = k;
+      rowok[u] = x0 + r < xvalid;
+      eoff[u] = (long long)(x0 + r) * ld + k;
+    } else {
+      const int k = q >> 1;
+      const int r = 64 * (q & 1) + lane;
+      kk[u] = k;
+      rowok[u] = x0 + r < xvalid;
+      eoff[u] = (long long)k * ld + x0 + r;
+    }
+  }
+  auto issue = [&](int itl, int buf) {
+    const int it = it_begin + itl;
+    const int b = it / ktiles;
+    const int k0 = (it - b * ktiles) * Z64_BK;
+    const long long kofs = rk ? (long long)k0 : (long long)k0 * ld;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = (wave & 3) * 8 + u;
+      const bool ok = rowok[u] && (k0 + kk[u] < g.K);
+      const unsigned off = ok ? (unsigned)((b * bstride + kofs + eoff[u]) * 16) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t*)&S[buf][lop][64 * q], 16, off, 0, 0, 0);
+    }
+  };
+
+  v4d cr[4][2], ci[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = v4d{0, 0, 0, 0};
+      ci[i][j] = v4d{0, 0, 0, 0};
+    }
+  if (total > 0) issue(0, 0);
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    __syncthreads();  // this stage has landed; every wave is done with the other buffer
+    if (it + 1 < total) issue(it + 1, buf ^ 1);
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int k = 4 * st + (lane >> 4);
+      double2 a[4], bq[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = wm0 + i * 16 + (lane & 15);
+        a[i] = AN ? S[buf][0][m * 16 + (k ^ (m & 15))] : S[buf][0][k * 128 + m];
+        if (!AN) a[i].y = -a[i].y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int nn = wn0 + j * 16 + (lane & 15);
+        bq[j] = BN ? S[buf][1][k * 128 + nn] : S[buf][1][nn * 16 + (k ^ (nn & 15))];
+        if (!BN) bq[j].y = -bq[j].y;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double nai = -a[i].y;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = mfma(a[i].x, bq[j].x, cr[i][j]);
+          ci[i][j] = mfma(a[i].x, bq[j].y, ci[i][j]);
+          cr[i][j] = mfma(nai, bq[j].y, cr[i][j]);
+          ci[i][j] = mfma(a[i].y, bq[j].x, ci[i][j]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + i * 16 + 4 * r + (lane >> 4);
+        const int col = n0 + wn0 + j * 16 + (lane & 15);
+        if (g.nsplit > 1) {
+          if (row < g.M && col < g.N)
+            ((double2*)g.ws)[((long long)split * g.M + row) * g.N + col] = make_double2(cr[i][j][r], ci[i][j][r]);
+        } else {
+          epilogue_store<double2>(g, row, col, cr[i][j][r], ci[i][j][r]);
+        }
+      }
+}
+
+// bytes an operand spans (batches included), or -1 past the reach of a 32-bit buffer offset
+static long long z64_extent(long long rows, long long cols, long long ld, long long bstride, int nbatch) {
+  if (rows <= 0 || cols <= 0) return 0;
+  long long e = ((long long)(nbatch - 1) * bstride + (rows - 1) * ld + cols) * 16;
+  return e < 0x7ff00000LL ? e : -1;
+}
+
 // sum the split-K partials and apply the epilogue
 template <typename CplxAcc, typename CplxOut>
 __global__ __launch_bounds__(256) void k_splitk_reduce(GemmDesc g) {
@@ -559,6 +700,28 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
   }
   int rc = 0;
   if (prec == PREC_F64) {
+    const bool an = g.opA == OP_N, bn = g.opB == OP_N;
+    const long long ea = an ? z64_extent(g.M, g.K, g.lda, g.sA, g.nbatch) : z64_extent(g.K, g.M, g.lda, g.sA, g.nbatch);
+    const long long eb = bn ? z64_extent(g.K, g.N, g.ldb, g.sB, g.nbatch) : z64_extent(g.N, g.K, g.ldb, g.sB, g.nbatch);
+    const bool aligned = (((unsigned long long)g.A | (unsigned long long)g.B) & 15) == 0;
+    if (ea > 0 && eb > 0 && aligned) {
+      // direct-to-LDS kernel; the split-K count is re-derived for its 128 x 128 tiles
+      if (g0.ws) {
+        int s = 1;
+        const long long t = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128);
+        while (s * 2 <= g.nbatch && (g.nbatch % (s * 2)) == 0 && t * s < 1024 && (long long)(s * 2) * g.M * g.N * 16 <= gemm_ws_bytes(PREC_F64, g.M, g.N, g.nbatch)) s *= 2;
+        g.nsplit = s;
+      }
+      const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+      const dim3 grid(tm * tn * g.nsplit), blk(512);
+      if (an && bn) hipLaunchKernelGGL((zgemm64_dma<true, true>), grid, blk, 0, st, g, (int)ea, (int)eb);
+      else if (an) hipLaunchKernelGGL((zgemm64_dma<true, false>), grid, blk, 0, st, g, (int)ea, (int)eb);
+      else if (bn) hipLaunchKernelGGL((zgemm64_dma<false, true>), grid, blk, 0, st, g, (int)ea, (int)eb);
+      else hipLaunchKernelGGL((zgemm64_dma<false, false>), grid, blk, 0, st, g, (int)ea, (int)eb);
+      rc = hipGetLastError() == hipSuccess ? 0 : -4;
+      if (!rc && g.nsplit > 1) rc = launch_reduce<double2, double2>(g, st);
+      return rc;
+    }
     if (g.nsplit > 1 || (g.M >= 1024 && g.N >= 1024)) rc = launch(zgemm_kernel<double, 128, 64, 16, double2>, 128, 64, g, st);
     else rc = launch(zgemm_kernel<double, 64, 64, 16, double2>, 64, 64, g, st);
     if (!rc && g.nsplit > 1) rc = launch_reduce<double2, double2>(g, st);

@@ -10,7 +10,7 @@
 // matrix cores work on the current one.
 //
 // Every real product is hi*hi + hi*lo + lo*hi with FP32 accumulation (v_mfma_f32_16x16x32_bf16):
-// twelve MFMAs per complex 16 x 16 x 32 step.  Block tile 128 x 128, 4 waves of 64 x 64.
+// twelve MFMAs per complex 16 x 16 x 32 step.  Block tile 128 x 128, 8 waves of 64 x 32.
 //
 // Outputs: planes (the next product's A operand, row-major), transposed planes (the next
 // product's B operand), or FP32 split-K partials reduced to complex128 by a second kernel.
@@ -44,11 +44,25 @@ __device__ inline v4f_p mfma16(v8bf_p a, v8bf_p b, v4f_p c) {
 __device__ inline int slot_of(int r, int q) { return q ^ ((r >> 2) & 3); }
 
 // XCD-aware tile order: consecutive workgroup ids go to different XCDs (round robin over 8), so
-// ids congruent mod 8 get a contiguous run of row-major tiles and share A panels in one L2
+// ids congruent mod 8 get a contiguous run of tiles.  When that run is whole tile rows, it is
+// walked in column-major groups of 4 tile rows: the 32 workgroups an XCD runs at once then cover
+// 4 x 8 tiles and share 4 A panels and 8 B panels in that XCD's L2 (2 x 16 for row-major order).
 __device__ inline void tile_xcd(int bid, int tm, int tn, int& bm, int& bn) {
   const int T = tm * tn;
   int t = bid;
-  if ((T & 7) == 0) t = (bid & 7) * (T >> 3) + (bid >> 3);
+  if ((T & 7) == 0) {
+    const int run = T >> 3;
+    const int local = bid >> 3;
+    t = (bid & 7) * run + local;
+    constexpr int GH = 4;
+    if (run % (GH * tn) == 0) {
+      const int r0 = (bid & 7) * (run / tn);
+      const int g = local / (GH * tn), w = local - g * GH * tn;
+      bm = r0 + g * GH + w % GH;
+      bn = w / GH;
+      return;
+    }
+  }
   bm = t / tn;
   bn = t - bm * tn;
 }
@@ -58,8 +72,11 @@ __device__ inline void split_bf16(float x, __bf16& h, __bf16& l) {
   l = (__bf16)(x - (float)h);
 }
 
-template <bool SWAP, bool CONJ_A, bool CONJ_B, int OUT>
-__global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
+// NW waves per block: 4 (2 x 2 waves of 64 x 64) or 8 (2 x 4 waves of 64 x 32, two waves per SIMD)
+template <int NW, bool SWAP, bool CONJ_A, bool CONJ_B, int OUT>
+__global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
+  constexpr int TNW = NW == 4 ? 4 : 2;   // 16-wide n fragments per wave
+  constexpr int LPW = 64 / NW;           // wave-loads (1 KB) per wave per stage
   // [stage][operand][plane][row][k]
   __shared__ __attribute__((aligned(1024))) __bf16 S[2][2][4][TB][KS];
   const int tid = threadIdx.x;
@@ -67,8 +84,8 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
   // wave-uniform values live in scalar registers: the stage loader's selections and addresses do
   // not go through vector memory (whose waits would also wait for the loads in flight)
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm0 = (wave >> 1) * 64;
-  const int wn0 = (wave & 1) * 64;
+  const int wm0 = (wave / (NW / 2)) * 64;
+  const int wn0 = (wave % (NW / 2)) * (16 * TNW);
   const int tm = (g.M + TB - 1) / TB, tn = (g.N + TB - 1) / TB;
   const int tiles = tm * tn;
   const int split = blockIdx.x / tiles;
@@ -80,13 +97,13 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
   const int it_begin = split * bps * ktiles;
   const int total = bps * ktiles;
 
-  // stage loader: 64 wave-loads of 1 KB (operand, plane, 16-row group).  Waves 0, 1 stage A and
-  // waves 2, 3 stage B, two planes each, all eight row groups.  Lane l of a wave-load writes LDS
+  // stage loader: 64 wave-loads of 1 KB (operand, plane, 16-row group), LPW per wave: the first
+  // half of the waves stage A, the second half B.  Lane l of a wave-load writes LDS
   // bytes [16 l, 16 l + 16) of the group: row l / 4, slot l % 4, i.e. k chunk slot_of(row, l % 4).
   const int lrow = lane >> 2;
   const int lslot = lane & 3;
-  const int lop = wave >> 1;
-  const int pl0 = 2 * (wave & 1);
+  const int lop = wave / (NW / 2);
+  const int pl0 = ((wave * LPW) >> 3) & 3;
   const __bf16* Xs = lop ? g.B : g.A;
   const long long xld = lop ? g.ldb : g.lda;
   const long long xp = lop ? g.pB : g.pA;
@@ -98,7 +115,7 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
     const int k0 = (it - b * ktiles) * KS;
     const __bf16* base = Xs + (long long)b * xs + k0 + lane_off;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < LPW; ++u) {
       const int pl = pl0 + (u >> 3);
       const int q = u & 7;
       const __bf16* src = base + (long long)pl * xp + (long long)q * 16 * xld;
@@ -106,11 +123,11 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
     }
   };
 
-  v4f_p cr[4][4], ci[4][4];
+  v4f_p cr[4][TNW], ci[4][TNW];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < TNW; ++j) {
       cr[i][j] = v4f_p{0, 0, 0, 0};
       ci[i][j] = v4f_p{0, 0, 0, 0};
     }
@@ -123,7 +140,7 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
     // every wave is done with the other buffer, which the next stage may now overwrite
     __syncthreads();
     if (it + 1 < total) issue(it + 1, buf ^ 1);
-    v8bf_p a[4][4], bb[4][4];
+    v8bf_p a[4][4], bb[TNW][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = wm0 + i * 16 + (lane & 15);
@@ -132,7 +149,7 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
       if (CONJ_A) { a[i][2] = neg8(a[i][2]); a[i][3] = neg8(a[i][3]); }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < TNW; ++j) {
       const int r = wn0 + j * 16 + (lane & 15);
 #pragma unroll
       for (int p = 0; p < 4; ++p) bb[j][p] = *(const v8bf_p*)&S[buf][1][p][r][slot_of(r, kq) * 8];
@@ -147,7 +164,7 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
     // four accumulator entries run along n instead of m.
 #define P4_GROUP(ACC, AF, BP)                                                          \
   _Pragma("unroll") for (int i = 0; i < 4; ++i)                                        \
-    _Pragma("unroll") for (int j = 0; j < 4; ++j) ACC[i][j] =                          \
+    _Pragma("unroll") for (int j = 0; j < TNW; ++j) ACC[i][j] =                        \
         SWAP ? mfma16(bb[j][BP], AF, ACC[i][j]) : mfma16(AF, bb[j][BP], ACC[i][j]);
     P4_GROUP(cr, a[i][0], 0)
     P4_GROUP(ci, a[i][0], 2)
@@ -169,7 +186,7 @@ __global__ __launch_bounds__(256) void k_p4_gemm(P4Desc g) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < TNW; ++j) {
       const int mb = m0 + wm0 + i * 16, nb = n0 + wn0 + j * 16;
       const int m_l = SWAP ? mb + (lane & 15) : mb + 4 * (lane >> 4);
       const int n_l = SWAP ? nb + 4 * (lane >> 4) : nb + (lane & 15);
@@ -323,10 +340,13 @@ __global__ __launch_bounds__(256) void k_p4_join(const __bf16* __restrict__ P, l
 
 template <bool SWAP, int OUT>
 int launch_p4_out(const P4Desc& g, int blocks, hipStream_t st) {
-  if (g.conjA && g.conjB) hipLaunchKernelGGL((k_p4_gemm<SWAP, true, true, OUT>), dim3(blocks), dim3(256), 0, st, g);
-  else if (g.conjA) hipLaunchKernelGGL((k_p4_gemm<SWAP, true, false, OUT>), dim3(blocks), dim3(256), 0, st, g);
-  else if (g.conjB) hipLaunchKernelGGL((k_p4_gemm<SWAP, false, true, OUT>), dim3(blocks), dim3(256), 0, st, g);
-  else hipLaunchKernelGGL((k_p4_gemm<SWAP, false, false, OUT>), dim3(blocks), dim3(256), 0, st, g);
+  // 8 waves per block (two per SIMD) hide the LDS-read latency of one wave behind the other's
+  // matrix-core work
+  constexpr int NW = 8;
+  if (g.conjA && g.conjB) hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, true, true, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
+  else if (g.conjA) hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, true, false, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
+  else if (g.conjB) hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, false, true, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
+  else hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, false, false, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
