@@ -22,9 +22,12 @@ quantum systems"):
 * ``oracle.gradient`` -- gradients of <O> = Re Tr(O rho_inf): dense forward
   sensitivity (one linear solve per real direction), the adjoint formula, and
   central finite differences.
+* ``oracle.dynamics`` -- the resolvent (lambda - L)^{-1} (dense definition, the
+  series of the resolvent corollary, right-preconditioned GMRES), the contraction
+  norm of K R^S_lambda, and the implicit Euler step (I - dt L)^{-1}.
 
 Parity status of every function is stated in its docstring.  Nothing in the
 oracle is "parity unpinned" except the matrix-free spectrum at sizes where no
 dense reference exists (certified there only by its own residual).
 """
-from . import lindblad, krylov, gradient  # noqa: F401
+from . import lindblad, krylov, gradient, dynamics  # noqa: F401

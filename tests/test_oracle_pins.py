@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import lind_inputs as li
+from oracle import dynamics as od
 from oracle import gradient as og
 from oracle import krylov as ok
 from oracle import lindblad as ol
@@ -440,3 +441,99 @@ def test_planted_resolvent_shift_is_caught():
     lam = g["lambda"]
     wrong = -ol.lyap_solve(G - 0.5 * lam * np.eye(2), ol.K_apply(Ls, rho), lam)
     assert abs(wrong[0, 0] - g["RK_coefficient"] * rho[1, 1]) > 1e-3
+
+
+# --------------------------------------------------------------------------------------
+# resolvent and implicit Euler (oracle.dynamics)
+# --------------------------------------------------------------------------------------
+def test_resolvent_three_routes():
+    """(lambda - L)^{-1} B three ways: dense LU of the superoperator, the series of the resolvent
+    corollary (Lyapunov solves only), and right-preconditioned GMRES; lambda spans the three
+    shifts of the resolvent benchmark (lambda_max * 10^{0,-1,-2}, lambda_max = spectral radius)."""
+    for H, Ls in [li.random_dense(6, 2, seed=5), li.kerr_cavity(8)]:
+        n = H.shape[0]
+        lam_max = float(np.max(np.abs(ol.spectrum_dense(H, Ls))))
+        B = li.random_state(n, seed=9, hermitian=False)
+        for lam in [lam_max, lam_max / 10, lam_max / 100]:
+            X = od.resolvent_dense(H, Ls, lam, B)
+            res = lam * X - ol.lindblad_apply(H, Ls, X) - B
+            assert np.max(np.abs(res)) < 1e-11 * max(1, np.max(np.abs(B)))
+            terms = int(np.ceil(np.log(1e-15) / np.log(od.contraction_norm(H, Ls, lam)))) + 5
+            S = od.resolvent_series(H, Ls, lam, B, terms=min(terms, 20000))
+            assert np.max(np.abs(S - X)) < 1e-9 * np.max(np.abs(X))
+            Y = od.resolvent_gmres(H, Ls, lam, B, tol=1e-13)
+            assert np.max(np.abs(Y - X)) < 1e-9 * np.max(np.abs(X))
+
+
+def test_contraction_norm_footnote_and_brute_force():
+    """Left/right preconditioning footnote: n = 2, H = 0, L = sqrt(gamma)|0><1| gives
+    ||K R^S_lambda|| = gamma / (gamma + lambda); and the CP-map norm formula against the dual map
+    built column by column on a random system."""
+    g = 0.7
+    H, Ls = li.two_level_decay(g)
+    for lam in [0.01, 0.3, 2.0]:
+        assert abs(od.contraction_norm(H, Ls, lam) - g / (g + lam)) < 1e-13
+    H, Ls = li.random_dense(5, 3, seed=17)
+    G = ol.no_jump_generator(H, Ls)
+    for lam in [0.05, 1.0]:
+        KR = ol.superop_of_map(lambda X: ol.K_apply(Ls, ol.resolvent_S(G, X, lam)), 5)
+        dual_I = ol.hermitize(ol.unvec(KR.conj().T @ ol.vec(np.eye(5)), 5))
+        assert abs(od.contraction_norm(H, Ls, lam) - np.max(np.linalg.eigvalsh(dual_I))) < 1e-12
+        assert od.contraction_norm(H, Ls, lam) < 1
+
+
+def ie_two_level_closed_form(g, dt, k, rho0):
+    """Implicit Euler for L = sqrt(g)|0><1|, H = 0: rho_11 -> rho_11 / (1 + g dt),
+    rho_01 -> rho_01 / (1 + g dt / 2), trace kept."""
+    r = rho0.astype(np.complex128).copy()
+    p1 = r[1, 1] / (1 + g * dt) ** k
+    c = r[0, 1] / (1 + g * dt / 2) ** k
+    out = np.array([[1 - p1, c], [np.conj(c), p1]], dtype=np.complex128)
+    return out
+
+
+def test_implicit_euler_two_level_closed_form():
+    """eq. resolvent (implicit solver section) on the two-level decay, against the per-step
+    closed form, and its first-order agreement with exp(t L) (scipy.linalg.expm)."""
+    import scipy.linalg as sl
+    g, dt = 0.8, 0.25
+    H, Ls = li.two_level_decay(g)
+    plus = 0.5 * np.array([[1, 1], [1, 1]], dtype=np.complex128)
+    for rho0 in [np.diag([0.0, 1.0]).astype(np.complex128), plus]:
+        states = od.implicit_euler_dense(H, Ls, rho0, dt, 6)
+        for k, r in enumerate(states, 1):
+            assert np.allclose(r, ie_two_level_closed_form(g, dt, k, rho0), atol=1e-14)
+    H, Ls = li.kerr_cavity(6)
+    rho0 = li.random_state(6, seed=4)
+    t = 0.5
+    ex = ol.unvec(sl.expm(t * ol.superop_dense(H, Ls)) @ ol.vec(rho0), 6)
+    errs = []
+    for steps in [50, 100, 200]:
+        errs.append(np.max(np.abs(od.implicit_euler_dense(H, Ls, rho0, t / steps, steps)[-1] - ex)))
+    assert errs[0] / errs[1] > 1.8 and errs[1] / errs[2] > 1.8  # first order in dt
+    assert errs[2] < 1e-2
+
+
+def test_implicit_euler_trace_hermiticity_and_steady_limit():
+    """Each step keeps the trace and Hermiticity (L is trace-annihilating and Hermiticity-
+    preserving); long steps converge to the steady state (the fixed point of (I - dt L)^{-1})."""
+    H, Ls, _ = li.workload("kerr32")
+    H, Ls = H[:12, :12], [L[:12, :12] for L in Ls]
+    rho0 = li.random_state(12, seed=6)
+    states = od.implicit_euler_dense(H, Ls, rho0, 0.3, 5)
+    for r in states:
+        assert abs(np.trace(r) - np.trace(rho0)) < 1e-13
+        assert np.max(np.abs(r - r.conj().T)) < 1e-13
+    far = od.implicit_euler_dense(H, Ls, rho0, 50.0, 60)[-1]
+    assert ol.trace_distance(far / np.trace(far), ol.steady_state_dense(H, Ls)) < 1e-10
+
+
+def test_planted_explicit_euler_sign_is_caught():
+    """Plant (I + dt L) instead of (I - dt L) in a copy of the implicit Euler step: the two-level
+    closed form catches it."""
+    g, dt = 0.8, 0.25
+    H, Ls = li.two_level_decay(g)
+    rho0 = np.diag([0.0, 1.0]).astype(np.complex128)
+    A = np.eye(4, dtype=np.complex128) + dt * ol.superop_dense(H, Ls)
+    bad = ol.unvec(np.linalg.solve(A, ol.vec(rho0)), 2)
+    assert not np.allclose(bad, ie_two_level_closed_form(g, dt, 1, rho0), atol=1e-6)
