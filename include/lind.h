@@ -142,6 +142,27 @@ int lind_eigs(lind_ctx* ctx, int k, double mu_re, double mu_im, double tol, void
 int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double* expval, void* grad_H, void* grad_L,
                      void* rho_out, lind_info* info);
 
+/* X = (lambda - L)^{-1} B for Re(lambda) > 0 (Corollary "Resolvent of the Lindbladian") by
+   GMRES right-preconditioned with the no-jump resolvent R^S_lambda = (lambda - S)^{-1}
+   (eq. right-precond-identity; the contraction theorem bounds ||K R^S_lambda|| < 1), with a
+   recycled subspace kept across restarts.  The operator lambda - L is applied in FP64, the
+   preconditioner in the context's precision.  Stops when ||B - (lambda - L) X||_F <= tol ||B||_F.
+   B, X: device n x n complex128 (may not alias).  info (may be NULL): n_inner = GMRES steps,
+   n_phi = preconditioner applications, n_restarts = cycles, err_est = final relative residual,
+   resid_max = its max-norm.  Errors: EINVAL (Re(lambda) <= 0, tol <= 0), ENOCONV (X holds the
+   last iterate). */
+int lind_resolve(lind_ctx* ctx, double lambda_re, double lambda_im, const void* B, void* X, double tol,
+                 lind_info* info);
+
+/* Implicit Euler (eq. resolvent of the implicit-solver section): rho_{k+1} = (I - dt L)^{-1} rho_k
+   = (1/dt) R^L_{1/dt} rho_k for k < steps, each step a lind_resolve-type solve at lambda = 1/dt to
+   relative residual tol, warm-started from rho_k; the recycled GMRES subspace is carried across
+   steps.  rho0, rho_out: device n x n complex128 (may alias: in-place stepping).  info:
+   n_restarts = steps done, n_inner = total GMRES steps, err_est = worst relative residual.
+   Errors: EINVAL (dt <= 0, steps < 0, tol <= 0), ENOCONV (a step missed tol or the time limit
+   was hit; rho_out holds the last completed state). */
+int lind_ie(lind_ctx* ctx, double dt, int steps, const void* rho0, void* rho_out, double tol, lind_info* info);
+
 /* Factorisation data (device pointers owned by the context, valid until lind_destroy):
    which: 0 = G, 1 = T (Schur factor), 2 = Z (Schur vectors), 3 = U (unit-column eigenvectors),
    4 = V = U^{-+}, 5 = s (n eigenvalues of G).  Returns NULL if not available. */

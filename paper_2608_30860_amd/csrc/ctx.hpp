@@ -155,13 +155,13 @@ int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std:
                    std::vector<cplx>& Y);
 int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst);
 int steady_state_impl(lind_ctx* X, double tol, const zd* rho0, zd* rho_out, lind_info* info);
-// right-preconditioned GMRES(m) with a recycled subspace of up to kdef vectors (GCRO-DR), carried in
-// rec across cycles and across solves with the same operators A and P (P may be null: identity).
+// right-preconditioned flexible GMRES(m) with a recycled subspace of up to kdef vectors (GCRO-DR),
+// carried in rec across cycles and across solves with the same operator A (P may be null: identity).
 // m <= 64 for recycling; longer cycles (up to kMaxLong) run without it.  x_zero: start from x = 0.
 int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const std::function<int(const zd*, zd*)>* P,
               const zd* b, zd* x, bool x_zero, int m, int kdef, int max_cycles, double rtol, double atol,
               Recycle& rec, GmresResult& res, double t_deadline);
 // longest cycle (<= want) whose basis fits the HBM budget; release a long basis after use
-int long_cycle_len(Ctx& c, int want);
+int long_cycle_len(Ctx& c, int want, bool flexible);
 void release_long_basis(Ctx& c);
 }  // namespace lindx

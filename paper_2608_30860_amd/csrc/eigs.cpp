@@ -398,7 +398,7 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
   if (!gr.converged && !gr.stagnated) {
     const double r0 = gr.resid0;
     GmresResult g2;
-    const int ml = long_cycle_len(c, kMaxLong);
+    const int ml = long_cycle_len(c, kMaxLong, true);
     int rc2 = gmres_rec(X, Aop, &Pop, rhs, wadj, false, ml, 0, 4, rtol_adj, 0.0, c.rec, g2, 0.0);
     release_long_basis(c);
     TRY(rc2);

@@ -1,15 +1,19 @@
 // Right-preconditioned GMRES with Krylov subspace recycling (GCRO-DR: Parks, de Sturler, Mackey,
 // Johnson and Maiti, SIAM J. Sci. Comput. 2006), the inner solver of the linear-solver section:
-// after every cycle a harmonic-Ritz subspace (U, C) with (A P) U = C, C orthonormal, is kept and
+// after every cycle a harmonic-Ritz subspace (U, C) with A U = C, C orthonormal, is kept and
 // carried into the next cycle and into later solves with the same operator.
+// The preconditioned directions z_j = P(v_j) are stored (flexible form): the solution is updated
+// from them directly, so a preconditioner applied in reduced precision (an operator that is
+// linear only up to its rounding) limits neither the residual recurrence nor the final accuracy,
+// and U lives in the solution space, tied to A alone.
 //
 // Notation for one cycle with k recycled vectors and j Arnoldi steps (s = k + j):
 //   V^ = [C, v_0 .. v_j]        (s + 1 orthonormal vectors, stored contiguously in the K2 basis)
-//   W^ = [U D, v_0 .. v_{j-1}]  (D = diag(1 / ||u_i||))
-//   (A P) W^ = V^ Gbar,  Gbar = [[D, B], [0, Hbar]]  ((s + 1) x s)
+//   W^ = [U D, z_0 .. z_{j-1}]  (D = diag(1 / ||u_i||), z_i = P(v_i), or v_i without P)
+//   A W^ = V^ Gbar,  Gbar = [[D, B], [0, Hbar]]  ((s + 1) x s)
 // The least-squares problem min || beta e_{k+1} - Gbar z || decouples: the U block of z zeroes the
 // first k rows, so the residual estimate is the one of plain GMRES on Hbar.  The new recycle space
-// is spanned by the harmonic Ritz vectors of (A P) for the smallest harmonic Ritz values:
+// is spanned by the harmonic Ritz vectors for the smallest harmonic Ritz values:
 //   Gbar^H Gbar p = theta Gbar^H V^^H W^ p,
 // rewritten with Gbar = Qg Rg as the standard problem Rg^{-1} Qg^H (V^^H W^) p = (1/theta) p.
 // All vector work (Gram-Schmidt, the tall-skinny products of the update) runs on the device in
@@ -110,13 +114,13 @@ int rows_combine(Ctx& c, int M, int K, const zd* Acoef, const zd* Vrows, zd* Cou
 
 }  // namespace
 
-int long_cycle_len(Ctx& c, int want) {
+int long_cycle_len(Ctx& c, int want, bool flexible) {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
   const double vec = 16.0 * (double)c.n2;
-  // at most half of the free HBM and 32 GiB for the basis
+  // at most half of the free HBM and 32 GiB for the basis (and the preconditioned directions)
   const double budget = std::min(0.5 * (double)fr + (double)c.K2cap * vec, 32.0 * (1ull << 30));
-  const int fit = (int)std::max(0.0, budget / vec) - 3;
+  const int fit = ((int)std::max(0.0, budget / vec) - 3) / (flexible ? 2 : 1);
   return std::max(3, std::min({want, kMaxLong, fit}));
 }
 
@@ -187,22 +191,22 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
   const long long n2 = c.n2;
   m = std::max(3, std::min(m, kMaxLong));
   kdef = (m > 64) ? 0 : std::max(0, std::min(kdef, m - 2));
-  TRY(c.ensure_krylov(2, m + 3));
+  const bool flex = P != nullptr;
+  TRY(c.ensure_krylov(2, flex ? 2 * m + 3 : m + 3));
   if (kdef > 0) TRY(rec.ensure(c, kdef));
   if (rec.k > kdef) rec.k = 0;  // a space from a larger setting is dropped, not truncated
   if (!rec.coef) TRY(c.alloc(&rec.coef, 3 * 64 * 72));
   if (!rec.hb) TRY(c.alloc(&rec.hb, 2 * (kMaxLong + 1) + 8));
   zd* Vh = c.K2;                          // slots 0 .. m: [C, v_0 .. v_j]
   zd* tmp = Vh + (long long)(m + 1) * n2;  // scratch slot
-  zd* dy = Vh + (long long)(m + 2) * n2;   // correction in the preconditioned space
+  zd* dy = Vh + (long long)(m + 2) * n2;   // correction of x accumulated over the cycle
+  zd* Zb = flex ? Vh + (long long)(m + 3) * n2 : nullptr;  // z_j = P(v_j), slots m + 3 ..
+
   // device scalars of a step with nb basis vectors: [norm | h (first pass, nb) | h (second pass, nb)]
   zd* nrmdev = rec.hb;
   zd* hdev = rec.hb + 1;
   zd* crdev = c.dsc + 160;
-  auto applyP = [&](const zd* in, zd* out) -> int {
-    if (P) return (*P)(in, out);
-    return copy(in, out, n2, c.st);
-  };
+
   double bnorm = 0;
   TRY(op_nrm(c, b, &bnorm));
   if (x_zero) TRY(fill_zero(x, n2 * (long long)sizeof(zd), c.st));
@@ -229,7 +233,7 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
     if (cyc > 0) {
       // rounding floor: the previous cycle's recurrence reached the target but the true residual
       // did not (twice), or restarts no longer reduce the true residual at all (three times)
-      if (prev_est_hit) ++floor_hits;
+      if (prev_est_hit && beta > 0.5 * prev_beta) ++floor_hits;
       if (beta > 0.999 * prev_beta) ++slow;
       else slow = 0;
       if (floor_hits >= 2 || slow >= 3) { res.stagnated = true; break; }
@@ -248,8 +252,7 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
       for (int i = 0; i < kc; ++i) cr[i] = cplx(c.hsc[i].x, c.hsc[i].y);
       TRY(op_nrm(c, r, &beta));
       if (!(beta > 0)) {
-        TRY(applyP(dy, tmp));
-        TRY(axpby(zmk(1, 0), tmp, zmk(1, 0), x, n2, c.st));
+        TRY(axpby(zmk(1, 0), dy, zmk(1, 0), x, n2, c.st));
         res.cycles = cyc + 1;
         continue;
       }
@@ -266,9 +269,10 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
     for (int j = 0; j < mm; ++j) {
       zd* vj = Vh + (long long)(kc + j) * n2;
       zd* w = Vh + (long long)(kc + j + 1) * n2;
-      if (P) {
-        TRY((*P)(vj, tmp));
-        TRY(A(tmp, w));
+      if (flex) {
+        zd* zj = Zb + (long long)j * n2;
+        TRY((*P)(vj, zj));
+        TRY(A(zj, w));
       } else {
         TRY(A(vj, w));
       }
@@ -317,7 +321,7 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
       if (t_deadline > 0 && now_s() > t_deadline) break;
     }
     // z_V from the triangular system; the U block of z is -D^{-1} B z_V, so that
-    // dy += V z_V - U (B z_V)
+    // dy += Z z_V - U (B z_V)   (Z = V without a preconditioner)
     std::vector<cplx> z(jd);
     for (int i = jd - 1; i >= 0; --i) {
       cplx acc = g[i];
@@ -332,29 +336,36 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
       TRY(multi_axpy(rec.U, n2, kc, crdev, dy, n2, 1, 1.0, c.st));
     }
     TRY(upload(c, z, hdev));
-    TRY(maxpy(c, Vh + (long long)kc * n2, jd, hdev, dy, kc > 0 ? 1 : 0, 1.0));
-    TRY(applyP(dy, tmp));
-    TRY(axpby(zmk(1, 0), tmp, zmk(1, 0), x, n2, c.st));
+    zd* Zpart = flex ? Zb : Vh + (long long)kc * n2;
+    TRY(maxpy(c, Zpart, jd, hdev, dy, kc > 0 ? 1 : 0, 1.0));
+    TRY(axpby(zmk(1, 0), dy, zmk(1, 0), x, n2, c.st));
     res.cycles = cyc + 1;
     res.resid = est;
     prev_est_hit = est <= target;
 
-    // ---- recycle update: harmonic Ritz vectors of A P over span(W^) ----
+    // ---- recycle update: harmonic Ritz vectors over span(W^) ----
+    // Without a preconditioner W^ and V^ live in one space and F = V^^H W^ is formed exactly.  In
+    // the flexible form the harmonic Ritz problem is posed on the orthonormal [C, v_0 ..], i.e.
+    // F = [I; 0] (as in flexible GMRES with deflated restarting); any selection keeps A U = C exact.
     const int s = kc + jd;
     int knew = std::min(kdef, s - 1);
     if (kdef == 0 || breakdown || knew < 1) continue;
     std::vector<double> dn(kc, 1.0);
-    std::vector<cplx> VU;  // (s + 1) x kc: V^^H U
+    std::vector<cplx> VU;  // (s + 1) x kc: V^^H U (exact form only)
     if (kc > 0) {
       for (int i = 0; i < kc; ++i) TRY(nrm2(rec.U + (long long)i * n2, n2, (double*)(c.dsc + 200 + i), c.dscr, c.st));
-      TRY(rec.cross(c, rec.U, kc, Vh, s + 1, rec.coef));  // T[a][b] = <V^_b, u_a>
+      if (!flex) TRY(rec.cross(c, rec.U, kc, Vh, s + 1, rec.coef));  // T[a][b] = <V^_b, u_a>
       TRY(c.fetch(c.dsc + 200, sizeof(zd) * kc));
       for (int i = 0; i < kc; ++i) dn[i] = ((const double*)(c.hsc + i))[0];
-      TRY(c.fetch(rec.coef, sizeof(zd) * kc * (s + 1)));
       VU.assign((size_t)(s + 1) * kc, 0.0);
-      for (int a = 0; a < kc; ++a)
-        for (int bq = 0; bq <= s; ++bq)
-          VU[(size_t)bq * kc + a] = std::conj(cplx(c.hsc[(size_t)a * (s + 1) + bq].x, c.hsc[(size_t)a * (s + 1) + bq].y));
+      if (flex) {
+        for (int a = 0; a < kc; ++a) VU[(size_t)a * kc + a] = dn[a];  // F's U block becomes I
+      } else {
+        TRY(c.fetch(rec.coef, sizeof(zd) * kc * (s + 1)));
+        for (int a = 0; a < kc; ++a)
+          for (int bq = 0; bq <= s; ++bq)
+            VU[(size_t)bq * kc + a] = std::conj(cplx(c.hsc[(size_t)a * (s + 1) + bq].x, c.hsc[(size_t)a * (s + 1) + bq].y));
+      }
     }
     for (int i = 0; i < kc; ++i)
       if (!(dn[i] > 0) || !std::isfinite(dn[i])) { rec.k = 0; knew = 0; }
@@ -439,7 +450,7 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
       TRY(rows_combine(c, keep, kc, dAu, rec.U, rec.Un, n2, 0));
     }
     TRY(upload(c, Av, dAv));
-    TRY(rows_combine(c, keep, jd, dAv, Vh + (long long)kc * n2, rec.Un, n2, kc > 0 ? 1 : 0));
+    TRY(rows_combine(c, keep, jd, dAv, Zpart, rec.Un, n2, kc > 0 ? 1 : 0));
     std::swap(rec.U, rec.Un);
     rec.k = keep;
   }

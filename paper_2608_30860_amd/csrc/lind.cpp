@@ -566,7 +566,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
       inf.n_inner += gr.iters;
       if (!gr.converged && !gr.stagnated && !long_mode) {
         long_mode = true;
-        m_ref = long_cycle_len(c, 256);
+        m_ref = long_cycle_len(c, 256, false);
       }
       TRY(op_sinv(c, X->zetaB, X->delB, cplx(0, 0), p, false));
       TRY(axpby(zmk(-1, 0), X->delB, zmk(1, 0), X->rhoB, n2, c.st));

@@ -21,7 +21,8 @@ LIND_OK, LIND_EINVAL, LIND_ESINGULAR, LIND_ENOCONV, LIND_EDEVICE, LIND_ENOMEM = 
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 ROUTE = {"auto": 0, "eig": 1, "schur": 2}
 SYMBOLS = ["lind_default_opts", "lind_create", "lind_destroy", "lind_apply", "lind_apply_adjoint", "lind_sinv",
-           "lind_phi", "lind_steady_state", "lind_eigs", "lind_steady_grad", "lind_factor_ptr", "lind_last_error"]
+           "lind_phi", "lind_steady_state", "lind_eigs", "lind_steady_grad", "lind_resolve", "lind_ie",
+           "lind_factor_ptr", "lind_last_error"]
 
 
 class LindOpts(ctypes.Structure):
@@ -77,6 +78,10 @@ def load_library(path: str = LIB_PATH):
     lib.lind_eigs.restype = ci
     lib.lind_steady_grad.argtypes = [vp, vp, cd, ctypes.POINTER(cd), vp, vp, vp, ctypes.POINTER(LindInfo)]
     lib.lind_steady_grad.restype = ci
+    lib.lind_resolve.argtypes = [vp, cd, cd, vp, vp, cd, ctypes.POINTER(LindInfo)]
+    lib.lind_resolve.restype = ci
+    lib.lind_ie.argtypes = [vp, cd, ci, vp, vp, cd, ctypes.POINTER(LindInfo)]
+    lib.lind_ie.restype = ci
     lib.lind_factor_ptr.argtypes = [vp, ci]
     lib.lind_factor_ptr.restype = vp
     lib.lind_last_error.argtypes = [vp]
@@ -230,6 +235,31 @@ class Lindblad:
         if rc:
             self._err(rc)
         return val.value, gH, gL[: self.d], rho, info.as_dict()
+
+    def resolve(self, lam, B, tol=1e-12, raise_on_noconv=True):
+        """X = (lam - L)^{-1} B, Re(lam) > 0 (lind_resolve).  Returns (X, info)."""
+        _check_mat(B, self.n, "B")
+        X = self._new()
+        info = LindInfo()
+        lam = complex(lam)
+        rc = self.lib.lind_resolve(self.h, lam.real, lam.imag, _ptr(B), _ptr(X), tol, ctypes.byref(info))
+        if rc and not (rc == LIND_ENOCONV and not raise_on_noconv):
+            self._err(rc)
+        d = info.as_dict()
+        d["status"] = rc
+        return X, d
+
+    def implicit_euler(self, dt, steps, rho0, tol=1e-12, raise_on_noconv=True):
+        """rho_steps of rho_{k+1} = (I - dt L)^{-1} rho_k (lind_ie).  Returns (rho, info)."""
+        _check_mat(rho0, self.n, "rho0")
+        out = self._new()
+        info = LindInfo()
+        rc = self.lib.lind_ie(self.h, float(dt), int(steps), _ptr(rho0), _ptr(out), tol, ctypes.byref(info))
+        if rc and not (rc == LIND_ENOCONV and not raise_on_noconv):
+            self._err(rc)
+        d = info.as_dict()
+        d["status"] = rc
+        return out, d
 
     def factor(self, which):
         """Device tensors viewing the factorisation: 'G', 'T', 'Z', 'U', 'V' (n x n) or 's' (n)."""
