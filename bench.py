@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the resolvent / implicit Euler measurement")
     ap.add_argument("--phi-loop", type=int, default=10, help="Phi applications per precision in the pure loop")
     ap.add_argument("--kernel-only", default=None, help="profiling mode: only run Phi loops in this precision")
     args = ap.parse_args()
@@ -282,6 +283,39 @@ def main():
                                                              "resid_trace_bound", "phi_loop_rate",
                                                              "trace_distance_to_mixed"]}
 
+    # resolvent benchmark of the paper (after the timed region): (lambda - L) X = I/n at
+    # lambda = lambda_max * 10^{0,-1,-2}, lambda_max the spectral radius of L by power iteration
+    # (off the clock), plus implicit Euler steps at dt = 1/lambda_max * 100
+    extras = None
+    if not args.no_extras:
+        gen = torch.Generator(device="cpu").manual_seed(7)
+        x = torch.complex(torch.randn(n, n, generator=gen, dtype=torch.float64),
+                          torch.randn(n, n, generator=gen, dtype=torch.float64)).to(dev)
+        lam_max = 0.0
+        for _ in range(30):
+            y = model.apply(x)
+            lam_max = float(torch.linalg.norm(y) / torch.linalg.norm(x))
+            x = y / torch.linalg.norm(y)
+        B = torch.eye(n, dtype=torch.complex128, device=dev) / n
+        shifts = []
+        for f in [1.0, 0.1, 0.01]:
+            model.resolve(lam_max * f, B, tol=args.tol)  # warm (allocations)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, rinfo = model.resolve(lam_max * f, B, tol=args.tol)
+            torch.cuda.synchronize()
+            shifts.append({"lambda": lam_max * f, "time_s": time.perf_counter() - t0, "gmres_steps": rinfo["n_inner"],
+                           "rel_residual": rinfo["err_est"]})
+        dt = 100.0 / lam_max
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho_ie, iinfo = model.implicit_euler(dt, 10, B, tol=args.tol)
+        torch.cuda.synchronize()
+        extras = {"resolve": {"rhs": "I/n", "tol": args.tol, "lambda_max_estimate": lam_max, "shifts": shifts},
+                  "implicit_euler": {"dt": dt, "steps": 10, "time_s": time.perf_counter() - t0,
+                                     "gmres_steps": iinfo["n_inner"], "worst_rel_residual": iinfo["err_est"]}}
+        log(f"[bench] extras {extras}")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -296,7 +330,7 @@ def main():
                       "step": "one steady-state solve (Arnoldi on Phi + FP64 refinement); factorisation once, "
                               "reported in time_to_tol", "parallelism": "single GPU"},
            "time_to_tol": t_to_tol, "roofline": roof, "kernels": other, "cpu_baseline": cpu,
-           "create_s": t_create}
+           "create_s": t_create, "resolvent": extras}
     model.close()
     print(json.dumps(out), flush=True)
 
