@@ -189,6 +189,17 @@ class EigResolvent:
         return float(np.linalg.cond(Un))
 
 
+def gauge_shift(H, Ls, c):
+    """Remark "Non-uniqueness of the decomposition", eq. lindblad_gauge:
+    Lt_j = L_j + c_j I,  Ht = H + (1/2i) sum_j (conj(c_j) Lt_j - c_j Lt_j^+).
+    The pair (Ht, Lt) defines the same Lindbladian with another no-jump / jump split."""
+    n = H.shape[0]
+    I = np.eye(n, dtype=np.complex128)
+    Lt = [L + cj * I for L, cj in zip(Ls, c)]
+    Ht = H.astype(np.complex128) + sum((np.conj(cj) * L - cj * dag(L)) for L, cj in zip(Lt, c)) / 2j
+    return Ht, Lt
+
+
 # ----------------------------------------------------------------------------
 # dense superoperators (column stacking)
 # ----------------------------------------------------------------------------

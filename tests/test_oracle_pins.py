@@ -537,3 +537,61 @@ def test_planted_explicit_euler_sign_is_caught():
     A = np.eye(4, dtype=np.complex128) + dt * ol.superop_dense(H, Ls)
     bad = ol.unvec(np.linalg.solve(A, ol.vec(rho0)), 2)
     assert not np.allclose(bad, ie_two_level_closed_form(g, dt, 1, rho0), atol=1e-6)
+
+
+# --------------------------------------------------------------------------------------
+# gauge-shifted split (Remark "Non-uniqueness of the decomposition")
+# --------------------------------------------------------------------------------------
+def test_gauge_shift_keeps_the_lindbladian():
+    """Every shift c gives an admissible split of the same L (the remark's direct computation):
+    the dense superoperators agree, and G changes by -B - sum|c_j|^2/2 with B = sum conj(c_j) L_j."""
+    H, Ls = li.random_dense(5, 3, seed=23)
+    c = [0.3 - 0.2j, -1.1 + 0.4j, 0.05j]
+    Ht, Lt = ol.gauge_shift(H, Ls, c)
+    assert np.allclose(Ht, Ht.conj().T, atol=1e-15)
+    assert np.allclose(ol.superop_dense(Ht, Lt), ol.superop_dense(H, Ls), atol=1e-13)
+    G, Gt = ol.no_jump_generator(H, Ls), ol.no_jump_generator(Ht, Lt)
+    B = sum(np.conj(cj) * L for L, cj in zip(Ls, c))
+    assert np.allclose(Gt, G - B - 0.5 * sum(abs(cj) ** 2 for cj in c) * np.eye(5), atol=1e-13)
+
+
+def test_gauge_three_level_golden():
+    """Conclusion: on the three-level example, c = (1, 0, 0) leaves 1 simple in the shifted Phi and
+    brings every other eigenvalue to modulus <= sqrt(3/8), the pair becoming 1/2 +- i/(2 sqrt 2)."""
+    g = read_golden("three_level_gauge.txt")
+    H, Ls = li.three_level_cyclic()
+    c = np.array(g["gauge_re"]) + 1j * np.array(g["gauge_im"])
+    Ht, Lt = ol.gauge_shift(H, Ls, c)
+    Gt = ol.no_jump_generator(Ht, Lt)
+    P = ol.superop_of_map(lambda X: ol.phi_apply(Gt, Lt, X), 3)
+    ev = np.linalg.eigvals(P)
+    assert np.sum(np.abs(ev - 1) < 1e-9) == 1
+    others = ev[np.abs(ev - 1) >= 1e-9]
+    assert np.max(np.abs(others)) <= g["bound"] + 1e-12
+    for re, im in zip(g["pair_re"], g["pair_im"]):
+        assert np.min(np.abs(ev - (re + 1j * im))) < 1e-12
+    assert abs(g["bound"] - np.sqrt(3 / 8)) < 1e-15
+
+
+def test_gauge_repairs_singular_split():
+    """Conclusion: the shifted S is singular only if some psi has L_j psi = -c_j psi for all j; the
+    two-level decay (Theorem 1, first case: S singular at c = 0) is repaired by any c != 0 and its
+    steady state |0><0| comes out of the shifted Phi-Arnoldi."""
+    H, Ls = li.two_level_decay(1.0)
+    G = ol.no_jump_generator(H, Ls)
+    assert np.min(np.abs(np.linalg.eigvals(G).real)) < 1e-14
+    Ht, Lt = ol.gauge_shift(H, Ls, [0.5])
+    Gt = ol.no_jump_generator(Ht, Lt)
+    assert np.min(np.abs(np.linalg.eigvals(Gt).real)) > 0.1
+    rho = ok.steady_state_phi(Ht, Lt, tol=1e-12, m=3)
+    assert np.allclose(rho, np.diag([1.0, 0.0]), atol=1e-12)
+
+
+def test_planted_gauge_sign_is_caught():
+    """Plant the wrong sign of the Hamiltonian correction in a copy of gauge_shift."""
+    H, Ls = li.random_dense(4, 2, seed=29)
+    c = [0.4 + 0.1j, -0.3j]
+    n = 4
+    Lt = [L + cj * np.eye(n) for L, cj in zip(Ls, c)]
+    bad_H = H - sum((np.conj(cj) * L - cj * L.conj().T) for L, cj in zip(Lt, c)) / 2j
+    assert not np.allclose(ol.superop_dense(bad_H, Lt), ol.superop_dense(H, Ls), atol=1e-6)
