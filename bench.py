@@ -256,6 +256,22 @@ def main():
                           "trace_distance_to_mixed": float(0.5 * ev.abs().sum())}
             log(f"[bench] {p}: {compare[p]}")
             mp.close()
+        # the same steady state by preconditioned GMRES (method option), same precision
+        log("[bench] comparison: steady state by preconditioned GMRES")
+        mg = Lindblad(Ht, Lt, prec=args.prec, method="gmres")
+        mg.steady_state(args.tol)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rg = mg.steady_state(args.tol)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        diff = (rg.rho - rho_mixed)
+        ev = torch.linalg.eigvalsh(0.5 * (diff + diff.conj().T))
+        compare["gmres_method"] = {"time_to_tol_iteration_s": tg, "gmres_steps": rg.info["n_inner"],
+                                   "resid_trace_bound": rg.info["resid_trace"],
+                                   "trace_distance_to_mixed": float(0.5 * ev.abs().sum())}
+        log(f"[bench] gmres method: {compare['gmres_method']}")
+        mg.close()
     # pure Phi loop of the benchmarked precision
     x = xi.clone()
     torch.cuda.synchronize()
@@ -278,6 +294,8 @@ def main():
                             "trace_distance_to_mixed": f["trace_distance_to_mixed"]}
         t_to_tol["speedup_iteration_fp64_over_mixed"] = f["time_to_tol_iteration_s"] / it_mixed
         t_to_tol["speedup_total_fp64_over_mixed"] = t_to_tol["fp64"]["total_s"] / t_to_tol["mixed"]["total_s"]
+    if "gmres_method" in compare:
+        t_to_tol["gmres_method"] = compare["gmres_method"]
     if "fp32" in compare:
         t_to_tol["fp32"] = {k: compare["fp32"][k] for k in ["time_to_tol_iteration_s", "t_factor_s", "n_phi",
                                                              "resid_trace_bound", "phi_loop_rate",

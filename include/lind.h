@@ -50,6 +50,10 @@ enum { LIND_PREC_FP64 = 0, LIND_PREC_FP32 = 1, LIND_PREC_BF16X3 = 2 };
 /* Lyapunov backend (Section A.1): eigenbasis transform + elementwise divide, or Schur form +
    triangular Sylvester (Bartels-Stewart).  AUTO picks EIG when kappa_2(U) <= kappa_max. */
 enum { LIND_ROUTE_AUTO = 0, LIND_ROUTE_EIG = 1, LIND_ROUTE_SCHUR = 2 };
+/* steady-state method: Algorithm "Steady state as the fixed point of Phi" (Arnoldi on Phi, then
+   FP64 refinement) or Algorithm "Steady state via preconditioned GMRES" (the deflated system
+   L~_eta rho = eta I, eq. steady_state_linear_problem, right-preconditioned by Precond(., 0, eta)) */
+enum { LIND_METHOD_PHI_ARNOLDI = 0, LIND_METHOD_GMRES = 1 };
 
 typedef struct {
   int prec;             /* LIND_PREC_*                                    default FP64        */
@@ -62,6 +66,11 @@ typedef struct {
   double eta;           /* deflation constant (eq. steady_state_linear_problem), default 1.0 */
   double time_limit_s;  /* wall-clock cap per solver call, <= 0: none     default 0           */
   void* stream;         /* hipStream_t, NULL = default stream                                 */
+  int method;           /* LIND_METHOD_* for lind_steady_state (and the state of steady_grad), default PHI_ARNOLDI */
+  const double* gauge;  /* HOST, NULL or 2d doubles (re, im) of c_j: the split uses L_j + c_j I and
+                           H + (1/2i) sum_j (conj(c_j)(L_j + c_j) - c_j (L_j + c_j)^+) (Remark
+                           "Non-uniqueness of the decomposition", eq. lindblad_gauge); L itself is
+                           unchanged.  Read by lind_create only.               default NULL        */
 } lind_opts;
 
 typedef struct {

@@ -44,6 +44,9 @@ struct Ctx {
 
   // FP64 operator data
   zd *H = nullptr, *L = nullptr, *G = nullptr, *T = nullptr, *Z = nullptr, *U = nullptr, *V = nullptr;
+  // gauge-shifted split: H, L hold the shifted operators; L0 the given jump operators (gradients)
+  zd* L0 = nullptr;
+  std::vector<cplx> gauge;
   zd *s = nullptr, *sbar = nullptr;
   zd *Lt = nullptr;    // L_j U (eigen route) or L_j Z (Schur route), stacked d x n x n
   zd *Tadj = nullptr;  // J T^H J (upper triangular) for the adjoint Schur solve
@@ -155,6 +158,10 @@ int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std:
                    std::vector<cplx>& Y);
 int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst);
 int steady_state_impl(lind_ctx* X, double tol, const zd* rho0, zd* rho_out, lind_info* info);
+// Algorithm "Steady state via preconditioned GMRES" (method LIND_METHOD_GMRES)
+int steady_state_gmres(lind_ctx* X, double tol, const zd* rho0, zd* rho_out, lind_info* info);
+// rho <- herm(rho)/Tr; FP64 residual L(rho) into resB; its norms (colsum bound, max, Frobenius)
+int finish_state(lind_ctx* X, zd* rho, double* colsum, double* mx, double* fro, cplx* tr_before);
 // right-preconditioned flexible GMRES(m) with a recycled subspace of up to kdef vectors (GCRO-DR),
 // carried in rec across cycles and across solves with the same operator A (P may be null: identity).
 // m <= 64 for recycling; longer cycles (up to kMaxLong) run without it.  x_zero: start from x = 0.

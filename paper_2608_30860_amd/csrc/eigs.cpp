@@ -414,12 +414,14 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
     TRY(op_gemm(c, PREC_F64, n, n, n, wadj, n, OP_N, rho, n, OP_N, grad_H, n, cplx(0, -1), 1));
   }
   if (grad_L && d > 0) {
+    // derivatives with respect to the jump operators as given (a gauge shift leaves L unchanged)
+    const zd* Lg = c.L0 ? c.L0 : c.L;
     zd* M = X->xiB;
     TRY(op_gemm(c, PREC_F64, n, n, n, rho, n, OP_N, wadj, n, OP_N, M, n, one, 0));
     TRY(op_gemm(c, PREC_F64, n, n, n, wadj, n, OP_N, rho, n, OP_N, M, n, one, 1));
     // grad_L = L M (stacked), then grad_L_j -= 2 w (L_j rho)
-    TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, M, n, OP_N, grad_L, n, one, 0));
-    TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, rho, n, OP_N, c.Ys, n, one, 0));
+    TRY(op_gemm(c, PREC_F64, d * n, n, n, Lg, n, OP_N, M, n, OP_N, grad_L, n, one, 0));
+    TRY(op_gemm(c, PREC_F64, d * n, n, n, Lg, n, OP_N, rho, n, OP_N, c.Ys, n, one, 0));
     for (int j = 0; j < d; ++j)
       TRY(op_gemm(c, PREC_F64, n, n, n, wadj, n, OP_N, c.Ys + (long long)j * n2, n, OP_N,
                   (zd*)grad_L + (long long)j * n2, n, cplx(-2, 0), 1));
@@ -445,5 +447,81 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
                   gr.resid / std::max(gr.resid0, 1e-300), gr.iters);
     return c.fail(LIND_ENOCONV, msg);
   }
+  return LIND_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Algorithm "Steady state via preconditioned GMRES": the deflated system L~_eta rho = eta I
+// (eq. steady_state_linear_problem), written as -(L~_eta) rho = -eta I and right-preconditioned by
+// P_0 = Precond(., 0, eta) (Algorithm "Precond", eq. ShermanMorr), solved by the recycled flexible
+// GMRES(m) one cycle at a time from the warm start |0><0| (or rho0).  After every cycle the iterate is
+// hermitised and trace-normalised and its FP64 residual bound tested against tol; the best
+// iterate is returned.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_ket0bra0(zd* X, int n) {
+  const long long tot = (long long)n * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride)
+    X[t] = zmk(t == 0 ? 1.0 : 0.0, 0.0);
+}
+
+int lindx::steady_state_gmres(lind_ctx* X, double tol, const zd* rho0, zd* rho_out, lind_info* info) {
+  Ctx& c = X->c;
+  const int n = c.n;
+  const long long n2 = c.n2;
+  const double t0 = now_s();
+  const double deadline = c.opts.time_limit_s > 0 ? t0 + c.opts.time_limit_s : 0.0;
+  const double eta = c.opts.eta;
+  TRY(ensure_solver_bufs(X));
+  lind_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.kappa_U = c.kappa;
+  inf.t_factor_s = c.t_factor;
+  inf.route_used = c.route;
+  Precond P;
+  TRY(make_precond(X, P, cplx(0, 0), eta, false));
+  std::function<int(const zd*, zd*)> Aop = [&](const zd* in, zd* out) -> int {
+    return apply_shifted_deflated(c, in, out, cplx(0, 0), eta, false);
+  };
+  std::function<int(const zd*, zd*)> Pop = [&](const zd* in, zd* out) -> int {
+    ++inf.n_phi;
+    return apply_precond(c, P, in, out, c.prec);
+  };
+  // right-hand side -eta I (zetaB) and the iterate (rhoB)
+  TRY(fill_zero(X->zetaB, n2 * (long long)sizeof(zd), c.st));
+  TRY(add_identity(X->zetaB, n, zmk(-eta, 0), c.st));
+  if (rho0) TRY(copy(rho0, X->rhoB, n2, c.st));
+  else hipLaunchKernelGGL(k_ket0bra0, dim3(1024), dim3(256), 0, c.st, X->rhoB, n);
+  const int m = c.opts.m;
+  const int k = std::max(0, std::min(m / 2, m - 2));
+  c.rec.reset();
+  double best = 1e300, best_max = 0;
+  bool converged = false;
+  for (int cyc = 0; cyc < c.opts.max_restarts; ++cyc) {
+    GmresResult gr;
+    TRY(gmres_rec(X, Aop, &Pop, X->zetaB, X->rhoB, false, m, k, 1, 1e-15, 0.0, c.rec, gr, deadline));
+    inf.n_inner += gr.iters;
+    ++inf.n_restarts;
+    // rho^ = herm(rho)/Tr rho, FP64 residual
+    TRY(copy(X->rhoB, X->delB, n2, c.st));
+    double colsum = 0, mx = 0, fro = 0;
+    TRY(finish_state(X, X->delB, &colsum, &mx, &fro, nullptr));
+    if (colsum < best) {
+      best = colsum;
+      best_max = mx;
+      TRY(copy(X->delB, rho_out, n2, c.st));
+    }
+    if (colsum <= tol) { converged = true; break; }
+    if (gr.stagnated && gr.cycles == 0) break;
+    if (deadline > 0 && now_s() > deadline) break;
+  }
+  c.rec.reset();
+  TRY(c.sync());
+  inf.resid_trace = best;
+  inf.resid_max = best_max;
+  inf.err_est = best;
+  inf.t_solve_s = now_s() - t0;
+  if (info) *info = inf;
+  if (!converged) return c.fail(LIND_ENOCONV, "steady state (GMRES): tolerance not reached (best iterate returned)");
   return LIND_OK;
 }

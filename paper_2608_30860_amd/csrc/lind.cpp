@@ -55,6 +55,8 @@ extern "C" void lind_default_opts(lind_opts* o) {
   o->eta = 1.0;
   o->time_limit_s = 0.0;
   o->stream = nullptr;
+  o->method = LIND_METHOD_PHI_ARNOLDI;
+  o->gauge = nullptr;
 }
 
 static int prec_of(int p) {
@@ -73,6 +75,27 @@ __global__ void k_fill_identity_scaled(zd* X, int n, double v) {
   long long stride = (long long)gridDim.x * blockDim.x;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride)
     X[t] = (t / n == t % n) ? zmk(v, 0) : zmk(0, 0);
+}
+
+// eq. lindblad_gauge: with Lt_j = L_j + c_j I (already applied to L),
+// H <- H + (1/2i) sum_j (conj(c_j) Lt_j - c_j Lt_j^+), elementwise
+__global__ void k_gauge_H(zd* H, const zd* Lt, const zd* cs, int n, int d) {
+  const long long tot = (long long)n * n;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    const long long a = t / n, b = t % n;
+    double sr = 0, si = 0;
+    for (int j = 0; j < d; ++j) {
+      const zd cj = cs[j];
+      const zd x = Lt[(long long)j * tot + a * n + b];   // Lt_j[a][b]
+      const zd y = Lt[(long long)j * tot + b * n + a];   // Lt_j[b][a]; (Lt_j^+)[a][b] = conj(y)
+      // conj(c) x - c conj(y)
+      sr += (cj.x * x.x + cj.y * x.y) - (cj.x * y.x + cj.y * y.y);
+      si += (cj.x * x.y - cj.y * x.x) - (cj.y * y.x - cj.x * y.y);
+    }
+    // (1/2i)(sr + i si) = si/2 - i sr/2
+    H[t] = zmk(H[t].x + 0.5 * si, H[t].y - 0.5 * sr);
+  }
 }
 
 static int count_nonfinite(Ctx& c, const zd* x, long long len, int* flag_dev, bool* bad) {
@@ -201,8 +224,8 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
   lind_default_opts(&o);
   if (opts) o = *opts;
   if (o.m < 4 || o.m > 64 || !(o.eta > 0) || o.prec < 0 || o.prec > 2 || o.route < 0 || o.route > 2 ||
-      o.max_restarts < 1 || o.refine_max < 0) {
-    g_create_err = "invalid options (m in [4, 64], eta > 0, prec/route enums, max_restarts >= 1)";
+      o.max_restarts < 1 || o.refine_max < 0 || o.method < 0 || o.method > 1) {
+    g_create_err = "invalid options (m in [4, 64], eta > 0, prec/route/method enums, max_restarts >= 1)";
     return LIND_EINVAL;
   }
   int dev = 0;
@@ -260,6 +283,36 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
     g_create_err = frc ? "device error while checking inputs" : "non-finite entries in H or L";
     return frc ? LIND_EDEVICE : LIND_EINVAL;
   }
+  if (o.gauge && d > 0) {
+    // keep the given L for the gradients, factorise the shifted split
+    std::vector<zd> cs(d);
+    for (int j = 0; j < d; ++j) {
+      cs[j] = zmk(o.gauge[2 * j], o.gauge[2 * j + 1]);
+      if (!std::isfinite(cs[j].x) || !std::isfinite(cs[j].y)) {
+        delete X;
+        g_create_err = "non-finite gauge shift";
+        return LIND_EINVAL;
+      }
+    }
+    zd* cdev = nullptr;
+    int grc = c.alloc(&c.L0, (size_t)d * n2) | c.alloc(&cdev, (size_t)d);
+    if (!grc && hipMemcpyAsync(c.L0, c.L, sizeof(zd) * (size_t)d * n2, hipMemcpyDeviceToDevice, c.st) != hipSuccess) grc = 1;
+    if (!grc && hipMemcpyAsync(cdev, cs.data(), sizeof(zd) * d, hipMemcpyHostToDevice, c.st) != hipSuccess) grc = 1;
+    for (int j = 0; j < d && !grc; ++j) grc = add_identity(c.L + (long long)j * n2, n, cs[j], c.st);
+    if (!grc) {
+      hipLaunchKernelGGL(k_gauge_H, dim3(1024), dim3(256), 0, c.st, c.H, (const zd*)c.L, (const zd*)cdev, n, d);
+      grc = hipGetLastError() != hipSuccess;
+    }
+    if (!grc) grc = c.sync();
+    if (grc) {
+      delete X;
+      g_create_err = "gauge shift failed";
+      return LIND_EDEVICE;
+    }
+    c.gauge.assign(d, cplx(0, 0));
+    for (int j = 0; j < d; ++j) c.gauge[j] = cplx(cs[j].x, cs[j].y);
+  }
+  c.opts.gauge = nullptr;  // host memory of the caller: not kept
   rc = ctx_factor(X);
   if (rc) {
     g_create_err = c.err.empty() ? "factorisation failed" : c.err;
@@ -415,7 +468,7 @@ int lindx::upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst) {
 }
 
 // rho <- hermitise, normalise (trace 1); res = L(rho); norms (colsum bound, max) to host
-static int finish_state(lind_ctx* X, zd* rho, double* colsum, double* mx, double* fro, cplx* tr_before) {
+int lindx::finish_state(lind_ctx* X, zd* rho, double* colsum, double* mx, double* fro, cplx* tr_before) {
   Ctx& c = X->c;
   TRY(hermitize(rho, c.n, 1, c.dsc + 900, c.dscr, c.st));
   if (tr_before) {
@@ -439,6 +492,7 @@ extern "C" int lind_steady_state(lind_ctx* ctx, double tol, const void* rho0, vo
 int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_out, lind_info* info) {
   lind_ctx* X = ctx;
   Ctx& c = X->c;
+  if (c.opts.method == LIND_METHOD_GMRES) return steady_state_gmres(X, tol, rho0, rho_out, info);
   const int n = c.n;
   const long long n2 = c.n2;
   const int m = c.opts.m;

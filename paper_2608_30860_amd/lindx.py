@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblindx.so")
 
 LIND_OK, LIND_EINVAL, LIND_ESINGULAR, LIND_ENOCONV, LIND_EDEVICE, LIND_ENOMEM = 0, -1, -2, -3, -4, -5
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+METHOD = {"phi_arnoldi": 0, "gmres": 1}
 ROUTE = {"auto": 0, "eig": 1, "schur": 2}
 SYMBOLS = ["lind_default_opts", "lind_create", "lind_destroy", "lind_apply", "lind_apply_adjoint", "lind_sinv",
            "lind_phi", "lind_steady_state", "lind_eigs", "lind_steady_grad", "lind_resolve", "lind_ie",
@@ -29,7 +30,7 @@ class LindOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("route", ctypes.c_int), ("kappa_max", ctypes.c_double),
                 ("m", ctypes.c_int), ("p", ctypes.c_int), ("max_restarts", ctypes.c_int),
                 ("refine_max", ctypes.c_int), ("eta", ctypes.c_double), ("time_limit_s", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("method", ctypes.c_int), ("gauge", ctypes.POINTER(ctypes.c_double))]
 
 
 class LindInfo(ctypes.Structure):
@@ -112,11 +113,12 @@ class Lindblad:
 
     H: (n, n) complex128 CUDA tensor; Ls: (d, n, n) complex128 CUDA tensor or a list of (n, n).
     Options mirror lind_opts: prec ('fp64' | 'fp32' | 'bf16x3'), route ('auto' | 'eig' | 'schur'),
-    kappa_max, m, p, max_restarts, refine_max, eta, time_limit_s.
+    kappa_max, m, p, max_restarts, refine_max, eta, time_limit_s, method ('phi_arnoldi' | 'gmres')
+    and gauge (None or d complex shifts c_j of the no-jump / jump split).
     """
 
     def __init__(self, H, Ls, prec="fp64", route="auto", kappa_max=1e3, m=30, p=0, max_restarts=200,
-                 refine_max=8, eta=1.0, time_limit_s=0.0, stream=None):
+                 refine_max=8, eta=1.0, time_limit_s=0.0, stream=None, method="phi_arnoldi", gauge=None):
         self.lib = load_library()
         if isinstance(Ls, (list, tuple)):
             Ls = torch.stack(list(Ls)) if len(Ls) else torch.zeros((0,) + tuple(H.shape), dtype=H.dtype, device=H.device)
@@ -133,6 +135,13 @@ class Lindblad:
         o.prec, o.route, o.kappa_max, o.m, o.p = PREC[prec], ROUTE[route], kappa_max, m, p
         o.max_restarts, o.refine_max, o.eta, o.time_limit_s = max_restarts, refine_max, eta, time_limit_s
         o.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        o.method = METHOD[method]
+        if gauge is not None:
+            cs = [complex(z) for z in gauge]
+            if len(cs) != self.d:
+                raise ValueError(f"gauge needs one shift per jump operator ({self.d})")
+            self._gauge = (ctypes.c_double * (2 * len(cs)))(*[v for z in cs for v in (z.real, z.imag)])
+            o.gauge = ctypes.cast(self._gauge, ctypes.POINTER(ctypes.c_double))
         self._opts = o
         h = ctypes.c_void_p()
         lptr = _ptr(Ls) if self.d else ctypes.c_void_p(0)
