@@ -134,7 +134,7 @@ def main():
         lib.lindx_gemm.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong,
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_longlong, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                   ctypes.c_int, ctypes.c_void_p]
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         lib.lindx_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]
         stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         if pk == 2:
@@ -152,7 +152,7 @@ def main():
             else:
                 rc = lib.lindx_gemm(pk, d * n, n, n, 1, ctypes.c_void_p(A.data_ptr()), n, 0, 0,
                                     ctypes.c_void_p(B.data_ptr()), n, 0, 0, ctypes.c_void_p(C.data_ptr()), n, 1.0, 0.0,
-                                    0, 0, stream)
+                                    0, 0, 0, stream)
             assert rc == 0
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -13,10 +13,12 @@ extern "C" {
 /* C = alpha * sum_{b < nbatch} op(A_b) op(B_b) (+ C if beta), op: 0 = as stored, 2 = conjugate
    transpose; A_b = A + b*sA, B_b = B + b*sB (element strides).  prec 0: complex128 operands;
    prec 1 (FP32 MFMA) / 2 (BF16 split, FP32 accumulate): complex64 operands, complex64 output
-   unless out64 != 0 (complex128 output).  Asynchronous on stream. */
+   unless out64 != 0 (complex128 output).  flags bit 0 (prec 0, M == N, real alpha): the result is
+   Hermitian; only the tiles on and above the diagonal are computed and the rest is written as their
+   conjugate transpose.  Asynchronous on stream. */
 int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void* A, long long lda, long long sA, int opA,
                const void* B, long long ldb, long long sB, int opB, void* C, long long ldc, double alpha_re,
-               double alpha_im, int beta, int out64, void* stream);
+               double alpha_im, int beta, int out64, int flags, void* stream);
 
 /* Schur form in place: on entry A = G (n x n), on exit A = T (upper triangular), Z unitary with
    G = Z T Z^H.  stop_after_hessenberg != 0 returns the Hessenberg form instead of T. */
@@ -50,6 +52,8 @@ int lindx_profile_read(lind_ctx* ctx, int kind, long long* count, double* total_
    out_mode 0: planes, 1: transposed planes (both read back as complex128), 2: FP32 split-K
    partials reduced to complex128 (the only mode that takes nbatch > 1).  dr, dc (device
    complex128 of length M and N, or null; modes 0 and 1): entry (m, n) is divided by dr_m + dc_n.
+   out_mode + 4: the result is Hermitian (M == N): only the tiles on and above the diagonal are
+   computed and the rest is their conjugate transpose.
    Returns 0, or -1 for invalid arguments, -4 for a device error, -5 out of memory. */
 int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch, int opA, int opB, int out_mode,
                   const void* dr, const void* dc, void* C, void* stream);

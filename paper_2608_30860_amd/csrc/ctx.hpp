@@ -57,6 +57,7 @@ struct Ctx {
   zd *w1 = nullptr, *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *Ys = nullptr;
   zf *a32 = nullptr, *b32 = nullptr, *Y32 = nullptr;
   void* gws = nullptr;    // split-K workspace of the batch-reduction products
+  long long gws_bytes = 0;
   // BF16x3 eigen route: pre-split bf16 planes of V^H, V^T, the stacked L_j U (constants) and of
   // the intermediates of Phi; FP32 split-K partials of the jump reduction
   bool p4_ready = false;
@@ -115,8 +116,9 @@ int op_gemm(Ctx& c, int prec, int M, int N, int K, const void* A, long long lda,
             long long ldb, int opB, void* C, long long ldc, cplx alpha, int beta);
 // X = (S - mu)^{-1} Y in precision prec (route of the context); adjoint: (S* - conj(mu))^{-1}
 int op_sinv(Ctx& c, const zd* Y, zd* X, cplx mu, int prec, bool adjoint);
-// out = Phi(xi) in precision prec
-int op_phi(Ctx& c, const zd* xi, zd* out, int prec);
+// out = Phi(xi) in precision prec; hermitian: xi is Hermitian (Phi preserves it), so the Hermitian
+// intermediate and result are formed from the tiles on and above the diagonal
+int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian = false);
 // out = L(rho) (FP64); hermitian_in: rho is Hermitian (fewer products)
 int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in);
 // out = L*(X) (FP64)

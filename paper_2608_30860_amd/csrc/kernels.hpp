@@ -26,6 +26,10 @@ struct GemmDesc {
   // epilogue.  nsplit = 1: single pass.  ws must hold nsplit * M * N complex accumulators.
   int nsplit = 1;
   void* ws = nullptr;
+  long long ws_bytes = 0;  // capacity of ws (0: what gemm_ws_bytes gives for this shape)
+  // Hermitian result (M == N, real alpha, Hermitian epilogue data): only tiles on and above the
+  // diagonal are computed, the rest is written as their conjugate transpose (FP64 products)
+  int tri = 0;
 };
 // workspace bytes gemm() needs for a split-K launch of this shape (0 if it would not split)
 long long gemm_ws_bytes(int prec, int M, int N, int nbatch);
@@ -54,6 +58,9 @@ struct P4Desc {
   const zd* dr = nullptr; const zd* dc = nullptr;   // optional divide by dr_m + dc_n (planes out)
   float2* ws = nullptr;                             // P4OUT_WS: nsplit * M * N partials
   void* out64 = nullptr; long long ldo = 0; double alpha = 1.0;  // P4OUT_WS: complex128 result
+  // Hermitian result (M == N): only the tiles on and above the diagonal are computed; the result
+  // below is the conjugate transpose (P4OUT_WS: in the reduction; planes out: mirrored writes)
+  int tri = 0;
 };
 long long p4_rows_alloc(long long rows);
 long long p4_ld(long long k);

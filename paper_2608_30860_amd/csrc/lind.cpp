@@ -34,7 +34,9 @@ static int setup_p4(Ctx& c) {
   if (p4_split(c.V, 1, n, n, n, 1, 0, c.p4_VT, c.st)) return LIND_EDEVICE;
   if (p4_split(c.Lt, 1, n, d * n, n, 0, 0, c.p4_Lt, c.st)) return LIND_EDEVICE;
   // split-K over the d jump operators: enough workgroups to cover the chip four times
-  const long long tiles = (long long)((n + 127) / 128) * ((n + 127) / 128);
+  // (the Hermitian reduction of the steady-state iteration runs on the upper half of the tiles)
+  const long long tm = (n + 127) / 128;
+  const long long tiles = tm * (tm + 1) / 2;
   int s = 1;
   while (s * 2 <= d && d % (s * 2) == 0 && tiles * s < 1024) s *= 2;
   c.p4_nsplit = s;
@@ -134,7 +136,7 @@ static int ctx_factor(lind_ctx* X) {
   // W = sum_j L_j^H L_j (one launch, reduction over j), G = -iH - W/2   (eq. G)
   if (d > 0) {
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws; g.ws_bytes = c.gws_bytes;
     g.A = c.L; g.lda = n; g.sA = n2; g.opA = OP_C;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_N;
     g.C = c.w1; g.ldc = n;
@@ -260,7 +262,10 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
   }
   {
     long long wsb = std::max(gemm_ws_bytes(PREC_F64, n, n, std::max(d, 1)), gemm_ws_bytes(c.prec, n, n, std::max(d, 1)));
+    // room for up to 8 FP64 split-K partials (the Hermitian residual runs on half the tiles)
+    if (d >= 2) wsb = std::max(wsb, (long long)std::min(d, 8) * n2 * 16);
     if (wsb > 0) rc |= c.alloc((char**)&c.gws, (size_t)wsb);
+    c.gws_bytes = wsb;
   }
   if (rc == 0 && hipHostMalloc((void**)&c.hsc, sizeof(zd) * 8192) != hipSuccess) rc = LIND_ENOMEM;
   if (rc) {
@@ -509,8 +514,14 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   inf.t_factor_s = c.t_factor;
   inf.route_used = c.route;
   // start state and xi_0 = -S(rho_0)
-  if (rho0) TRY(copy((const zd*)rho0, X->rhoB, n2, c.st));
-  else hipLaunchKernelGGL(k_fill_identity_scaled, dim3(1024), dim3(256), 0, c.st, X->rhoB, n, 1.0 / n);
+  if (rho0) {
+    // the Hermitian part of the start state (the steady state is Hermitian), so that every Krylov
+    // vector is Hermitian
+    TRY(copy((const zd*)rho0, X->rhoB, n2, c.st));
+    TRY(hermitize(X->rhoB, n, 0, nullptr, c.dscr, c.st));
+  } else {
+    hipLaunchKernelGGL(k_fill_identity_scaled, dim3(1024), dim3(256), 0, c.st, X->rhoB, n, 1.0 / n);
+  }
   TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, X->rhoB, n, OP_N, X->xiB, n, mone, 0));
   TRY(op_gemm(c, PREC_F64, n, n, n, X->rhoB, n, OP_N, c.G, n, OP_C, X->xiB, n, mone, 1));
   double xin = 0;
@@ -536,7 +547,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     for (int j = 0; j < m; ++j) {
       zd* vj = K + (long long)j * n2;
       zd* wv = K + (long long)(j + 1) * n2;
-      TRY(op_phi(c, vj, wv, p));
+      TRY(op_phi(c, vj, wv, p, true));  // Krylov vectors of a Hermitian start stay Hermitian
       ++inf.n_phi;
       zd* h1 = c.dsc + 8;
       zd* h2 = c.dsc + 80;
@@ -569,6 +580,8 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     for (int i = 0; i < k; ++i) ysel[i] = Y[(size_t)i * k + sel];
     TRY(upload_vec(X, ysel.data(), k, X->yv));
     TRY(multi_axpy(K, n2, k, X->yv, X->xiB, n2, 0, 1.0, c.st));
+    // the fixed point xi = -S(rho_inf) is Hermitian: keep the restart vector Hermitian
+    TRY(hermitize(X->xiB, n, 0, nullptr, c.dscr, c.st));
     // rho = -S^{-1} xi, hermitised and normalised (the sign cancels in the normalisation)
     TRY(op_sinv(c, X->xiB, X->rhoB, cplx(0, 0), p, false));
     cplx trb;
@@ -599,7 +612,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     int stagn = 0;
     const double floor_inner = (p == PREC_F64) ? 1e-13 : (p == PREC_F32 ? 3e-6 : 1e-4);
     std::function<int(const zd*, zd*)> Aop = [&](const zd* in, zd* out) -> int {
-      int rc = op_phi(c, in, out, p);
+      int rc = op_phi(c, in, out, p, true);  // GMRES on a Hermitian right-hand side
       if (rc) return rc;
       ++inf.n_phi;
       return axpby(zmk(1, 0), in, zmk(-1, 0), out, n2, c.st) ? LIND_EDEVICE : 0;

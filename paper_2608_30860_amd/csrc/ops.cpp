@@ -171,7 +171,7 @@ int op_sinv(Ctx& c, const zd* Y, zd* X, cplx mu, int prec, bool adjoint) {
 // product [Lt_1; ..; Lt_d] Xh (one launch, M = d n) + the reduction product sum_j Y_j Lt_j^H
 // (one launch, K loop over (j, k)).
 // ---------------------------------------------------------------------------------------------
-int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
+int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian) {
   const int n = c.n, d = c.d;
   const long long n2 = c.n2;
   const cplx one(1, 0), mone(-1, 0);
@@ -183,7 +183,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     if (prec == PREC_F64) {
       TRY(op_gemm(c, PREC_F64, d * n, n, n, c.Lt, n, OP_N, c.w2, n, OP_N, c.Ys, n, one, 0));
       GemmDesc g;
-      g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
+      g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws; g.ws_bytes = c.gws_bytes;
       g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
       g.B = c.Lt; g.ldb = n; g.sB = n2; g.opB = OP_C;
       g.C = out; g.ldc = n; g.ar = -1.0;
@@ -193,7 +193,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     TRY(to_c64(c.w2, c.a32, n2, c.st));
     TRY(op_gemm(c, prec, d * n, n, n, c.Lt32, n, OP_N, c.a32, n, OP_N, c.Y32, n, one, 0));
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws; g.ws_bytes = c.gws_bytes;
     g.A = c.Y32; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.Lt32; g.ldb = n; g.sB = n2; g.opB = OP_C;
     g.C = out; g.ldc = n; g.ar = -1.0; g.out64 = 1;
@@ -210,16 +210,18 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     g.B = c.V; g.ldb = n; g.opB = OP_N;
     g.C = c.w2; g.ldc = n;
     g.epi = EPI_DIV; g.dr = c.s; g.dc = c.sbar;
+    g.tri = hermitian;  // Hermitian xi: Xh = (V^H xi V) / (s_i + conj s_j) is Hermitian
     TRY(gemm(PREC_F64, g, c.st));
     c.prof_end(s0);
     int s1 = c.prof_begin(PROF_JUMP_STACK);
     TRY(op_gemm(c, PREC_F64, d * n, n, n, c.Lt, n, OP_N, c.w2, n, OP_N, c.Ys, n, one, 0));
     c.prof_end(s1);
     GemmDesc h;
-    h.M = n; h.N = n; h.K = n; h.nbatch = d; h.ws = c.gws;
+    h.M = n; h.N = n; h.K = n; h.nbatch = d; h.ws = c.gws; h.ws_bytes = c.gws_bytes;
     h.A = c.Ys; h.lda = n; h.sA = n2; h.opA = OP_N;
     h.B = c.Lt; h.ldb = n; h.sB = n2; h.opB = OP_C;
     h.C = out; h.ldc = n; h.ar = -1.0;
+    h.tri = hermitian;
     int s2 = c.prof_begin(PROF_JUMP_REDUCE);
     TRY(gemm(PREC_F64, h, c.st));
     c.prof_end(s2);
@@ -244,6 +246,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     h.B = c.p4_VT.p; h.ldb = c.p4_VT.ld; h.pB = c.p4_VT.pstride;
     h.dr = c.s; h.dc = c.sbar;
     h.out = P4OUT_PLANES_T; h.C = c.p4_XhT.p; h.ldc = c.p4_XhT.ld; h.pC = c.p4_XhT.pstride;
+    h.tri = hermitian;  // Hermitian xi: V^H xi V and the divisors are Hermitian, so is Xh
     TRY(p4_gemm(h, c.st));
     c.prof_end(s0);
     int s1 = c.prof_begin(PROF_JUMP_STACK);
@@ -260,6 +263,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
     r.B = c.p4_Lt.p; r.ldb = c.p4_Lt.ld; r.pB = c.p4_Lt.pstride; r.sB = (long long)n * c.p4_Lt.ld;
     r.conjB = 1;
     r.out = P4OUT_WS; r.ws = c.p4_ws; r.out64 = out; r.ldo = n; r.alpha = -1.0;
+    r.tri = hermitian;  // sum_j L_j X L_j^+ of a Hermitian X
     int s2 = c.prof_begin(PROF_JUMP_REDUCE);
     TRY(p4_gemm(r, c.st));
     c.prof_end(s2);
@@ -281,7 +285,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec) {
   TRY(op_gemm(c, prec, d * n, n, n, c.Lt32, n, OP_N, c.a32, n, OP_N, c.Y32, n, one, 0));
   c.prof_end(s1);
   GemmDesc h;
-  h.M = n; h.N = n; h.K = n; h.nbatch = d; h.ws = c.gws;
+  h.M = n; h.N = n; h.K = n; h.nbatch = d; h.ws = c.gws; h.ws_bytes = c.gws_bytes;
   h.A = c.Y32; h.lda = n; h.sA = n2; h.opA = OP_N;
   h.B = c.Lt32; h.ldb = n; h.sB = n2; h.opB = OP_C;
   h.C = out; h.ldc = n; h.ar = -1.0; h.out64 = 1;
@@ -304,11 +308,12 @@ int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in) {
     TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, rho, n, OP_N, c.w4, n, one, 0));
     TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, rho, n, OP_N, c.Ys, n, one, 0));
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws; g.ws_bytes = c.gws_bytes;
     g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_C;
     g.C = out; g.ldc = n;
     g.epi = EPI_HERM_ADD; g.E = c.w4; g.lde = n;
+    g.tri = 1;  // the result is Hermitian: tiles on and above the diagonal only
     TRY(gemm(PREC_F64, g, c.st));
     return 0;
   }
@@ -317,7 +322,7 @@ int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in) {
   if (d > 0) {
     TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, rho, n, OP_N, c.Ys, n, one, 0));
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws; g.ws_bytes = c.gws_bytes;
     g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_C;
     g.C = out; g.ldc = n; g.beta = 1;
@@ -337,7 +342,7 @@ int op_apply_adj(Ctx& c, const zd* X, zd* out) {
     TRY(op_gemm(c, PREC_F64, n, n, n, c.L + j * n2, n, OP_C, X, n, OP_N, c.Ys + j * n2, n, one, 0));
   if (d > 0) {
     GemmDesc g;
-    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws;
+    g.M = n; g.N = n; g.K = n; g.nbatch = d; g.ws = c.gws; g.ws_bytes = c.gws_bytes;
     g.A = c.Ys; g.lda = n; g.sA = n2; g.opA = OP_N;
     g.B = c.L; g.ldb = n; g.sB = n2; g.opB = OP_N;
     g.C = out; g.ldc = n; g.beta = 1;

@@ -6,7 +6,7 @@ using namespace lindx;
 
 extern "C" int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void* A, long long lda, long long sA,
                           int opA, const void* B, long long ldb, long long sB, int opB, void* C, long long ldc,
-                          double alpha_re, double alpha_im, int beta, int out64, void* stream) {
+                          double alpha_re, double alpha_im, int beta, int out64, int flags, void* stream) {
   if (!A || !B || !C || M < 0 || N < 0 || K < 1 || nbatch < 1 || prec < 0 || prec > 2) return -1;
   if ((opA != OP_N && opA != OP_C) || (opB != OP_N && opB != OP_C)) return -1;
   GemmDesc g;
@@ -15,6 +15,7 @@ extern "C" int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void*
   g.B = B; g.ldb = ldb; g.sB = sB; g.opB = opB;
   g.C = C; g.ldc = ldc;
   g.ar = alpha_re; g.ai = alpha_im; g.beta = beta; g.out64 = out64;
+  g.tri = flags & 1;
   // a batch reduction that would split over K gets its workspace here (tests only)
   long long wsb = gemm_ws_bytes(prec, M, N, nbatch);
   void* ws = nullptr;
@@ -87,7 +88,10 @@ extern "C" int lindx_copy(void* dst, const void* src, long long nbytes, void* st
 // planes modes): divide entry (m, n) by dr_m + dc_n.
 extern "C" int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch, int opA, int opB,
                              int out_mode, const void* dr, const void* dc, void* C, void* stream) {
+  const int tri = (out_mode >> 2) & 1;  // bit 2: Hermitian result from the upper tiles
+  out_mode &= 3;
   if (!A || !B || !C || M < 1 || N < 1 || K < 1 || nbatch < 1 || out_mode < 0 || out_mode > 2) return -1;
+  if (tri && M != N) return -1;
   if ((opA != OP_N && opA != OP_C) || (opB != OP_N && opB != OP_C)) return -1;
   if (out_mode != 2 && nbatch != 1) return -1;
   hipStream_t st = (hipStream_t)stream;
@@ -126,6 +130,7 @@ extern "C" int lindx_p4_test(const void* A, const void* B, int M, int N, int K, 
     g.C = pc.p; g.ldc = pc.ld; g.pC = pc.pstride;
     g.dr = (const zd*)dr; g.dc = (const zd*)dc;
     g.ws = ws; g.out64 = C; g.ldo = N; g.alpha = 1.0;
+    g.tri = tri;
     rc = p4_gemm(g, st);
     if (!rc && out_mode != 2) rc = p4_join(pc, M, N, out_mode == 1, (zd*)C, N, st);
   }

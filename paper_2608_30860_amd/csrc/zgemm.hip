@@ -46,6 +46,17 @@ __device__ inline void tile_of(int bid, int tm, int tn, int& bm, int& bn) {
   bn = t - bm * tn;
 }
 
+// tile t of the upper triangle (bm <= bn) of a tm x tm grid, row-major, after the round robin
+// over the 8 XCDs
+__device__ inline void tile_upper64(int bid, int tm, int& bm, int& bn) {
+  const int T = tm * (tm + 1) / 2;
+  int t = ((T & 7) == 0) ? (bid & 7) * (T >> 3) + (bid >> 3) : bid;
+  int r = 0;
+  while (t >= tm - r) { t -= tm - r; ++r; }
+  bm = r;
+  bn = r + t;
+}
+
 template <typename CplxOut>
 __device__ inline void store_out(CplxOut* p, double re, double im);
 template <> __device__ inline void store_out<double2>(double2* p, double re, double im) {
@@ -507,10 +518,11 @@ __global__ __launch_bounds__(512) void zgemm64_dma(GemmDesc g, int a_bytes, int 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 32;
   const int tm = (g.M + Z64_TB - 1) / Z64_TB, tn = (g.N + Z64_TB - 1) / Z64_TB;
-  const int tiles = tm * tn;
+  const int tiles = g.tri ? tm * (tm + 1) / 2 : tm * tn;
   const int split = blockIdx.x / tiles;
   int bm, bn;
-  tile_of(blockIdx.x - split * tiles, tm, tn, bm, bn);
+  if (g.tri) tile_upper64(blockIdx.x - split * tiles, tm, bm, bn);
+  else tile_of(blockIdx.x - split * tiles, tm, tn, bm, bn);
   const int m0 = bm * Z64_TB, n0 = bn * Z64_TB;
   const int ktiles = (g.K + Z64_BK - 1) / Z64_BK;
   const int bps = g.nbatch / g.nsplit;
@@ -616,6 +628,8 @@ __global__ __launch_bounds__(512) void zgemm64_dma(GemmDesc g, int a_bytes, int 
             ((double2*)g.ws)[((long long)split * g.M + row) * g.N + col] = make_double2(cr[i][j][r], ci[i][j][r]);
         } else {
           epilogue_store<double2>(g, row, col, cr[i][j][r], ci[i][j][r]);
+          // Hermitian result: entry (col, row) is the conjugate
+          if (g.tri && bm < bn) epilogue_store<double2>(g, col, row, cr[i][j][r], -ci[i][j][r]);
         }
       }
 }
@@ -633,14 +647,17 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmDesc g) {
   const long long tot = (long long)g.M * g.N;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    const int row = (int)(t / g.N), col = (int)(t - (long long)row * g.N);
+    // Hermitian result: below the diagonal tiles, the partials of the mirrored entry, conjugated
+    const bool low = g.tri && (row / 128) > (col / 128);
+    const long long src = low ? (long long)col * g.N + row : t;
     double re = 0, im = 0;
     for (int s = 0; s < g.nsplit; ++s) {
-      CplxAcc v = ((const CplxAcc*)g.ws)[(long long)s * tot + t];
+      CplxAcc v = ((const CplxAcc*)g.ws)[(long long)s * tot + src];
       re += v.x;
       im += v.y;
     }
-    const int row = (int)(t / g.N), col = (int)(t - (long long)row * g.N);
-    epilogue_store<CplxOut>(g, row, col, re, im);
+    epilogue_store<CplxOut>(g, row, col, re, low ? -im : im);
   }
 }
 
@@ -693,6 +710,7 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
   if (g0.M <= 0 || g0.N <= 0) return 0;
   if (g0.K <= 0 || g0.nbatch <= 0) return -1;  // callers never ask for an empty reduction
   GemmDesc g = g0;
+  if (prec != PREC_F64) g.tri = 0;
   g.nsplit = 1;
   if (g0.ws) {
     int s = choose_split(prec, g.M, g.N, g.nbatch);
@@ -706,14 +724,16 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
     const bool aligned = (((unsigned long long)g.A | (unsigned long long)g.B) & 15) == 0;
     if (ea > 0 && eb > 0 && aligned) {
       // direct-to-LDS kernel; the split-K count is re-derived for its 128 x 128 tiles
+      g.tri = (g0.tri && g.M == g.N && g.ai == 0.0) ? 1 : 0;
       if (g0.ws) {
         int s = 1;
-        const long long t = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128);
-        while (s * 2 <= g.nbatch && (g.nbatch % (s * 2)) == 0 && t * s < 1024 && (long long)(s * 2) * g.M * g.N * 16 <= gemm_ws_bytes(PREC_F64, g.M, g.N, g.nbatch)) s *= 2;
+        const long long tm0 = (g.M + 127) / 128;
+        const long long t = g.tri ? tm0 * (tm0 + 1) / 2 : tm0 * ((g.N + 127) / 128);
+        while (s * 2 <= g.nbatch && (g.nbatch % (s * 2)) == 0 && t * s < 1024 && (long long)(s * 2) * g.M * g.N * 16 <= (g0.ws_bytes > 0 ? g0.ws_bytes : gemm_ws_bytes(PREC_F64, g.M, g.N, g.nbatch))) s *= 2;
         g.nsplit = s;
       }
       const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
-      const dim3 grid(tm * tn * g.nsplit), blk(512);
+      const dim3 grid((g.tri ? tm * (tm + 1) / 2 : tm * tn) * g.nsplit), blk(512);
       if (an && bn) hipLaunchKernelGGL((zgemm64_dma<true, true>), grid, blk, 0, st, g, (int)ea, (int)eb);
       else if (an) hipLaunchKernelGGL((zgemm64_dma<true, false>), grid, blk, 0, st, g, (int)ea, (int)eb);
       else if (bn) hipLaunchKernelGGL((zgemm64_dma<false, true>), grid, blk, 0, st, g, (int)ea, (int)eb);
@@ -722,6 +742,7 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
       if (!rc && g.nsplit > 1) rc = launch_reduce<double2, double2>(g, st);
       return rc;
     }
+    g.tri = 0;  // the register-staged kernel computes every tile
     if (g.nsplit > 1 || (g.M >= 1024 && g.N >= 1024)) rc = launch(zgemm_kernel<double, 128, 64, 16, double2>, 128, 64, g, st);
     else rc = launch(zgemm_kernel<double, 64, 64, 16, double2>, 64, 64, g, st);
     if (!rc && g.nsplit > 1) rc = launch_reduce<double2, double2>(g, st);

@@ -67,6 +67,17 @@ __device__ inline void tile_xcd(int bid, int tm, int tn, int& bm, int& bn) {
   bn = t - bm * tn;
 }
 
+// tile t of the upper triangle (bm <= bn) of a tm x tm tile grid, row-major, after the same
+// round robin over the 8 XCDs as tile_xcd
+__device__ inline void tile_upper(int bid, int tm, int& bm, int& bn) {
+  const int T = tm * (tm + 1) / 2;
+  int t = ((T & 7) == 0) ? (bid & 7) * (T >> 3) + (bid >> 3) : bid;
+  int r = 0;
+  while (t >= tm - r) { t -= tm - r; ++r; }
+  bm = r;
+  bn = r + t;
+}
+
 __device__ inline void split_bf16(float x, __bf16& h, __bf16& l) {
   h = (__bf16)x;
   l = (__bf16)(x - (float)h);
@@ -87,10 +98,11 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
   const int wm0 = (wave / (NW / 2)) * 64;
   const int wn0 = (wave % (NW / 2)) * (16 * TNW);
   const int tm = (g.M + TB - 1) / TB, tn = (g.N + TB - 1) / TB;
-  const int tiles = tm * tn;
+  const int tiles = g.tri ? tm * (tm + 1) / 2 : tm * tn;
   const int split = blockIdx.x / tiles;
   int bm, bn;
-  tile_xcd(blockIdx.x - split * tiles, tm, tn, bm, bn);
+  if (g.tri) tile_upper(blockIdx.x - split * tiles, tm, bm, bn);
+  else tile_xcd(blockIdx.x - split * tiles, tm, tn, bm, bn);
   const int m0 = bm * TB, n0 = bn * TB;
   const int ktiles = (g.K + KS - 1) / KS;
   const int bps = g.nbatch / g.nsplit;
@@ -230,6 +242,18 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
       // (P4OUT_PLANES_T, normal: four consecutive m)
       const long long base = (OUT == P4OUT_PLANES) ? (long long)m_l * g.ldc + n_l : (long long)n_l * g.ldc + m_l;
       const bool all = ok[0] && ok[1] && ok[2] && ok[3];
+      if (g.tri && bm < bn) {
+        // the conjugate of entry (mm, nn) is entry (nn, mm) of the Hermitian result
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (!ok[r]) continue;
+          const long long o = (OUT == P4OUT_PLANES) ? (long long)nn[r] * g.ldc + mm[r] : (long long)mm[r] * g.ldc + nn[r];
+          g.C[o] = h0[r];
+          g.C[g.pC + o] = l0[r];
+          g.C[2 * g.pC + o] = -h1[r];
+          g.C[3 * g.pC + o] = -l1[r];
+        }
+      }
       if (all) {
         *(v4bf_p*)(g.C + base) = h0;
         *(v4bf_p*)(g.C + g.pC + base) = l0;
@@ -250,17 +274,21 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
 
 // sum of the FP32 split-K partials, scaled by alpha, into complex128 (row-major, ldo)
 __global__ __launch_bounds__(256) void k_p4_reduce(const float2* __restrict__ ws, int nsplit, int M, int N,
-                                                   double alpha, zd* __restrict__ out, long long ldo) {
+                                                   double alpha, zd* __restrict__ out, long long ldo, int tri) {
   const long long tot = (long long)M * N;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    const int row = (int)(t / N), col = (int)(t - (long long)row * N);
+    // Hermitian result: entries below the diagonal are the conjugates of those above it
+    const bool low = tri && row > col;
+    const long long src = low ? (long long)col * N + row : t;
     double re = 0, im = 0;
     for (int s = 0; s < nsplit; ++s) {
-      const float2 v = ws[(long long)s * tot + t];
+      const float2 v = ws[(long long)s * tot + src];
       re += v.x;
       im += v.y;
     }
-    const int row = (int)(t / N), col = (int)(t - (long long)row * N);
+    if (tri) im = (row == col) ? 0.0 : (low ? -im : im);
     out[(long long)row * ldo + col] = zmk(alpha * re, alpha * im);
   }
 }
@@ -406,7 +434,8 @@ int p4_gemm(const P4Desc& g0, hipStream_t st) {
   if ((g.nbatch - 1) * g.sB + (nt - 1) * g.ldb + kpad > g.pB) return -1;
   if ((g.lda % 8) || (g.ldb % 8) || (g.sA % 8) || (g.sB % 8) || (g.pA % 8) || (g.pB % 8)) return -1;
   if ((((unsigned long long)g.A) & 15) || (((unsigned long long)g.B) & 15)) return -1;
-  const int tiles = (int)((mt / TB) * (nt / TB));
+  if (g.tri && g.M != g.N) return -1;
+  const int tiles = g.tri ? (int)((mt / TB) * (mt / TB + 1) / 2) : (int)((mt / TB) * (nt / TB));
   const int blocks = tiles * g.nsplit;
   if (g.out == P4OUT_WS) {
     if (!g.ws) return -1;
@@ -416,7 +445,7 @@ int p4_gemm(const P4Desc& g0, hipStream_t st) {
     long long nbk = (tot + 255) / 256;
     if (nbk > 16384) nbk = 16384;
     hipLaunchKernelGGL(k_p4_reduce, dim3((int)nbk), dim3(256), 0, st, (const float2*)g.ws, g.nsplit, g.M, g.N,
-                       g.alpha, (zd*)g.out64, g.ldo);
+                       g.alpha, (zd*)g.out64, g.ldo, g.tri);
     return hipGetLastError() == hipSuccess ? 0 : -4;
   }
   if (!g.C || (g.ldc % 4) || (g.pC % 4)) return -1;

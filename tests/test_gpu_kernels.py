@@ -13,7 +13,7 @@ def lib():
     from paper_2608_30860_amd.lindx import load_library
     L = load_library()
     vp, ci, cd, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
-    L.lindx_gemm.argtypes = [ci, ci, ci, ci, ci, vp, ll, ll, ci, vp, ll, ll, ci, vp, ll, cd, cd, ci, ci, vp]
+    L.lindx_gemm.argtypes = [ci, ci, ci, ci, ci, vp, ll, ll, ci, vp, ll, ll, ci, vp, ll, cd, cd, ci, ci, ci, vp]
     L.lindx_schur.argtypes = [vp, vp, ci, ci, vp]
     L.lindx_small_eig.argtypes = [vp, ci, vp, vp, vp]
     L.lindx_trevec.argtypes = [vp, vp, ci, vp]
@@ -61,7 +61,7 @@ def test_gemm(prec, tol, M, N, K, nb, opA, opB):
             lda = Ash[2]
             ldb = Bsh[2]
             rc = lib().lindx_gemm(prec, M, N, K, nb, P(At), lda, Ash[1] * Ash[2], opA, P(Bt), ldb, Bsh[1] * Bsh[2],
-                                  opB, P(Ct), N, alpha.real, alpha.imag, beta, out64, None)
+                                  opB, P(Ct), N, alpha.real, alpha.imag, beta, out64, 0, None)
             assert rc == 0
             torch.cuda.synchronize()
             got = Ct.cpu().numpy().astype(np.complex128)
@@ -102,6 +102,55 @@ def test_p4_gemm(M, N, K, nb, opA, opB, mode):
         got = Ct.cpu().numpy()
         err = np.max(np.abs(got - want)) / np.max(np.abs(want))
         assert err < 3e-4, (div, err)
+
+
+@pytest.mark.parametrize("n,K,nb", [(37, 29, 1), (130, 200, 1), (256, 64, 1), (300, 72, 4), (1, 5, 1), (2048, 96, 1)])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_p4_gemm_hermitian(n, K, nb, mode):
+    """Hermitian products A A^H (summed over batches, and divided by d_m + conj(d_n)) from the upper
+    tiles only: against the full product, and exactly Hermitian"""
+    if mode != 2 and nb != 1:
+        pytest.skip("batched products only reduce into split-K partials")
+    print(f"[case] p4 hermitian n={n} K={K} nb={nb} mode={mode}", flush=True)
+    rng = np.random.default_rng(n + K + nb + mode)
+    A = crand(rng, nb, n, K)
+    ref = sum(A[b] @ A[b].conj().T for b in range(nb))
+    div = mode != 2
+    dr = crand(rng, n) + 3.0
+    if div:
+        ref = ref / (dr[:, None] + dr.conj()[None, :])
+    At = T(A)
+    drt, dct = T(dr), T(dr.conj())
+    Ct = T(np.zeros((n, n)))
+    rc = lib().lindx_p4_test(P(At), P(At), n, n, K, nb, 0, 2, mode + 4, P(drt) if div else None,
+                             P(dct) if div else None, P(Ct), None)
+    assert rc == 0
+    got = Ct.cpu().numpy()
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 3e-4
+    if mode == 2:
+        assert np.array_equal(got, got.conj().T)
+
+
+@pytest.mark.parametrize("n,K,nb", [(37, 29, 1), (130, 70, 1), (300, 72, 8), (1024, 64, 4), (257, 33, 3)])
+@pytest.mark.parametrize("beta", [0, 1])
+def test_gemm_fp64_hermitian(n, K, nb, beta):
+    """FP64 product with a Hermitian result (sum_b A_b A_b^H, real alpha, Hermitian C for beta) from
+    the upper tiles only, against NumPy; exactly Hermitian when beta = 0"""
+    print(f"[case] gemm64 hermitian n={n} K={K} nb={nb} beta={beta}", flush=True)
+    rng = np.random.default_rng(n + K + nb)
+    A = crand(rng, nb, n, K)
+    C0 = crand(rng, n, n)
+    C0 = C0 + C0.conj().T
+    alpha = -0.75
+    ref = alpha * sum(A[b] @ A[b].conj().T for b in range(nb)) + (C0 if beta else 0)
+    At, Ct = T(A), T(C0)
+    rc = lib().lindx_gemm(0, n, n, K, nb, P(At), K, n * K, 0, P(At), K, n * K, 2, P(Ct), n, alpha, 0.0, beta, 0, 1,
+                          None)
+    assert rc == 0
+    got = Ct.cpu().numpy()
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-13
+    if not beta:
+        assert np.max(np.abs(got - got.conj().T)) <= 1e-14 * np.max(np.abs(got))
 
 
 @pytest.mark.parametrize("n", [3, 37, 130, 257])
