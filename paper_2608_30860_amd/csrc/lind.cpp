@@ -540,6 +540,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   std::vector<cplx> Hh((size_t)(m + 1) * m), w, Y;
   double colsum = 0, mx = 0, fro = 0;
   bool floor_hit = false;
+  bool best_is_last = false;  // rhoB / resB hold the best state and its FP64 residual
   for (int rs = 0; rs < c.opts.max_restarts && !converged; ++rs) {
     std::fill(Hh.begin(), Hh.end(), cplx(0));
     int k = 0, sel = 0;
@@ -590,6 +591,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     double xn = 0;
     TRY(op_nrm(c, X->xiB, &xn));
     if (std::abs(trb) > 0) c_scale = std::sqrt((double)n) * xn / std::abs(trb);
+    best_is_last = colsum < best;
     if (colsum < best) {
       best = colsum;
       best_max = mx;
@@ -605,9 +607,14 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   }
   // FP64 iterative refinement: (I - Phi_p) zeta = L rho, rho <- rho - S_p^{-1} zeta
   if (!converged && (floor_hit || true)) {
-    // continue from the best state
-    TRY(copy((const zd*)rho_out, X->rhoB, n2, c.st));
-    TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
+    // continue from the best state; when it is the last one evaluated, rhoB and its residual in
+    // resB are already in place
+    if (!best_is_last) {
+      TRY(copy((const zd*)rho_out, X->rhoB, n2, c.st));
+      TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
+    } else {
+      colsum = best;
+    }
     double prev = colsum;
     int stagn = 0;
     const double floor_inner = (p == PREC_F64) ? 1e-13 : (p == PREC_F32 ? 3e-6 : 1e-4);
