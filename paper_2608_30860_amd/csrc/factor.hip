@@ -206,142 +206,163 @@ __global__ __launch_bounds__(64) void k_shifts(const zd* A, int n, int lo, int n
   (void)rc;
 }
 
+// Broadcast lane l's value of a double to the whole wave (l uniform): v_readlane into scalars.
+__device__ inline double bcast(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Chase the bulge chain through window rows/cols [r, r+bw).  All bulges move in lockstep: at
 // step t bulge b rotates at pair P0 + t - 2b (front bulge first in the equivalent sequential
 // order).  Rotations of one step act on disjoint row pairs and disjoint column pairs, and a
-// bulge's parameters only read entries that the other bulges of the same step do not touch, so
-// each step is three phases: parameters (one thread per bulge), row rotations, column rotations
-// (with the accumulated window unitary).
+// bulge's parameters only read entries that the other bulges of the same step do not touch.
+//
+// Bulge b belongs to wave b % 4 for the whole chase: lane b / 4 of that wave computes the
+// rotation, v_readlane hands it to the wave in scalar registers, and the same wave applies the
+// row rotation (lane = column) and then the column rotation of the window and of the window
+// unitary (lane = row).  The parameters of a bulge read rows q, q+1, which no other bulge's row
+// rotation of the same step writes, so one step needs a barrier only between the row and the
+// column rotations (other bulges' rows meet this bulge's columns) and at its end.
 __global__ __launch_bounds__(256) void k_chase(zd* A, int n, int ilo, int ihi, int r, int bw,
                                                 const zd* shifts, int ns, int* cnt, zd* Uout) {
   __shared__ zd Hs[WIN * LDM];
   __shared__ zd Us[WIN * LDM];
-  __shared__ double cs_s[NSMAX];
-  __shared__ zd sn_s[NSMAX];
-  __shared__ int q_s[NSMAX];
-  __shared__ int c0_s[NSMAX];
-  __shared__ int nxt_s[NSMAX];
+  constexpr int BPW = (NSMAX + 3) / 4;  // bulges per wave
   const int t = threadIdx.x;
-  for (int e = t; e < bw * bw; e += 256) {
-    int i = e / bw, j = e - i * bw;
-    Hs[i * LDM + j] = A[(long long)(r + i) * n + r + j];
-    Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int lane = t & 63;
+  {
+    zd v[WIN * WIN / 256];
+#pragma unroll
+    for (int k = 0; k < WIN * WIN / 256; ++k) {
+      const int e = t + 256 * k, i = e >> 6, j = e & 63;
+      v[k] = (i < bw && j < bw) ? A[(long long)(r + i) * n + r + j] : zmk(0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < WIN * WIN / 256; ++k) {
+      const int e = t + 256 * k, i = e >> 6, j = e & 63;
+      Hs[i * LDM + j] = v[k];
+      Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
+    }
   }
-  if (t < ns) nxt_s[t] = ilo + cnt[t];
+  // lane u < BPW of wave w owns bulge b = w + 4u: its shift and its next pair
+  const int myb = w + 4 * lane;
+  const bool own = lane < BPW && myb < ns;
+  zd sh = zmk(0, 0);
+  int nxt = 0;
+  if (own) {
+    sh = shifts[myb];
+    nxt = ilo + cnt[myb];
+  }
+  const int P0 = ilo + cnt[0];
   __syncthreads();
   const bool at_end = (r + bw - 1 >= ihi);
   const int pmax = at_end ? ihi - 1 : r + bw - 3;
   const int pmin = (r == ilo) ? ilo : r + 1;
   const int plim = pmax < ihi - 1 ? pmax : ihi - 1;
-  const int P0 = nxt_s[0];
   const int t_end = at_end ? (ihi - 1 - (P0 - 2 * (ns - 1))) : (pmax - P0);
   for (int step = 0; step <= t_end; ++step) {
-    // phase A: rotation parameters
-    if (t < ns) {
-      const int p = P0 + step - 2 * t;
+    // parameters of this wave's bulges (lane u: bulge w + 4u)
+    double cs = 1.0;
+    zd sn = zmk(0, 0);
+    int q = -1;
+    if (own) {
+      const int p = P0 + step - 2 * myb;
       if (p >= ilo && p >= pmin && p <= plim) {
-        const int q = p - r;
-        zd f, g;
+        q = p - r;
+        zd f, g, rr;
         if (p == ilo) {
-          f = zsub(Hs[q * LDM + q], shifts[t]);
+          f = zsub(Hs[q * LDM + q], sh);
           g = Hs[(q + 1) * LDM + q];
         } else {
           f = Hs[q * LDM + q - 1];
           g = Hs[(q + 1) * LDM + q - 1];
         }
-        double cs;
-        zd sn, rr;
         zlartg(f, g, cs, sn, rr);
-        cs_s[t] = cs;
-        sn_s[t] = sn;
-        q_s[t] = q;
-        c0_s[t] = (p == ilo) ? q : q - 1;
-        nxt_s[t] = p + 1;
-      } else {
-        q_s[t] = -1;
+        nxt = p + 1;
+      }
+    }
+    double bc[BPW], bsr[BPW], bsi[BPW];
+    int bq[BPW];
+#pragma unroll
+    for (int u = 0; u < BPW; ++u) {
+      bq[u] = __builtin_amdgcn_readlane(q, u);
+      bc[u] = bcast(cs, u);
+      bsr[u] = bcast(sn.x, u);
+      bsi[u] = bcast(sn.y, u);
+    }
+    // row rotations: rows q, q+1 from column c0 (q, or q-1 with the chased entry zeroed)
+    {
+      zd x[BPW], y[BPW];
+#pragma unroll
+      for (int u = 0; u < BPW; ++u) {
+        const int qq = bq[u];
+        const int c0 = (qq >= 0 && r + qq == ilo) ? qq : qq - 1;
+        if (qq >= 0 && lane >= c0 && lane < bw) {
+          x[u] = Hs[qq * LDM + lane];
+          y[u] = Hs[(qq + 1) * LDM + lane];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < BPW; ++u) {
+        const int qq = bq[u];
+        const bool first = (qq >= 0 && r + qq == ilo);
+        const int c0 = first ? qq : qq - 1;
+        if (qq >= 0 && lane >= c0 && lane < bw) {
+          const zd sv = zmk(bsr[u], bsi[u]);
+          Hs[qq * LDM + lane] = zadd(zscale(x[u], bc[u]), zmul(sv, y[u]));
+          Hs[(qq + 1) * LDM + lane] =
+              (!first && lane == qq - 1) ? zmk(0, 0) : zsub(zscale(y[u], bc[u]), zmul(zconj(sv), x[u]));
+        }
       }
     }
     __syncthreads();
-    // phase B: row rotations (rows q, q+1 of each active bulge), zero the chased entry.  The
-    // items of one thread belong to different bulges (disjoint rows), so all loads are issued
-    // before the stores.
+    // column rotations: columns q, q+1 of the window (rows <= q+2) and of the window unitary
     {
-      constexpr int NB = (NSMAX * 64 + 255) / 256;
-      zd x[NB], y[NB];
-      int off[NB];
-      bool ok[NB];
+      zd hx[BPW], hy[BPW], ux[BPW], uy[BPW];
 #pragma unroll
-      for (int u = 0; u < NB; ++u) {
-        const int item = t + 256 * u;
-        const int b = item >> 6, col = item & 63;
-        ok[u] = false;
-        off[u] = 0;
-        if (b < ns) {
-          const int q = q_s[b];
-          if (q >= 0 && col >= c0_s[b] && col < bw) {
-            ok[u] = true;
-            off[u] = q * LDM + col;
-            x[u] = Hs[off[u]];
-            y[u] = Hs[off[u] + LDM];
+      for (int u = 0; u < BPW; ++u) {
+        const int qq = bq[u];
+        if (qq >= 0) {
+          if (lane <= qq + 2 && lane < bw) {
+            hx[u] = Hs[lane * LDM + qq];
+            hy[u] = Hs[lane * LDM + qq + 1];
+          }
+          if (lane < bw) {
+            ux[u] = Us[lane * LDM + qq];
+            uy[u] = Us[lane * LDM + qq + 1];
           }
         }
       }
 #pragma unroll
-      for (int u = 0; u < NB; ++u) {
-        if (!ok[u]) continue;
-        const int item = t + 256 * u;
-        const int b = item >> 6, col = item & 63;
-        const int q = q_s[b];
-        const double c = cs_s[b];
-        const zd sv = sn_s[b];
-        Hs[off[u]] = zadd(zscale(x[u], c), zmul(sv, y[u]));
-        Hs[off[u] + LDM] = (col == q - 1 && c0_s[b] == q - 1) ? zmk(0, 0) : zsub(zscale(y[u], c), zmul(zconj(sv), x[u]));
-      }
-    }
-    __syncthreads();
-    // phase C: column rotations (columns q, q+1) of the window and of the window unitary
-    {
-      constexpr int NC = (NSMAX * 128 + 255) / 256;
-      zd x[NC], y[NC];
-      zd* ptr[NC];
-#pragma unroll
-      for (int u = 0; u < NC; ++u) {
-        const int item = t + 256 * u;
-        const int b = item >> 7, rr = item & 127;
-        ptr[u] = nullptr;
-        if (b < ns) {
-          const int q = q_s[b];
-          if (q >= 0) {
-            if (rr < 64) {
-              const int r1 = q + 2 < bw - 1 ? q + 2 : bw - 1;
-              if (rr <= r1) ptr[u] = &Hs[rr * LDM + q];
-            } else if (rr - 64 < bw) {
-              ptr[u] = &Us[(rr - 64) * LDM + q];
-            }
+      for (int u = 0; u < BPW; ++u) {
+        const int qq = bq[u];
+        if (qq >= 0) {
+          const zd sv = zmk(bsr[u], bsi[u]);
+          const double c = bc[u];
+          if (lane <= qq + 2 && lane < bw) {
+            Hs[lane * LDM + qq] = zadd(zscale(hx[u], c), zmul(zconj(sv), hy[u]));
+            Hs[lane * LDM + qq + 1] = zsub(zscale(hy[u], c), zmul(sv, hx[u]));
+          }
+          if (lane < bw) {
+            Us[lane * LDM + qq] = zadd(zscale(ux[u], c), zmul(zconj(sv), uy[u]));
+            Us[lane * LDM + qq + 1] = zsub(zscale(uy[u], c), zmul(sv, ux[u]));
           }
         }
-        if (ptr[u]) {
-          x[u] = ptr[u][0];
-          y[u] = ptr[u][1];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < NC; ++u) {
-        if (!ptr[u]) continue;
-        const int b = (t + 256 * u) >> 7;
-        const double c = cs_s[b];
-        const zd sv = sn_s[b];
-        ptr[u][0] = zadd(zscale(x[u], c), zmul(zconj(sv), y[u]));
-        ptr[u][1] = zsub(zscale(y[u], c), zmul(sv, x[u]));
       }
     }
     __syncthreads();
   }
-  if (t < ns) cnt[t] = nxt_s[t] - ilo;
-  for (int e = t; e < bw * bw; e += 256) {
-    int i = e / bw, j = e - i * bw;
-    A[(long long)(r + i) * n + r + j] = Hs[i * LDM + j];
-    Uout[i * WIN + j] = Us[i * LDM + j];
+  if (own) cnt[myb] = nxt - ilo;
+#pragma unroll
+  for (int k = 0; k < WIN * WIN / 256; ++k) {
+    const int e = t + 256 * k, i = e >> 6, j = e & 63;
+    if (i < bw && j < bw) {
+      A[(long long)(r + i) * n + r + j] = Hs[i * LDM + j];
+      Uout[i * WIN + j] = Us[i * LDM + j];
+    }
   }
 }
 
