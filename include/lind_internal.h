@@ -21,8 +21,10 @@ int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void* A, long lo
                double alpha_im, int beta, int out64, int flags, void* stream);
 
 /* Schur form in place: on entry A = G (n x n), on exit A = T (upper triangular), Z unitary with
-   G = Z T Z^H.  stop_after_hessenberg != 0 returns the Hessenberg form instead of T. */
-int lindx_schur(void* A, void* Z, int n, int stop_after_hessenberg, void* stream);
+   G = Z T Z^H.  mode bit 0 set returns the Hessenberg form instead of T; mode bits 8..15 choose
+   the early-deflation window of the QR iteration (0: the library default, 1: none, 16..64: that
+   many rows; anything else returns -1). */
+int lindx_schur(void* A, void* Z, int n, int mode, void* stream);
 
 /* eigenvalues w (m) and unit-norm right eigenvectors Y (m x m, column j for w[j]) of a dense
    m x m matrix A (m <= 64), one workgroup */

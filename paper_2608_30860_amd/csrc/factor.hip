@@ -4,14 +4,18 @@
 //
 // 1. Householder reduction to upper Hessenberg form (one reflector per column; the reflector
 //    build is one workgroup, the two-sided updates are bandwidth-bound multi-workgroup kernels).
-// 2. Multishift QR iteration (complex single-shift bulges, up to 15 per sweep, shifts from the
+// 2. Multishift QR iteration (complex single-shift bulges, up to 19 per sweep, shifts from the
 //    eigenvalues of the trailing block).  A chain of bulges is chased down the diagonal in
-//    64 x 64 windows that advance by 32 rows: each window is chased in LDS by one wave which
+//    64 x 64 windows that advance by 24 rows: each window is chased in LDS by one workgroup that
 //    accumulates the window's unitary U_w; the product of U_w^H with the rest of the window's
 //    rows inside the active block is applied at once (the next window reads it), while the
 //    updates of the rows above the window, of the columns right of the active block, and of Z
 //    are deferred to the end of the sweep and applied window after window by row/column-parallel
-//    kernels.  Active blocks of at most 64 rows are finished in LDS by one wave.
+//    kernels (those of Z on a second stream, since the iteration never reads Z).  Active blocks of at most 64 rows are finished in LDS by one wave.  Before each
+//    sweep, aggressive early deflation (Braman, Byers and Mathias, SIAM J. Matrix Anal. Appl. 23,
+//    2002) brings the trailing 32 x 32 window to Schur form in LDS, splits off the eigenvalues
+//    whose coupling to the rest of the matrix is below machine precision, and hands the window's
+//    remaining eigenvalues to the sweep as shifts; when many deflate the sweep is skipped.
 // 3. Eigenvectors of T by back substitution (one wave per column) and the inverse of the unit
 //    upper-triangular eigenvector matrix, giving the eigenbasis route G = U diag(s) U^{-1}.
 #include <vector>
@@ -22,9 +26,11 @@
 namespace lindx {
 
 static constexpr int WIN = 64;    // window rows
-static constexpr int STEP = 32;   // window advance
-static constexpr int NSMAX = 15;  // bulges per sweep (WIN >= STEP + 2*NSMAX + 1)
+static constexpr int STEP = 24;   // default window advance
+static constexpr int NSMAX = 19;  // default bulges per sweep (WIN >= step + 2 * bulges + 1)
+static constexpr int NSCAP = 23;  // most bulges one chase kernel holds
 static constexpr int MAXWIN = 256;
+static constexpr int AEDW = 32;   // default early-deflation window rows (<= WIN)
 
 struct WinList {
   int nwin;
@@ -229,7 +235,7 @@ __global__ __launch_bounds__(256) void k_chase(zd* A, int n, int ilo, int ihi, i
                                                 const zd* shifts, int ns, int* cnt, zd* Uout) {
   __shared__ zd Hs[WIN * LDM];
   __shared__ zd Us[WIN * LDM];
-  constexpr int BPW = (NSMAX + 3) / 4;  // bulges per wave
+  constexpr int BPW = (NSCAP + 3) / 4;  // bulges per wave
   const int t = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lane = t & 63;
@@ -366,18 +372,190 @@ __global__ __launch_bounds__(256) void k_chase(zd* A, int n, int ilo, int ihi, i
   }
 }
 
+// One wave loads the m x m diagonal block of A at (r0, r0) into Hs (row stride LDM) and sets Us
+// to the identity; loads are issued 16 rows at a time before their LDS stores.
+__device__ inline void load_window(const zd* A, int n, int r0, int m, zd* Hs, zd* Us) {
+  const int t = threadIdx.x & 63;
+  for (int i0 = 0; i0 < m; i0 += 16) {
+    zd v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = i0 + k;
+      v[k] = (i < m && t < m) ? A[(long long)(r0 + i) * n + r0 + t] : zmk(0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = i0 + k;
+      if (i < m && t < m) {
+        Hs[i * LDM + t] = v[k];
+        Us[i * LDM + t] = (i == t) ? zmk(1, 0) : zmk(0, 0);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Aggressive early deflation on the trailing window [kw, ihi] (jw = ihi - kw + 1 <= 64 rows, kw
+// above the first row of the active block, s = A[kw, kw-1] the entry that couples the window to
+// the rest).  The window is brought to Schur form T = V^H W V in LDS; the coupling column then
+// reads s V^H e_1, so the eigenvalue in position k of T decouples when |s| |V[0, k]| is below
+// machine precision relative to |T[k, k]|.  Deflations are counted from the bottom of T up to the
+// first one that fails the test (no reordering).  If none deflate, A is left unchanged.  Otherwise
+// the undeflated leading part is returned to Hessenberg form: a reflector P maps s conj(V[0, :nu])
+// to a multiple of e_1 (applied as P T P and V P), then Householder reduction of T[:nu, :nu]
+// (applied to the rows' full width and accumulated into V); the window, the coupling column and V
+// (into Uout, for the deferred updates outside the window) are written back.
+// res[0] = deflated count, res[1] = 1 if A was changed, res[2] = status of the window QR.
+// ritz[0 .. jw) = diagonal of T; its first jw - res[0] entries are the undeflated eigenvalues.
+__global__ __launch_bounds__(64) void k_aed(zd* A, int n, int kw, int ihi, zd* Uout, zd* ritz, int* res) {
+  __shared__ zd Hs[WIN * LDM];
+  __shared__ zd Us[WIN * LDM];
+  __shared__ zd hv[WIN];
+  __shared__ double red[2];
+  __shared__ int nd_s;
+  const double ulp = 2.220446049250313e-16;
+  const int jw = ihi - kw + 1;
+  const int t = threadIdx.x;
+  const zd s = A[(long long)kw * n + kw - 1];
+  load_window(A, n, kw, jw, Hs, Us);
+  const int rc = qr_lds(Hs, Us, jw, 1);
+  for (int i = 0; i < jw; ++i)
+    for (int j = t; j < i; j += 64) Hs[i * LDM + j] = zmk(0, 0);
+  __syncthreads();
+  if (t == 0) {
+    int nd = 0;
+    if (rc == 0) {
+      const double as = cabs1(s);
+      for (int k = jw - 1; k >= 0; --k) {
+        double foo = cabs1(Hs[k * LDM + k]);
+        if (foo == 0.0) foo = as;
+        if (as * cabs1(Us[k]) <= fmax(1e-300, ulp * foo)) ++nd;
+        else break;
+      }
+    }
+    nd_s = nd;
+    res[0] = nd;
+    res[1] = nd > 0 ? 1 : 0;
+    res[2] = rc;
+  }
+  for (int i = t; i < jw; i += 64) ritz[i] = Hs[i * LDM + i];
+  __syncthreads();
+  const int nd = nd_s, nu = jw - nd;
+  if (nd == 0) return;
+  if (nu > 1) {
+    // reflector P = I - 2 h h^H with P x = -ph |x| e_1, x = s conj(V[0, :nu])
+    if (t == 0) {
+      double nx2 = 0;
+      for (int i = 0; i < nu; ++i) nx2 += zabs2(Us[i]);
+      const double nx = sqrt(nx2) * sqrt(zabs2(s));
+      const zd x0 = zmul(s, zconj(Us[0]));
+      const double ax0 = sqrt(zabs2(x0));
+      const zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
+      red[0] = nx;
+      // |v|^2 = |x|^2 + 2 |x0| |x| + |x|^2
+      red[1] = 1.0 / sqrt(2.0 * nx * (nx + ax0));
+      hv[0] = zadd(x0, zscale(ph, nx));
+    }
+    __syncthreads();
+    for (int i = t + 1; i < nu; i += 64) hv[i] = zmul(s, zconj(Us[i]));
+    __syncthreads();
+    for (int i = t; i < nu; i += 64) hv[i] = zscale(hv[i], red[1]);
+    __syncthreads();
+    // T[:nu, :] = P T[:nu, :]   (lane = column)
+    for (int j = t; j < jw; j += 64) {
+      zd w = zmk(0, 0);
+      for (int i = 0; i < nu; ++i) w = zadd(w, zcmul(hv[i], Hs[i * LDM + j]));
+      w = zscale(w, 2.0);
+      for (int i = 0; i < nu; ++i) Hs[i * LDM + j] = zsub(Hs[i * LDM + j], zmul(hv[i], w));
+    }
+    __syncthreads();
+    // T[:nu, :nu] = T[:nu, :nu] P and V[:, :nu] = V[:, :nu] P   (lane = row)
+    for (int i = t; i < jw; i += 64) {
+      zd y = zmk(0, 0), yv = zmk(0, 0);
+      for (int j = 0; j < nu; ++j) {
+        if (i < nu) y = zadd(y, zmul(Hs[i * LDM + j], hv[j]));
+        yv = zadd(yv, zmul(Us[i * LDM + j], hv[j]));
+      }
+      y = zscale(y, 2.0);
+      yv = zscale(yv, 2.0);
+      for (int j = 0; j < nu; ++j) {
+        if (i < nu) Hs[i * LDM + j] = zsub(Hs[i * LDM + j], zmul(y, zconj(hv[j])));
+        Us[i * LDM + j] = zsub(Us[i * LDM + j], zmul(yv, zconj(hv[j])));
+      }
+    }
+    __syncthreads();
+    // Householder reduction of T[:nu, :nu] to Hessenberg form
+    for (int k = 0; k + 2 < nu; ++k) {
+      __syncthreads();
+      if (t == 0) {
+        double nrm2 = 0;
+        for (int i = k + 1; i < nu; ++i) nrm2 += zabs2(Hs[i * LDM + k]);
+        const zd x0 = Hs[(k + 1) * LDM + k];
+        const double ax0 = sqrt(zabs2(x0));
+        const double tail = nrm2 - ax0 * ax0;
+        if (tail > 0) {
+          const double nrm = sqrt(nrm2);
+          const zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
+          hv[k + 1] = zadd(x0, zscale(ph, nrm));
+          red[0] = 1.0 / (nrm * (nrm + ax0));  // gamma of I - gamma u u^H
+          red[1] = -nrm;
+          hv[0] = ph;
+        } else {
+          red[0] = 0.0;
+        }
+      }
+      __syncthreads();
+      const double gam = red[0];
+      if (gam != 0.0) {
+        for (int i = k + 2 + t; i < nu; i += 64) hv[i] = Hs[i * LDM + k];
+        __syncthreads();
+        // rows k+1 .. nu-1, columns k+1 .. jw-1 from the left
+        for (int j = k + 1 + t; j < jw; j += 64) {
+          zd w = zmk(0, 0);
+          for (int i = k + 1; i < nu; ++i) w = zadd(w, zcmul(hv[i], Hs[i * LDM + j]));
+          w = zscale(w, gam);
+          for (int i = k + 1; i < nu; ++i) Hs[i * LDM + j] = zsub(Hs[i * LDM + j], zmul(hv[i], w));
+        }
+        __syncthreads();
+        // columns k+1 .. nu-1 from the right: rows 0 .. nu-1 of T, all rows of V
+        for (int i = t; i < jw; i += 64) {
+          zd y = zmk(0, 0), yv = zmk(0, 0);
+          for (int j = k + 1; j < nu; ++j) {
+            if (i < nu) y = zadd(y, zmul(Hs[i * LDM + j], hv[j]));
+            yv = zadd(yv, zmul(Us[i * LDM + j], hv[j]));
+          }
+          y = zscale(y, gam);
+          yv = zscale(yv, gam);
+          for (int j = k + 1; j < nu; ++j) {
+            if (i < nu) Hs[i * LDM + j] = zsub(Hs[i * LDM + j], zmul(y, zconj(hv[j])));
+            Us[i * LDM + j] = zsub(Us[i * LDM + j], zmul(yv, zconj(hv[j])));
+          }
+        }
+        __syncthreads();
+        if (t == 0) Hs[(k + 1) * LDM + k] = zscale(hv[0], red[1]);
+        for (int i = k + 2 + t; i < nu; i += 64) Hs[i * LDM + k] = zmk(0, 0);
+        __syncthreads();
+      }
+    }
+  }
+  // write back: Hessenberg part T[:nu, :nu], triangular rest, the coupling column
+  for (int i = 0; i < jw; ++i)
+    for (int j = t; j < jw; j += 64) {
+      const bool keep = (j >= i) || (j == i - 1 && i < nu);
+      A[(long long)(kw + i) * n + kw + j] = keep ? Hs[i * LDM + j] : zmk(0, 0);
+      Uout[i * WIN + j] = Us[i * LDM + j];
+    }
+  for (int i = t; i < jw; i += 64)
+    A[(long long)(kw + i) * n + kw - 1] = (i == 0 && nu > 0) ? zmul(s, zconj(Us[0])) : zmk(0, 0);
+}
+
 // Finish an active block [lo, hi] (size <= 64) in LDS: Schur form of the block, unitary to Uout.
 __global__ __launch_bounds__(64) void k_small_block(zd* A, int n, int lo, int hi, zd* Uout, int* info) {
   __shared__ zd Hs[WIN * LDM];
   __shared__ zd Us[WIN * LDM];
   const int m = hi - lo + 1;
   const int t = threadIdx.x;
-  for (int i = 0; i < m; ++i)
-    for (int j = t; j < m; j += 64) {
-      Hs[i * LDM + j] = A[(long long)(lo + i) * n + lo + j];
-      Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
-    }
-  __syncthreads();
+  load_window(A, n, lo, m, Hs, Us);
   int rc = qr_lds(Hs, Us, m, 1);
   if (t == 0) info[0] = rc;
   for (int i = 0; i < m; ++i)
@@ -510,9 +688,16 @@ __global__ __launch_bounds__(256) void k_left_apply_seq(zd* A, int n, int c0, Wi
   }
 }
 
-static void apply_deferred(zd* A, zd* Z, int n, int hi, const WinList& wl, const zd* Ubuf, hipStream_t st) {
-  // Z: all rows
-  hipLaunchKernelGGL(k_right_apply_seq, dim3((n + 15) / 16), dim3(256), 0, st, Z, n, n, wl, Ubuf, 0);
+// Deferred updates of one sweep (or one early deflation / small block).  Z is never read by the
+// QR iteration, so its update runs on the side stream zs (ordered after the producers of the
+// window unitaries by `ready`; `done` tells the next user of this Ubuf half that it may be
+// overwritten); the updates of A stay on st.
+static void apply_deferred(zd* A, zd* Z, int n, int hi, const WinList& wl, const zd* Ubuf, hipStream_t st,
+                           hipStream_t zs, hipEvent_t ready, hipEvent_t done) {
+  hipEventRecord(ready, st);
+  hipStreamWaitEvent(zs, ready, 0);
+  hipLaunchKernelGGL(k_right_apply_seq, dim3((n + 15) / 16), dim3(256), 0, zs, Z, n, n, wl, Ubuf, 0);
+  hipEventRecord(done, zs);
   // A: rows above each window
   int maxr = 0;
   for (int w = 0; w < wl.nwin; ++w) maxr = wl.r[w] > maxr ? wl.r[w] : maxr;
@@ -528,26 +713,73 @@ int schur_factor(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_
   return schur_factor_ex(A, Z, n, st, t_hess, t_qr, 0);
 }
 
-int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int stop_after_hessenberg) {
+// mode bit 0: stop after the Hessenberg reduction; bits 8..15: early-deflation window (0: default,
+// 1: none, otherwise 16 .. 64 rows); bits 16..23: window advance (0: default, else 8 .. 48);
+// bits 24..30: most bulges per sweep (0: default, else 2 .. 23, and at most (63 - advance) / 2)
+int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int mode) {
+  const int stop_after_hessenberg = mode & 1;
+  int aedw = (mode >> 8) & 255;
+  if (aedw == 0) aedw = AEDW;
+  if (aedw != 1 && (aedw < 16 || aedw > WIN)) return -1;
+  int step = (mode >> 16) & 255;
+  if (step == 0) step = STEP;
+  int nsmax = (mode >> 24) & 127;
+  if (nsmax == 0) nsmax = NSMAX;
+  if (step < 8 || step > 48 || nsmax < 2 || nsmax > NSCAP || WIN < step + 2 * nsmax + 1) return -1;
+  // at most MAXWIN windows per sweep
+  while ((n + step - 1) / step + 2 > MAXWIN) ++step;
+  if (WIN < step + 2 * nsmax + 1) nsmax = (WIN - 1 - step) / 2;
+  if (nsmax < 2) return -1;
   if (n < 1) return -1;
-  if ((n + STEP - 1) / STEP + 2 > MAXWIN) return -1;
   zd *u = nullptr, *part = nullptr, *w = nullptr, *y = nullptr, *Ubuf = nullptr, *shifts = nullptr, *ds = nullptr;
+  hipStream_t zs = nullptr;
+  hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   double* gam = nullptr;
   int *cnt = nullptr, *info = nullptr;
   const int nrc = 16;
   auto cleanup = [&]() {
+    if (zs) hipStreamSynchronize(zs);
+    for (int b = 0; b < 2; ++b) {
+      if (ev_ready[b]) hipEventDestroy(ev_ready[b]);
+      if (ev_done[b]) hipEventDestroy(ev_done[b]);
+    }
+    if (zs) hipStreamDestroy(zs);
     hipFree(u); hipFree(part); hipFree(w); hipFree(y); hipFree(Ubuf); hipFree(shifts); hipFree(ds);
     hipFree(gam); hipFree(cnt); hipFree(info);
   };
   if (hipMalloc(&u, sizeof(zd) * n) != hipSuccess || hipMalloc(&part, sizeof(zd) * (size_t)nrc * n) != hipSuccess ||
       hipMalloc(&w, sizeof(zd) * n) != hipSuccess || hipMalloc(&y, sizeof(zd) * 2 * n) != hipSuccess ||
-      hipMalloc(&Ubuf, sizeof(zd) * (size_t)MAXWIN * WIN * WIN) != hipSuccess ||
-      hipMalloc(&shifts, sizeof(zd) * 64) != hipSuccess || hipMalloc(&ds, sizeof(zd) * 2 * n) != hipSuccess ||
+      hipMalloc(&Ubuf, sizeof(zd) * 2 * (size_t)MAXWIN * WIN * WIN) != hipSuccess ||
+      hipMalloc(&shifts, sizeof(zd) * 2 * WIN) != hipSuccess || hipMalloc(&ds, sizeof(zd) * 2 * n) != hipSuccess ||
       hipMalloc(&gam, sizeof(double) * 4) != hipSuccess || hipMalloc(&cnt, sizeof(int) * 64) != hipSuccess ||
       hipMalloc(&info, sizeof(int) * 4) != hipSuccess) {
     cleanup();
     return -5;
   }
+  if (hipStreamCreateWithFlags(&zs, hipStreamNonBlocking) != hipSuccess) {
+    zs = nullptr;
+    cleanup();
+    return -4;
+  }
+  for (int b = 0; b < 2; ++b) {
+    if (hipEventCreateWithFlags(&ev_ready[b], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_done[b], hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return -4;
+    }
+    hipEventRecord(ev_done[b], zs);
+  }
+  // the window unitaries of consecutive deferred updates alternate between two halves of Ubuf,
+  // so the side stream can still read one half while the next windows are written to the other
+  int ub = 0;
+  auto ubuf = [&]() {
+    hipStreamWaitEvent(st, ev_done[ub], 0);
+    return Ubuf + (long long)ub * MAXWIN * WIN * WIN;
+  };
+  auto deferred = [&](int hi, const WinList& wl, const zd* U) {
+    apply_deferred(A, Z, n, hi, wl, U, st, zs, ev_ready[ub], ev_done[ub]);
+    ub ^= 1;
+  };
   auto t0 = std::chrono::steady_clock::now();
   hipLaunchKernelGGL(k_identity, dim3(gridN((long long)n * n)), dim3(256), 0, st, Z, n);
   if (n > 2) hessenberg(A, Z, n, u, gam, part, w, y, st);
@@ -564,7 +796,8 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
   int ihi = n - 1;
   int stall = 0, sweeps = 0, last_ihi = -1, last_ilo = -1;
   int status = 0;
-  const long long max_sweeps = 20LL * n / NSMAX + 400;
+  const long long max_sweeps = 20LL * n / nsmax + 400;
+  int hres[4] = {0, 0, 0, 0};
   while (ihi > 0) {
     hipLaunchKernelGGL(k_extract_diag_sub, dim3((n + 255) / 256), dim3(256), 0, st, A, n, ds);
     if (hipMemcpyAsync(hds.data(), ds, sizeof(zd) * 2 * n, hipMemcpyDeviceToHost, st) != hipSuccess) { status = -4; break; }
@@ -584,14 +817,15 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
     if (ihi == last_ihi && ilo == last_ilo) ++stall; else stall = 0;
     last_ihi = ihi;
     last_ilo = ilo;
-    const int size = ihi - ilo + 1;
+    int size = ihi - ilo + 1;
     WinList wl;
     if (size <= WIN) {
-      hipLaunchKernelGGL(k_small_block, dim3(1), dim3(64), 0, st, A, n, ilo, ihi, Ubuf, info);
+      zd* U = ubuf();
+      hipLaunchKernelGGL(k_small_block, dim3(1), dim3(64), 0, st, A, n, ilo, ihi, U, info);
       wl.nwin = 1;
       wl.r[0] = ilo;
       wl.bw[0] = size;
-      apply_deferred(A, Z, n, ihi, wl, Ubuf, st);
+      deferred(ihi, wl, U);
       int hinfo = 0;
       hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st);
       hipStreamSynchronize(st);
@@ -600,17 +834,54 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
       continue;
     }
     if (++sweeps > max_sweeps) { status = -3; break; }
+    // aggressive early deflation on the trailing window; its undeflated eigenvalues are the
+    // next sweep's shifts
     int ns = size / 8;
-    if (ns > NSMAX) ns = NSMAX;
+    if (ns > nsmax) ns = nsmax;
     if (ns < 2) ns = 2;
+    const zd* sh = shifts + WIN;
+    bool need_shifts = true;
+    if (aedw > 1) {
+      const int jw = aedw;
+      const int kw = ihi - jw + 1;
+      zd* U = ubuf();
+      hipLaunchKernelGGL(k_aed, dim3(1), dim3(64), 0, st, A, n, kw, ihi, U, shifts, info + 1);
+      if (hipMemcpyAsync(hres, info + 1, sizeof(int) * 3, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) { status = -4; break; }
+      const int nd = hres[0];
+      if (hres[1]) {
+        wl.nwin = 1;
+        wl.r[0] = kw;
+        wl.bw[0] = jw;
+        deferred(ihi, wl, U);
+      }
+      if (nd > 0) stall = 0;
+      // many deflations: look again before sweeping
+      if (100 * nd > 14 * jw) continue;
+      ihi -= nd;
+      size = ihi - ilo + 1;
+      if (size <= WIN) continue;
+      ns = size / 8;
+      if (ns > nsmax) ns = nsmax;
+      if (ns < 2) ns = 2;
+      const int nu = jw - nd;
+      if (hres[2] == 0 && nu >= ns) {
+        sh = shifts + (nu - ns);
+        need_shifts = false;
+      }
+    }
     const int exceptional = (stall > 0 && stall % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(k_shifts, dim3(1), dim3(64), 0, st, A, n, ihi - ns + 1, ns, exceptional, shifts);
+    if (exceptional || need_shifts) {
+      hipLaunchKernelGGL(k_shifts, dim3(1), dim3(64), 0, st, A, n, ihi - ns + 1, ns, exceptional, shifts + WIN);
+      sh = shifts + WIN;
+    }
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, cnt, 64);
+    zd* U = ubuf();
     wl.nwin = 0;
-    for (int r = ilo;; r += STEP) {
+    for (int r = ilo;; r += step) {
       int bw = ihi + 1 - r < WIN ? ihi + 1 - r : WIN;
-      zd* Uw = Ubuf + (long long)wl.nwin * WIN * WIN;
-      hipLaunchKernelGGL(k_chase, dim3(1), dim3(256), 0, st, A, n, ilo, ihi, r, bw, shifts, ns, cnt, Uw);
+      zd* Uw = U + (long long)wl.nwin * WIN * WIN;
+      hipLaunchKernelGGL(k_chase, dim3(1), dim3(256), 0, st, A, n, ilo, ihi, r, bw, sh, ns, cnt, Uw);
       if (r + bw <= ihi)
         hipLaunchKernelGGL(k_left_apply, dim3((ihi - (r + bw) + 1 + 15) / 16), dim3(256), 0, st, A, n, r, bw, r + bw,
                            ihi, (const zd*)Uw);
@@ -619,9 +890,12 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
       ++wl.nwin;
       if (r + bw - 1 >= ihi) break;
     }
-    apply_deferred(A, Z, n, ihi, wl, Ubuf, st);
+    deferred(ihi, wl, U);
   }
   if (status == 0) hipLaunchKernelGGL(k_zero_lower, dim3(gridN((long long)n * n)), dim3(256), 0, st, A, n);
+  // Z is complete once the side stream's updates are
+  hipStreamWaitEvent(st, ev_done[0], 0);
+  hipStreamWaitEvent(st, ev_done[1], 0);
   hipStreamSynchronize(st);
   auto t2 = std::chrono::steady_clock::now();
   if (t_qr) *t_qr = std::chrono::duration<double>(t2 - t1).count();

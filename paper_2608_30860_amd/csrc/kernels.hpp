@@ -128,7 +128,7 @@ struct SchurWork;
 // In: A (n x n, overwritten by T, upper triangular), Z (n x n) out: Schur vectors, A = Z T Z^H
 // on entry A holds G.  Returns 0 on success, -3 if the QR iteration failed to converge.
 int schur_factor(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr);
-int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int stop_after_hessenberg);
+int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int mode);
 // Y: eigenvectors of upper-triangular T (unit diagonal), Yinv = Y^{-1} (unit upper triangular)
 int trevec(const zd* T, zd* Y, int n, hipStream_t st);
 int triinv_unit(const zd* Y, zd* Yinv, int n, hipStream_t st);

@@ -104,75 +104,113 @@ __device__ inline void hessenberg_lds(zd* A, zd* Q, int m, zd* u) {
   }
 }
 
+// Broadcast of lane l's complex value to the wave (l uniform): v_readlane into scalar registers.
+__device__ inline zd zreadlane(zd v, int l) {
+  const long long xr = __double_as_longlong(v.x), xi = __double_as_longlong(v.y);
+  const int a0 = __builtin_amdgcn_readlane((int)xr, l), a1 = __builtin_amdgcn_readlane((int)(xr >> 32), l);
+  const int b0 = __builtin_amdgcn_readlane((int)xi, l), b1 = __builtin_amdgcn_readlane((int)(xi >> 32), l);
+  return zmk(__longlong_as_double(((long long)a1 << 32) | (unsigned)a0),
+             __longlong_as_double(((long long)b1 << 32) | (unsigned)b0));
+}
+
 // Complex single-shift QR (Wilkinson shifts, exceptional shifts every 10 stalled sweeps) on an
-// m x m upper Hessenberg matrix in LDS.  With full != 0 the whole rows/columns are updated so
-// the result is the Schur form T = Q^H H Q; Q (if non-null) accumulates the rotations.
-// Returns 0 on convergence, 1 otherwise.
+// m x m upper Hessenberg matrix in LDS, m <= 64, run by ONE wave of 64 lanes.  With full != 0 the
+// whole rows/columns are updated so the result is the Schur form T = Q^H H Q; Q (if non-null)
+// accumulates the rotations.  Returns 0 on convergence, 1 otherwise.
+//
+// Lane j owns column j in a row rotation and row j in a column rotation.  The next rotation's
+// input (column p, rows p+1 and p+2) comes out of the current column rotation in lanes p+1 and
+// p+2 and is handed on by v_readlane, so each rotation costs two LDS round trips; one wave's LDS
+// operations complete in order, so no barrier is needed between the phases.  The deflation test
+// looks at all subdiagonal entries at once (one lane each) and takes the lowest split point from
+// a ballot.
 __device__ inline int qr_lds(zd* H, zd* Q, int m, int full) {
   const double ulp = 2.220446049250313e-16;
   const double smlnum = 1e-300;
+  const int lane = threadIdx.x & 63;
   int ihi = m - 1;
   int its = 0, total = 0;
+  __syncthreads();
   while (ihi > 0) {
-    wsync();
-    int l = ihi;
-    for (; l > 0; --l) {
-      zd sub = H[l * LDM + l - 1];
-      double tst = cabs1(H[(l - 1) * LDM + l - 1]) + cabs1(H[l * LDM + l]);
-      if (cabs1(sub) <= fmax(ulp * tst, smlnum)) break;
+    bool negl = false;
+    if (lane >= 1 && lane <= ihi) {
+      const zd sub = H[lane * LDM + lane - 1];
+      const double tst = cabs1(H[(lane - 1) * LDM + lane - 1]) + cabs1(H[lane * LDM + lane]);
+      negl = cabs1(sub) <= fmax(ulp * tst, smlnum);
     }
-    wsync();
-    if (l > 0 && (threadIdx.x & 63) == 0) H[l * LDM + l - 1] = zmk(0, 0);
-    wsync();
+    const unsigned long long bal = __ballot(negl);
+    const int l = bal ? 63 - __clzll(bal) : 0;
+    if (l > 0 && lane == 0) H[l * LDM + l - 1] = zmk(0, 0);
     if (l == ihi) {
       ihi -= 1;
       its = 0;
       continue;
     }
-    if (++total > 60 * m + 200) return 1;
-    // shift
+    if (++total > 60 * m + 200) {
+      __syncthreads();
+      return 1;
+    }
     zd sigma;
-    zd a = H[(ihi - 1) * LDM + ihi - 1], b = H[(ihi - 1) * LDM + ihi];
-    zd c = H[ihi * LDM + ihi - 1], d = H[ihi * LDM + ihi];
+    const zd a = H[(ihi - 1) * LDM + ihi - 1], b = H[(ihi - 1) * LDM + ihi];
+    const zd c = H[ihi * LDM + ihi - 1], d = H[ihi * LDM + ihi];
     if (its == 10 || its == 20) {
       sigma = zadd(d, zmk(1.5 * cabs1(c), 0.0));
     } else {
       // eigenvalue of [[a, b], [c, d]] nearest d
-      zd hm = zscale(zsub(a, d), 0.5);
-      zd disc = zadd(zmul(hm, hm), zmul(b, c));
-      // principal sqrt
-      double r = sqrt(sqrt(zabs2(disc)));
-      double th = 0.5 * atan2(disc.y, disc.x);
-      zd sq = zmk(r * cos(th), r * sin(th));
-      zd e1 = zadd(zadd(d, hm), sq), e2 = zsub(zadd(d, hm), sq);
+      const zd hm = zscale(zsub(a, d), 0.5);
+      const zd disc = zadd(zmul(hm, hm), zmul(b, c));
+      // principal square root of disc (non-negative real part) without trigonometry
+      const double ad = sqrt(zabs2(disc));
+      zd sq = zmk(0, 0);
+      if (ad > 0) {
+        if (disc.x >= 0) {
+          const double re = sqrt(0.5 * (ad + disc.x));
+          sq = zmk(re, disc.y / (2.0 * re));
+        } else {
+          const double im = copysign(sqrt(0.5 * (ad - disc.x)), disc.y);
+          sq = zmk(disc.y / (2.0 * im), im);
+        }
+      }
+      const zd e1 = zadd(zadd(d, hm), sq), e2 = zsub(zadd(d, hm), sq);
       sigma = (zabs2(zsub(e1, d)) <= zabs2(zsub(e2, d))) ? e1 : e2;
     }
     ++its;
-    const int c0full = full ? 0 : l;
-    const int c1full = full ? m - 1 : ihi;
+    const int c1 = full ? m - 1 : ihi;
+    const int r0 = full ? 0 : l;
+    zd f = zsub(H[l * LDM + l], sigma);
+    zd g = H[(l + 1) * LDM + l];
     for (int p = l; p < ihi; ++p) {
-      zd f, g;
-      if (p == l) {
-        f = zsub(H[l * LDM + l], sigma);
-        g = H[(l + 1) * LDM + l];
-      } else {
-        f = H[p * LDM + p - 1];
-        g = H[(p + 1) * LDM + p - 1];
-      }
       double cs;
       zd sn, rr;
       zlartg(f, g, cs, sn, rr);
-      wsync();
-      rot_rows(H, LDM, p, (p == l) ? l : p - 1, c1full, cs, sn);
-      wsync();
-      int r1 = p + 2 < ihi ? p + 2 : ihi;
-      rot_cols(H, LDM, p, c0full, r1, cs, sn);
-      if (Q) rot_cols(Q, LDM, p, 0, m - 1, cs, sn);
-      wsync();
-      if (p > l && (threadIdx.x & 63) == 0) H[(p + 1) * LDM + p - 1] = zmk(0, 0);
+      // rows p, p+1 from column c0; the chased entry (p+1, p-1) becomes exactly zero
+      const int c0 = (p == l) ? l : p - 1;
+      if (lane >= c0 && lane <= c1) {
+        const zd x = H[p * LDM + lane], y = H[(p + 1) * LDM + lane];
+        H[p * LDM + lane] = zadd(zscale(x, cs), zmul(sn, y));
+        H[(p + 1) * LDM + lane] = (p > l && lane == p - 1) ? zmk(0, 0) : zsub(zscale(y, cs), zmul(zconj(sn), x));
+      }
+      // columns p, p+1 for rows r0 .. min(p+2, ihi), and of Q
+      const int r1 = p + 2 < ihi ? p + 2 : ihi;
+      zd nx = zmk(0, 0);
+      if (lane >= r0 && lane <= r1) {
+        const zd x = H[lane * LDM + p], y = H[lane * LDM + p + 1];
+        nx = zadd(zscale(x, cs), zmul(zconj(sn), y));
+        H[lane * LDM + p] = nx;
+        H[lane * LDM + p + 1] = zsub(zscale(y, cs), zmul(sn, x));
+      }
+      if (Q && lane < m) {
+        const zd x = Q[lane * LDM + p], y = Q[lane * LDM + p + 1];
+        Q[lane * LDM + p] = zadd(zscale(x, cs), zmul(zconj(sn), y));
+        Q[lane * LDM + p + 1] = zsub(zscale(y, cs), zmul(sn, x));
+      }
+      if (p + 1 < ihi) {
+        f = zreadlane(nx, p + 1);
+        g = zreadlane(nx, p + 2);
+      }
     }
   }
-  wsync();
+  __syncthreads();
   return 0;
 }
 

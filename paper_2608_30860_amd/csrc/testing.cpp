@@ -32,12 +32,12 @@ extern "C" int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void*
 }
 
 namespace lindx {
-int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int stop_after_hessenberg);
+int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int mode);
 }
 
-extern "C" int lindx_schur(void* A, void* Z, int n, int stop_after_hessenberg, void* stream) {
+extern "C" int lindx_schur(void* A, void* Z, int n, int mode, void* stream) {
   if (!A || !Z || n < 1) return -1;
-  return schur_factor_ex((zd*)A, (zd*)Z, n, (hipStream_t)stream, nullptr, nullptr, stop_after_hessenberg);
+  return schur_factor_ex((zd*)A, (zd*)Z, n, (hipStream_t)stream, nullptr, nullptr, mode);
 }
 
 extern "C" int lindx_small_eig(const void* A, int m, void* w, void* Y, void* stream) {
@@ -139,3 +139,4 @@ extern "C" int lindx_p4_test(const void* A, const void* B, int M, int N, int K, 
     if (p) hipFree(p);
   return rc;
 }
+
