@@ -522,17 +522,24 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   } else {
     hipLaunchKernelGGL(k_fill_identity_scaled, dim3(1024), dim3(256), 0, c.st, X->rhoB, n, 1.0 / n);
   }
-  TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, X->rhoB, n, OP_N, X->xiB, n, mone, 0));
-  TRY(op_gemm(c, PREC_F64, n, n, n, X->rhoB, n, OP_N, c.G, n, OP_C, X->xiB, n, mone, 1));
-  double xin = 0;
-  TRY(op_nrm(c, X->xiB, &xin));
-  if (!(xin > 0) || !std::isfinite(xin)) return c.fail(LIND_EINVAL, "start state gives xi_0 = 0 or non-finite");
-  cplx tr0;
-  TRY(op_trace(c, X->rhoB, &tr0));
-  double c_scale = std::sqrt((double)n) * xin / std::max(std::abs(tr0), 1e-300);
-  TRY(copy(X->xiB, K, n2, c.st));
-  TRY(op_nrm(c, K, &xin));
-  TRY(scale_by_inv(K, n2, (const double*)c.dsc, c.st));
+  // first Krylov vector xi = -S(rho) / ||.|| from the state in rhoB; c_scale converts the Ritz
+  // residual estimate into a bound on the state's residual
+  double c_scale = 1.0;
+  auto start_from_rho = [&]() -> int {
+    TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, X->rhoB, n, OP_N, X->xiB, n, mone, 0));
+    TRY(op_gemm(c, PREC_F64, n, n, n, X->rhoB, n, OP_N, c.G, n, OP_C, X->xiB, n, mone, 1));
+    double xin = 0;
+    TRY(op_nrm(c, X->xiB, &xin));
+    if (!(xin > 0) || !std::isfinite(xin)) return c.fail(LIND_EINVAL, "start state gives xi_0 = 0 or non-finite");
+    cplx tr0;
+    TRY(op_trace(c, X->rhoB, &tr0));
+    c_scale = std::sqrt((double)n) * xin / std::max(std::abs(tr0), 1e-300);
+    TRY(copy(X->xiB, K, n2, c.st));
+    TRY(op_nrm(c, K, &xin));
+    TRY(scale_by_inv(K, n2, (const double*)c.dsc, c.st));
+    return 0;
+  };
+  TRY(start_from_rho());
 
   const double eps_floor = (p == PREC_F64) ? 0.0 : (p == PREC_F32 ? 1e-6 : 3e-4);
   double best = 1e300, best_max = 0;
@@ -541,121 +548,150 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   double colsum = 0, mx = 0, fro = 0;
   bool floor_hit = false;
   bool best_is_last = false;  // rhoB / resB hold the best state and its FP64 residual
-  for (int rs = 0; rs < c.opts.max_restarts && !converged; ++rs) {
-    std::fill(Hh.begin(), Hh.end(), cplx(0));
-    int k = 0, sel = 0;
-    double est = 1e300;
-    for (int j = 0; j < m; ++j) {
-      zd* vj = K + (long long)j * n2;
-      zd* wv = K + (long long)(j + 1) * n2;
-      TRY(op_phi(c, vj, wv, p, true));  // Krylov vectors of a Hermitian start stay Hermitian
-      ++inf.n_phi;
-      zd* h1 = c.dsc + 8;
-      zd* h2 = c.dsc + 80;
-      TRY(multi_dot(K, n2, j + 1, wv, n2, h1, (zd*)c.dscr, c.st));
-      TRY(multi_axpy(K, n2, j + 1, h1, wv, n2, 1, -1.0, c.st));
-      TRY(multi_dot(K, n2, j + 1, wv, n2, h2, (zd*)c.dscr, c.st));
-      TRY(multi_axpy(K, n2, j + 1, h2, wv, n2, 1, -1.0, c.st));
-      TRY(nrm2(wv, n2, (double*)(c.dsc + 4), c.dscr, c.st));
-      TRY(c.fetch(c.dsc, sizeof(zd) * 160));
-      double hn = ((const double*)(c.hsc + 4))[0];
-      for (int i = 0; i <= j; ++i)
-        Hh[(size_t)i * m + j] = cplx(c.hsc[8 + i].x + c.hsc[80 + i].x, c.hsc[8 + i].y + c.hsc[80 + i].y);
-      Hh[(size_t)(j + 1) * m + j] = hn;
-      if (hn > 0) TRY(scale_by_inv(wv, n2, (const double*)(c.dsc + 4), c.st));
-      k = j + 1;
-      bool check = (k >= 3 && (k % 2 == 1)) || k == m || hn == 0.0;
-      if (check) {
-        int rc = small_eig_host(X, Hh, m, k, w, Y);
-        if (rc && rc != LIND_ENOCONV) return rc;
-        sel = pick_nearest_one(w);
-        cplx th = w[sel];
-        cplx ylast = Y[(size_t)(k - 1) * k + sel];
-        est = std::sqrt(std::norm(th - 1.0) + hn * hn * std::norm(ylast));
-        if (c_scale * est <= std::max(0.25 * tol, eps_floor) || hn == 0.0) break;
+  int restarts_left = c.opts.max_restarts;
+  // pass 0: restarted Arnoldi until the tolerance, its estimate's floor, or (FP64) a residual that
+  // oscillates without progress, then refinement on the FP64 residual.  If refinement stalls
+  // short of the tolerance after an oscillation stop, pass 1 resumes the restarted Arnoldi from
+  // the best state with the oscillation stop switched off.
+  for (int pass = 0; pass < 2 && !converged; ++pass) {
+    bool oscillation_stop = false;
+    double gain_ref = 1e300, prev_colsum = 1e300;
+    int restart_stall = 0;
+    floor_hit = false;
+    for (int rs = 0; restarts_left > 0 && !converged; ++rs) {
+      --restarts_left;
+      std::fill(Hh.begin(), Hh.end(), cplx(0));
+      int k = 0, sel = 0;
+      double est = 1e300;
+      for (int j = 0; j < m; ++j) {
+        zd* vj = K + (long long)j * n2;
+        zd* wv = K + (long long)(j + 1) * n2;
+        TRY(op_phi(c, vj, wv, p, true));  // Krylov vectors of a Hermitian start stay Hermitian
+        ++inf.n_phi;
+        zd* h1 = c.dsc + 8;
+        zd* h2 = c.dsc + 80;
+        TRY(multi_dot(K, n2, j + 1, wv, n2, h1, (zd*)c.dscr, c.st));
+        TRY(multi_axpy(K, n2, j + 1, h1, wv, n2, 1, -1.0, c.st));
+        TRY(multi_dot(K, n2, j + 1, wv, n2, h2, (zd*)c.dscr, c.st));
+        TRY(multi_axpy(K, n2, j + 1, h2, wv, n2, 1, -1.0, c.st));
+        TRY(nrm2(wv, n2, (double*)(c.dsc + 4), c.dscr, c.st));
+        TRY(c.fetch(c.dsc, sizeof(zd) * 160));
+        double hn = ((const double*)(c.hsc + 4))[0];
+        for (int i = 0; i <= j; ++i)
+          Hh[(size_t)i * m + j] = cplx(c.hsc[8 + i].x + c.hsc[80 + i].x, c.hsc[8 + i].y + c.hsc[80 + i].y);
+        Hh[(size_t)(j + 1) * m + j] = hn;
+        if (hn > 0) TRY(scale_by_inv(wv, n2, (const double*)(c.dsc + 4), c.st));
+        k = j + 1;
+        bool check = (k >= 3 && (k % 2 == 1)) || k == m || hn == 0.0;
+        if (check) {
+          int rc = small_eig_host(X, Hh, m, k, w, Y);
+          if (rc && rc != LIND_ENOCONV) return rc;
+          sel = pick_nearest_one(w);
+          cplx th = w[sel];
+          cplx ylast = Y[(size_t)(k - 1) * k + sel];
+          est = std::sqrt(std::norm(th - 1.0) + hn * hn * std::norm(ylast));
+          if (c_scale * est <= std::max(0.25 * tol, eps_floor) || hn == 0.0) break;
+        }
+        if (deadline > 0 && now_s() > deadline) break;
       }
-      if (deadline > 0 && now_s() > deadline) break;
-    }
-    // Ritz vector xi = V_k y
-    std::vector<cplx> ysel(k);
-    for (int i = 0; i < k; ++i) ysel[i] = Y[(size_t)i * k + sel];
-    TRY(upload_vec(X, ysel.data(), k, X->yv));
-    TRY(multi_axpy(K, n2, k, X->yv, X->xiB, n2, 0, 1.0, c.st));
-    // the fixed point xi = -S(rho_inf) is Hermitian: keep the restart vector Hermitian
-    TRY(hermitize(X->xiB, n, 0, nullptr, c.dscr, c.st));
-    // rho = -S^{-1} xi, hermitised and normalised (the sign cancels in the normalisation)
-    TRY(op_sinv(c, X->xiB, X->rhoB, cplx(0, 0), p, false));
-    cplx trb;
-    TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, &trb));
-    ++inf.n_restarts;
-    double xn = 0;
-    TRY(op_nrm(c, X->xiB, &xn));
-    if (std::abs(trb) > 0) c_scale = std::sqrt((double)n) * xn / std::abs(trb);
-    best_is_last = colsum < best;
-    if (colsum < best) {
-      best = colsum;
-      best_max = mx;
-      TRY(copy(X->rhoB, (zd*)rho_out, n2, c.st));
-    }
-    if (colsum <= tol) { converged = true; break; }
-    if (c_scale * est <= std::max(0.25 * tol, eps_floor) || p != PREC_F64) { floor_hit = true; break; }
-    if (deadline > 0 && now_s() > deadline) break;
-    // restart from xi
-    TRY(copy(X->xiB, K, n2, c.st));
-    TRY(op_nrm(c, K, &xn));
-    TRY(scale_by_inv(K, n2, (const double*)c.dsc, c.st));
-  }
-  // FP64 iterative refinement: (I - Phi_p) zeta = L rho, rho <- rho - S_p^{-1} zeta
-  if (!converged && (floor_hit || true)) {
-    // continue from the best state; when it is the last one evaluated, rhoB and its residual in
-    // resB are already in place
-    if (!best_is_last) {
-      TRY(copy((const zd*)rho_out, X->rhoB, n2, c.st));
-      TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
-    } else {
-      colsum = best;
-    }
-    double prev = colsum;
-    int stagn = 0;
-    const double floor_inner = (p == PREC_F64) ? 1e-13 : (p == PREC_F32 ? 3e-6 : 1e-4);
-    std::function<int(const zd*, zd*)> Aop = [&](const zd* in, zd* out) -> int {
-      int rc = op_phi(c, in, out, p, true);  // GMRES on a Hermitian right-hand side
-      if (rc) return rc;
-      ++inf.n_phi;
-      return axpby(zmk(1, 0), in, zmk(-1, 0), out, n2, c.st) ? LIND_EDEVICE : 0;
-    };
-    // inner solves: GMRES(m) first; once one misses its tolerance the map is treated as strongly
-    // non-normal and the remaining solves use one long cycle (basis in HBM)
-    int m_ref = m;
-    bool long_mode = false;
-    for (int it = 0; it < c.opts.refine_max && !converged; ++it) {
-      if (deadline > 0 && now_s() > deadline) break;
-      double rtol = std::min(0.1, std::max(floor_inner, 0.05 * tol / std::max(colsum, 1e-300)));
-      GmresResult gr;
-      int grc = gmres_rec(X, Aop, nullptr, X->resB, X->zetaB, true, m_ref, 0, 2, rtol, 0.0, c.rec, gr, deadline);
-      if (grc) {
-        if (long_mode) release_long_basis(c);
-        return grc;
-      }
-      inf.n_inner += gr.iters;
-      if (!gr.converged && !gr.stagnated && !long_mode) {
-        long_mode = true;
-        m_ref = long_cycle_len(c, 256, false);
-      }
-      TRY(op_sinv(c, X->zetaB, X->delB, cplx(0, 0), p, false));
-      TRY(axpby(zmk(-1, 0), X->delB, zmk(1, 0), X->rhoB, n2, c.st));
-      TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
-      ++inf.n_refine;
+      // Ritz vector xi = V_k y
+      std::vector<cplx> ysel(k);
+      for (int i = 0; i < k; ++i) ysel[i] = Y[(size_t)i * k + sel];
+      TRY(upload_vec(X, ysel.data(), k, X->yv));
+      TRY(multi_axpy(K, n2, k, X->yv, X->xiB, n2, 0, 1.0, c.st));
+      // the fixed point xi = -S(rho_inf) is Hermitian: keep the restart vector Hermitian
+      TRY(hermitize(X->xiB, n, 0, nullptr, c.dscr, c.st));
+      // rho = -S^{-1} xi, hermitised and normalised (the sign cancels in the normalisation)
+      TRY(op_sinv(c, X->xiB, X->rhoB, cplx(0, 0), p, false));
+      cplx trb;
+      TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, &trb));
+      ++inf.n_restarts;
+      double xn = 0;
+      TRY(op_nrm(c, X->xiB, &xn));
+      if (std::abs(trb) > 0) c_scale = std::sqrt((double)n) * xn / std::abs(trb);
+      best_is_last = colsum < best;
       if (colsum < best) {
         best = colsum;
         best_max = mx;
         TRY(copy(X->rhoB, (zd*)rho_out, n2, c.st));
       }
       if (colsum <= tol) { converged = true; break; }
-      if (colsum > 0.5 * prev) { if (++stagn >= 2) break; } else stagn = 0;
-      prev = colsum;
+      if (c_scale * est <= std::max(0.25 * tol, eps_floor) || p != PREC_F64) { floor_hit = true; break; }
+      // a residual that goes up again three times before the best one halves marks the rounding
+      // floor of the restarted iteration (slow convergence keeps decreasing): refinement on the FP64
+      // residual takes over
+      if (colsum < 0.5 * gain_ref) {
+        gain_ref = colsum;
+        restart_stall = 0;
+      } else if (pass == 0 && p == PREC_F64 && colsum >= 0.95 * prev_colsum && ++restart_stall >= 3) {
+        floor_hit = true;
+        oscillation_stop = true;
+        break;
+      }
+      prev_colsum = colsum;
+      if (deadline > 0 && now_s() > deadline) break;
+      // restart from xi
+      TRY(copy(X->xiB, K, n2, c.st));
+      TRY(op_nrm(c, K, &xn));
+      TRY(scale_by_inv(K, n2, (const double*)c.dsc, c.st));
     }
-    if (long_mode) release_long_basis(c);
+    // FP64 iterative refinement: (I - Phi_p) zeta = L rho, rho <- rho - S_p^{-1} zeta
+    if (!converged && (floor_hit || true)) {
+      // continue from the best state; when it is the last one evaluated, rhoB and its residual in
+      // resB are already in place
+      if (!best_is_last) {
+        TRY(copy((const zd*)rho_out, X->rhoB, n2, c.st));
+        TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
+      } else {
+        colsum = best;
+      }
+      double prev = colsum;
+      int stagn = 0;
+      const double floor_inner = (p == PREC_F64) ? 1e-13 : (p == PREC_F32 ? 3e-6 : 1e-4);
+      std::function<int(const zd*, zd*)> Aop = [&](const zd* in, zd* out) -> int {
+        int rc = op_phi(c, in, out, p, true);  // GMRES on a Hermitian right-hand side
+        if (rc) return rc;
+        ++inf.n_phi;
+        return axpby(zmk(1, 0), in, zmk(-1, 0), out, n2, c.st) ? LIND_EDEVICE : 0;
+      };
+      // inner solves: GMRES(m) first; once one misses its tolerance the map is treated as strongly
+      // non-normal and the remaining solves use one long cycle (basis in HBM)
+      int m_ref = m;
+      bool long_mode = false;
+      for (int it = 0; it < c.opts.refine_max && !converged; ++it) {
+        if (deadline > 0 && now_s() > deadline) break;
+        double rtol = std::min(0.1, std::max(floor_inner, 0.05 * tol / std::max(colsum, 1e-300)));
+        GmresResult gr;
+        int grc = gmres_rec(X, Aop, nullptr, X->resB, X->zetaB, true, m_ref, 0, 2, rtol, 0.0, c.rec, gr, deadline);
+        if (grc) {
+          if (long_mode) release_long_basis(c);
+          return grc;
+        }
+        inf.n_inner += gr.iters;
+        if (!gr.converged && !gr.stagnated && !long_mode) {
+          long_mode = true;
+          m_ref = long_cycle_len(c, 256, false);
+        }
+        TRY(op_sinv(c, X->zetaB, X->delB, cplx(0, 0), p, false));
+        TRY(axpby(zmk(-1, 0), X->delB, zmk(1, 0), X->rhoB, n2, c.st));
+        TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, nullptr));
+        ++inf.n_refine;
+        if (colsum < best) {
+          best = colsum;
+          best_max = mx;
+          TRY(copy(X->rhoB, (zd*)rho_out, n2, c.st));
+        }
+        if (colsum <= tol) { converged = true; break; }
+        if (colsum > 0.5 * prev) { if (++stagn >= 2) break; } else stagn = 0;
+        prev = colsum;
+      }
+      if (long_mode) release_long_basis(c);
+    }
+    if (converged || !oscillation_stop || restarts_left <= 0) break;
+    if (deadline > 0 && now_s() > deadline) break;
+    TRY(copy((const zd*)rho_out, X->rhoB, n2, c.st));
+    TRY(start_from_rho());
+    best_is_last = false;
   }
   TRY(c.sync());
   inf.resid_trace = best;

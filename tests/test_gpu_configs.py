@@ -254,8 +254,10 @@ def test_random1024_full_matrix_gradients_fd():
     h = 1e-6
 
     def Jof(Hh, Lh):
+        # central differences at h = 1e-6 need J to ~1e-13 and better: the FD primal solves run
+        # to the rounding floor of the FP64 residual
         mm = make(Hh, Lh)
-        rho = N(mm.steady_state(1e-13, raise_on_noconv=False).rho)
+        rho = N(mm.steady_state(1e-14, raise_on_noconv=False).rho)
         mm.close()
         return og.expectation(O, rho)
 
