@@ -145,14 +145,8 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
     }
 
   const int kq = lane >> 4;
-  if (total > 0) issue(0, 0);
-  for (int it = 0; it < total; ++it) {
-    const int buf = it & 1;
-    // the loads of this stage have landed (the barrier waits for every outstanding load), and
-    // every wave is done with the other buffer, which the next stage may now overwrite
-    __syncthreads();
-    if (it + 1 < total) issue(it + 1, buf ^ 1);
-    v8bf_p a[4][4], bb[TNW][4];
+  // operand fragments of one stage: A rows wm0 + 16 i, B rows wn0 + 16 j, all four planes
+  auto frags = [&](int buf, v8bf_p (&a)[4][4], v8bf_p (&bb)[TNW][4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = wm0 + i * 16 + (lane & 15);
@@ -167,13 +161,11 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
       for (int p = 0; p < 4; ++p) bb[j][p] = *(const v8bf_p*)&S[buf][1][p][r][slot_of(r, kq) * 8];
       if (CONJ_B) { bb[j][2] = neg8(bb[j][2]); bb[j][3] = neg8(bb[j][3]); }
     }
-    // -Ai for the real part
-    v8bf_p an[4][2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { an[i][0] = neg8(a[i][2]); an[i][1] = neg8(a[i][3]); }
-    // re += Ar Br - Ai Bi, im += Ar Bi + Ai Br; each group issues 16 independent MFMAs.
-    // SWAP computes the transposed tile (B fragment as the MFMA row operand), so that a lane's
-    // four accumulator entries run along n instead of m.
+  };
+  // re += Ar Br - Ai Bi, im += Ar Bi + Ai Br; each group issues 4 TNW independent MFMAs.
+  // SWAP computes the transposed tile (B fragment as the MFMA row operand), so that a lane's
+  // four accumulator entries run along n instead of m.
+  auto compute = [&](v8bf_p (&a)[4][4], v8bf_p (&bb)[TNW][4]) {
 #define P4_GROUP(ACC, AF, BP)                                                          \
   _Pragma("unroll") for (int i = 0; i < 4; ++i)                                        \
     _Pragma("unroll") for (int j = 0; j < TNW; ++j) ACC[i][j] =                        \
@@ -184,13 +176,27 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
     P4_GROUP(ci, a[i][0], 3)
     P4_GROUP(cr, a[i][1], 0)
     P4_GROUP(ci, a[i][1], 2)
-    P4_GROUP(cr, an[i][0], 2)
     P4_GROUP(ci, a[i][2], 0)
-    P4_GROUP(cr, an[i][0], 3)
     P4_GROUP(ci, a[i][2], 1)
-    P4_GROUP(cr, an[i][1], 2)
     P4_GROUP(ci, a[i][3], 0)
+    // the fragments die with this stage: negate Ai in place for the real part
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { a[i][2] = neg8(a[i][2]); a[i][3] = neg8(a[i][3]); }
+    P4_GROUP(cr, a[i][2], 2)
+    P4_GROUP(cr, a[i][2], 3)
+    P4_GROUP(cr, a[i][3], 2)
 #undef P4_GROUP
+  };
+  if (total > 0) issue(0, 0);
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    // the loads of this stage have landed (the barrier waits for every outstanding load), and
+    // every wave is done with the other buffer, which the next stage may now overwrite
+    __syncthreads();
+    if (it + 1 < total) issue(it + 1, buf ^ 1);
+    v8bf_p a[4][4], bb[TNW][4];
+    frags(buf, a, bb);
+    compute(a, bb);
   }
 
   // epilogue.  Normal: lane holds rows m = ..+4*(lane>>4)+r at column n = ..+(lane&15).
@@ -366,16 +372,20 @@ __global__ __launch_bounds__(256) void k_p4_join(const __bf16* __restrict__ P, l
   }
 }
 
-template <bool SWAP, int OUT>
-int launch_p4_out(const P4Desc& g, int blocks, hipStream_t st) {
-  // 8 waves per block (two per SIMD) hide the LDS-read latency of one wave behind the other's
-  // matrix-core work
-  constexpr int NW = 8;
+template <int NW, bool SWAP, int OUT>
+int launch_p4_nw(const P4Desc& g, int blocks, hipStream_t st) {
   if (g.conjA && g.conjB) hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, true, true, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
   else if (g.conjA) hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, true, false, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
   else if (g.conjB) hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, false, true, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
   else hipLaunchKernelGGL((k_p4_gemm<NW, SWAP, false, false, OUT>), dim3(blocks), dim3(64 * NW), 0, st, g);
   return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+template <bool SWAP, int OUT>
+int launch_p4_out(const P4Desc& g, int blocks, hipStream_t st) {
+  // 8 waves per block (two per SIMD) hide the LDS-read latency of one wave behind the other's
+  // matrix-core work
+  return launch_p4_nw<8, SWAP, OUT>(g, blocks, st);
 }
 
 }  // namespace
