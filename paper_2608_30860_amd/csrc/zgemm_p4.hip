@@ -39,9 +39,11 @@ __device__ inline v4f_p mfma16(v8bf_p a, v8bf_p b, v4f_p c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// 16-byte k chunk q of local row r sits in slot (q ^ ((r >> 2) & 3)) of the 64-byte LDS row, so
-// that the 16 rows an MFMA operand read touches fall in distinct bank groups
-__device__ inline int slot_of(int r, int q) { return q ^ ((r >> 2) & 3); }
+// 16-byte k chunk q of local row r sits in slot q ^ ((r >> 1) & 3) of the 64-byte LDS row.  An
+// operand read takes 16 consecutive rows at one q (lane = row + 16 q); with this placement the
+// read raises no LDS bank conflict on gfx950 (checked with the SQ_LDS_BANK_CONFLICT counter
+// against the unswizzled and other XOR placements, which all conflict).
+__device__ inline int slot_of(int r, int q) { return q ^ ((r >> 1) & 3); }
 
 // XCD-aware tile order: consecutive workgroup ids go to different XCDs (round robin over 8), so
 // ids congruent mod 8 get a contiguous run of tiles.  When that run is whole tile rows, it is
