@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the resolvent / implicit Euler measurement")
+    ap.add_argument("--no-configs", action="store_true", help="skip the Phi rates of the other workloads")
     ap.add_argument("--phi-loop", type=int, default=10, help="Phi applications per precision in the pure loop")
     ap.add_argument("--kernel-only", default=None, help="profiling mode: only run Phi loops in this precision")
     args = ap.parse_args()
@@ -334,6 +335,35 @@ def main():
                                      "gmres_steps": iinfo["n_inner"], "worst_rel_residual": iinfo["err_est"]}}
         log(f"[bench] extras {extras}")
 
+    # Phi-applications per second on the other workloads (after the timed region): plain loops of
+    # Phi on a seeded Hermitian state, per precision mode the workload is specified with
+    per_config = None
+    if not args.no_configs:
+        per_config = []
+        for wname, precs, loops in [("kerr32", ["fp64"], 2000), ("two_photon256", ["fp64", "fp32"], 400),
+                                    ("coupled_kerr1600", ["fp32"], 20), ("kerr512_dephasing", ["fp64"], 100),
+                                    ("random1024_d4", ["fp64", "bf16x3"], 50)]:
+            Hc, Lc, _ = li.workload(wname)
+            nc = Hc.shape[0]
+            Xc = torch.from_numpy(li.random_state(nc, seed=3)).to(dev)
+            for pc in precs:
+                t0 = time.perf_counter()
+                mc = Lindblad(torch.from_numpy(Hc).to(dev), torch.from_numpy(np.stack(Lc)).to(dev), prec=pc)
+                torch.cuda.synchronize()
+                tc = time.perf_counter() - t0
+                for _ in range(3):
+                    mc.phi(Xc)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(loops):
+                    mc.phi(Xc)
+                torch.cuda.synchronize()
+                dtc = time.perf_counter() - t0
+                per_config.append({"workload": wname, "n": nc, "d": len(Lc), "prec": pc,
+                                   "phi_per_s": loops / dtc, "us_per_phi": 1e6 * dtc / loops, "create_s": tc})
+                mc.close()
+        log(f"[bench] per-config Phi rates {per_config}")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -348,7 +378,7 @@ def main():
                       "step": "one steady-state solve (Arnoldi on Phi + FP64 refinement); factorisation once, "
                               "reported in time_to_tol", "parallelism": "single GPU"},
            "time_to_tol": t_to_tol, "roofline": roof, "kernels": other, "cpu_baseline": cpu,
-           "create_s": t_create, "resolvent": extras}
+           "create_s": t_create, "resolvent": extras, "phi_rates": per_config}
     model.close()
     print(json.dumps(out), flush=True)
 

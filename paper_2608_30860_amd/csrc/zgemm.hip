@@ -722,6 +722,25 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
     const long long ea = an ? z64_extent(g.M, g.K, g.lda, g.sA, g.nbatch) : z64_extent(g.K, g.M, g.lda, g.sA, g.nbatch);
     const long long eb = bn ? z64_extent(g.K, g.N, g.ldb, g.sB, g.nbatch) : z64_extent(g.N, g.K, g.ldb, g.sB, g.nbatch);
     const bool aligned = (((unsigned long long)g.A | (unsigned long long)g.B) & 15) == 0;
+    const long long ws_avail = g0.ws ? (g0.ws_bytes > 0 ? g0.ws_bytes : gemm_ws_bytes(PREC_F64, g.M, g.N, g.nbatch)) : 0;
+    const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.nbatch;
+    if (t128 < 96) {
+      // too few 128 x 128 tiles (even split over every batch) to occupy the chip: 64 x 64 or
+      // 32 x 32 tiles of the register-staged kernel, split-K over the batches
+      g.tri = 0;
+      const int bt = ((long long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch >= 128) ? 64 : 32;
+      const long long tiles = (long long)((g.M + bt - 1) / bt) * ((g.N + bt - 1) / bt);
+      int s = 1;
+      if (g0.ws)
+        while (s * 2 <= g.nbatch && (g.nbatch % (s * 2)) == 0 && tiles * s < 512 &&
+               (long long)(s * 2) * g.M * g.N * 16 <= ws_avail)
+          s *= 2;
+      g.nsplit = s;
+      rc = bt == 64 ? launch(zgemm_kernel<double, 64, 64, 16, double2>, 64, 64, g, st)
+                    : launch(zgemm_kernel<double, 32, 32, 16, double2>, 32, 32, g, st);
+      if (!rc && g.nsplit > 1) rc = launch_reduce<double2, double2>(g, st);
+      return rc;
+    }
     if (ea > 0 && eb > 0 && aligned) {
       // direct-to-LDS kernel; the split-K count is re-derived for its 128 x 128 tiles
       g.tri = (g0.tri && g.M == g.N && g.ai == 0.0) ? 1 : 0;
@@ -729,7 +748,7 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
         int s = 1;
         const long long tm0 = (g.M + 127) / 128;
         const long long t = g.tri ? tm0 * (tm0 + 1) / 2 : tm0 * ((g.N + 127) / 128);
-        while (s * 2 <= g.nbatch && (g.nbatch % (s * 2)) == 0 && t * s < 1024 && (long long)(s * 2) * g.M * g.N * 16 <= (g0.ws_bytes > 0 ? g0.ws_bytes : gemm_ws_bytes(PREC_F64, g.M, g.N, g.nbatch))) s *= 2;
+        while (s * 2 <= g.nbatch && (g.nbatch % (s * 2)) == 0 && t * s < 1024 && (long long)(s * 2) * g.M * g.N * 16 <= ws_avail) s *= 2;
         g.nsplit = s;
       }
       const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
