@@ -50,6 +50,7 @@ struct Ctx {
   zd *s = nullptr, *sbar = nullptr;
   zd *Lt = nullptr;    // L_j U (eigen route) or L_j Z (Schur route), stacked d x n x n
   zd *Tadj = nullptr;  // J T^H J (upper triangular) for the adjoint Schur solve
+  zd *tsws = nullptr;  // partial block products of the triangular Sylvester solve
   std::vector<cplx> s_host;
   // low-precision operands (complex64)
   zf *U32 = nullptr, *V32 = nullptr, *Z32 = nullptr, *Lt32 = nullptr;

@@ -143,6 +143,9 @@ int small_eig(const zd* A, int lda, int m, zd* w, zd* Y, int* info, hipStream_t 
 // ---------------------------------------------------------------------------
 // triangular Sylvester solve  T X + X T^H + shift*X = Y  (T upper triangular, n x n)
 // ---------------------------------------------------------------------------
-int trisylv(const zd* T, zd* X, int n, zd shift, hipStream_t st);
+// T X + X T^H + shift X = C (T upper triangular, X overwrites C); ws holds trisylv_ws_elems(n)
+// complex entries of scratch
+int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st);
+long long trisylv_ws_elems(int n);
 
 }  // namespace lindx

@@ -252,6 +252,7 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
   rc |= c.alloc(&c.H, n2); rc |= c.alloc(&c.L, nd); rc |= c.alloc(&c.G, n2); rc |= c.alloc(&c.T, n2);
   rc |= c.alloc(&c.Z, n2); rc |= c.alloc(&c.U, n2); rc |= c.alloc(&c.V, n2); rc |= c.alloc(&c.s, n);
   rc |= c.alloc(&c.sbar, n); rc |= c.alloc(&c.Lt, nd); rc |= c.alloc(&c.Tadj, n2);
+  rc |= c.alloc(&c.tsws, trisylv_ws_elems(n));
   rc |= c.alloc(&c.w1, n2); rc |= c.alloc(&c.w2, n2); rc |= c.alloc(&c.w3, n2); rc |= c.alloc(&c.w4, n2);
   rc |= c.alloc(&c.Ys, nd); rc |= c.alloc(&c.dsc, 1024); rc |= c.alloc(&c.dscr, (size_t)c.dscr_len);
   rc |= c.alloc(&X->hm, 64 * 64); rc |= c.alloc(&X->ev, 64); rc |= c.alloc(&X->Yv, 64 * 64);

@@ -152,12 +152,12 @@ int op_sinv(Ctx& c, const zd* Y, zd* X, cplx mu, int prec, bool adjoint) {
   TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_C, Y, n, OP_N, c.w1, n, one, 0));
   TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, c.Z, n, OP_N, c.w2, n, one, 0));
   if (!adjoint) {
-    TRY(trisylv(c.T, c.w2, n, zmk(-mu.real(), -mu.imag()), c.st));
+    TRY(trisylv(c.T, c.w2, n, zmk(-mu.real(), -mu.imag()), c.tsws, c.st));
   } else {
     // T^H Xt + Xt T - conj(mu) Xt = Yt  <=>  T' X' + X' T'^H - conj(mu) X' = Y'  with
     // T' = J T^H J (upper triangular, precomputed), X' = J Xt J, Y' = J Yt J (J = exchange)
     TRY(flip_rev(c.w2, c.w1, n, c.st));
-    TRY(trisylv(c.Tadj, c.w1, n, zmk(-mu.real(), mu.imag()), c.st));
+    TRY(trisylv(c.Tadj, c.w1, n, zmk(-mu.real(), mu.imag()), c.tsws, c.st));
     TRY(flip_rev(c.w1, c.w2, n, c.st));
   }
   TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_N, c.w2, n, OP_N, c.w1, n, one, 0));
@@ -179,7 +179,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian) {
   if (c.route == LIND_ROUTE_SCHUR) {
     TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_C, xi, n, OP_N, c.w1, n, one, 0));
     TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, c.Z, n, OP_N, c.w2, n, one, 0));
-    TRY(trisylv(c.T, c.w2, n, zmk(0, 0), c.st));
+    TRY(trisylv(c.T, c.w2, n, zmk(0, 0), c.tsws, c.st));
     if (prec == PREC_F64) {
       TRY(op_gemm(c, PREC_F64, d * n, n, n, c.Lt, n, OP_N, c.w2, n, OP_N, c.Ys, n, one, 0));
       GemmDesc g;

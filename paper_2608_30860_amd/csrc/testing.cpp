@@ -63,7 +63,11 @@ extern "C" int lindx_triinv(const void* Y, void* Yinv, int n, void* stream) {
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -4;
 }
 extern "C" int lindx_trisylv(const void* T, void* X, int n, double sr, double si, void* stream) {
-  int rc = trisylv((const zd*)T, (zd*)X, n, zmk(sr, si), (hipStream_t)stream);
+  zd* ws = nullptr;
+  if (hipMalloc(&ws, sizeof(zd) * (size_t)trisylv_ws_elems(n > 0 ? n : 1)) != hipSuccess) return -5;
+  int rc = trisylv((const zd*)T, (zd*)X, n, zmk(sr, si), ws, (hipStream_t)stream);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == 0) rc = -4;
+  hipFree(ws);
   if (rc) return rc;
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -4;
 }

@@ -203,14 +203,15 @@ def test_trevec_triinv(n):
     assert np.max(np.abs(Yi.cpu().numpy() @ Yn - np.eye(n))) < 1e-9 * np.abs(Yn).max()
 
 
-@pytest.mark.parametrize("n", [1, 17, 32, 100])
+@pytest.mark.parametrize("n", [1, 17, 32, 100, 700])
 @pytest.mark.parametrize("shift", [0.0, -0.3 + 0.2j])
 def test_trisylv(n, shift):
     rng = np.random.default_rng(n + 2)
     Tm = np.triu(crand(rng, n, n)) / np.sqrt(n) - 2.0 * np.eye(n)
     C = crand(rng, n, n)
     X = T(C)
-    assert lib().lindx_trisylv(P(T(Tm)), P(X), n, shift.real, shift.imag, None) == 0
+    Tt = T(Tm)
+    assert lib().lindx_trisylv(P(Tt), P(X), n, shift.real, shift.imag, None) == 0
     Xn = X.cpu().numpy()
     res = Tm @ Xn + Xn @ Tm.conj().T + shift * Xn - C
     assert np.max(np.abs(res)) < 1e-12 * np.abs(C).max() * n
