@@ -7,8 +7,9 @@
 //     of the anti-diagonal, spread over up to PMAX workgroups per block (FP64 MFMA, operands
 //     through LDS); each workgroup writes its partial sum to the workspace.
 //  2. k_trisylv_solve: one workgroup per block subtracts the partial sums from C_IJ and solves
-//     T_II X + X T_JJ^H + sigma X = C in LDS by an anti-diagonal sweep in which each solved
-//     entry immediately updates the entries that depend on it (two products per entry per step).
+//     T_II X + X T_JJ^H + sigma X = C in LDS by an anti-diagonal sweep: at each step every
+//     pending entry takes its products with the two entries solved at the step before (one in its
+//     column, one in its row), so a step costs two products per entry and one barrier.
 #include "kernels.hpp"
 
 namespace lindx {
@@ -99,13 +100,18 @@ __global__ __launch_bounds__(256) void k_trisylv_solve(const zd* __restrict__ T,
   const int i0 = I * TB, j0 = J * TB;
   const int bi = min(TB, n - i0), bj = min(TB, n - j0);
   const int np = min(PMAX, (nb - 1 - I) + (nb - 1 - J));
-  // thread t owns entries (r0 + 8 u, q0)
+  // thread t owns entries (r0 + 8 u, q0); the partial sums are loaded 16 at a time before use
   const int q0 = t & 31, r0 = t >> 5;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int r = r0 + 8 * u;
+    zd part[PMAX];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p)
+      part[p] = p < np ? ws[((long long)b * PMAX + p) * TB * TB + r * TB + q0] : zmk(0, 0);
     zd v = (r < bi && q0 < bj) ? X[(long long)(i0 + r) * n + j0 + q0] : zmk(0, 0);
-    for (int p = 0; p < np; ++p) v = zsub(v, ws[((long long)b * PMAX + p) * TB * TB + r * TB + q0]);
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) v = zsub(v, part[p]);
     Cs[r * TP + q0] = v;
   }
   for (int e = t; e < TB * TB; e += 256) {
@@ -114,31 +120,26 @@ __global__ __launch_bounds__(256) void k_trisylv_solve(const zd* __restrict__ T,
     Bs[r * TP + q] = (r < bj && q < bj) ? T[(long long)(j0 + r) * n + j0 + q] : zmk(0, 0);
   }
   __syncthreads();
-  // step L solves the entries with (bi-1-r) + (bj-1-q) = L; every later entry of the same column
-  // (rows above) and of the same row (columns to the left) then takes its product with them
+  // step L: every entry not solved yet takes its products with the two entries solved at step
+  // L - 1 in its column (row k below) and in its row (column m to the right); the entries with
+  // (bi-1-r) + (bj-1-q) = L are then complete and divided by their diagonal.  One thread owns
+  // an entry throughout, so one barrier per step separates the writes of step L from the reads
+  // of step L + 1.
   const int nlev = (bi - 1) + (bj - 1);
   for (int L = 0; L <= nlev; ++L) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = r0 + 8 * u, q = q0;
-      if (r < bi && q < bj && (bi - 1 - r) + (bj - 1 - q) == L) {
-        const zd den = zadd(zadd(As[r * TP + r], zconj(Bs[q * TP + q])), sigma);
-        Cs[r * TP + q] = zdiv(Cs[r * TP + q], den);
-      }
-    }
-    __syncthreads();
-    if (L == nlev) break;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + 8 * u, q = q0;
-      if (r >= bi || q >= bj || (bi - 1 - r) + (bj - 1 - q) <= L) continue;
+      const int lev = (bi - 1 - r) + (bj - 1 - q);
+      if (r >= bi || q >= bj || lev < L) continue;
       zd v = Cs[r * TP + q];
-      // the entry solved at step L in column q: row k = bi - 1 - (L - (bj - 1 - q))
-      const int k = bi - 1 - (L - (bj - 1 - q));
-      if (k > r && k < bi) v = zsub(v, zmul(As[r * TP + k], Cs[k * TP + q]));
-      // the entry solved at step L in row r: column m = bj - 1 - (L - (bi - 1 - r))
-      const int m = bj - 1 - (L - (bi - 1 - r));
-      if (m > q && m < bj) v = zsub(v, zmul(Cs[r * TP + m], zconj(Bs[q * TP + m])));
+      if (L > 0) {
+        const int k = bi - 1 - (L - 1 - (bj - 1 - q));
+        if (k > r && k < bi) v = zsub(v, zmul(As[r * TP + k], Cs[k * TP + q]));
+        const int m = bj - 1 - (L - 1 - (bi - 1 - r));
+        if (m > q && m < bj) v = zsub(v, zmul(Cs[r * TP + m], zconj(Bs[q * TP + m])));
+      }
+      if (lev == L) v = zdiv(v, zadd(zadd(As[r * TP + r], zconj(Bs[q * TP + q])), sigma));
       Cs[r * TP + q] = v;
     }
     __syncthreads();
