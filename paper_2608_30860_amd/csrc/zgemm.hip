@@ -768,18 +768,27 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
     return rc;
   }
   if (prec == PREC_F32) {
+    // 128 x 128 tiles for split or large products, else 64 x 64; 32 x 32 when the larger tiles
+    // would leave most of the chip idle
+    int bt = (g.nsplit > 1 || (g.M >= 1024 && g.N >= 1024)) ? 128 : 64;
+    auto tiles = [&](int b) { return (long long)((g.M + b - 1) / b) * ((g.N + b - 1) / b) * g.nsplit; };
+    if (tiles(bt) < 96 && tiles(32) > tiles(bt)) bt = 32;
     if (g.nsplit > 1) {
-      rc = launch(zgemm_kernel<float, 128, 128, 16, float2>, 128, 128, g, st);
+      rc = bt == 128 ? launch(zgemm_kernel<float, 128, 128, 16, float2>, 128, 128, g, st)
+                     : launch(zgemm_kernel<float, 32, 32, 16, float2>, 32, 32, g, st);
       if (!rc) rc = g.out64 ? launch_reduce<float2, double2>(g, st) : launch_reduce<float2, float2>(g, st);
       return rc;
     }
     if (g.out64) {
-      if (g.M >= 1024 && g.N >= 1024) return launch(zgemm_kernel<float, 128, 128, 16, double2>, 128, 128, g, st);
-      return launch(zgemm_kernel<float, 64, 64, 16, double2>, 64, 64, g, st);
+      if (bt == 128) return launch(zgemm_kernel<float, 128, 128, 16, double2>, 128, 128, g, st);
+      if (bt == 64) return launch(zgemm_kernel<float, 64, 64, 16, double2>, 64, 64, g, st);
+      return launch(zgemm_kernel<float, 32, 32, 16, double2>, 32, 32, g, st);
     }
-    if (g.M >= 1024 && g.N >= 1024) return launch(zgemm_kernel<float, 128, 128, 16, float2>, 128, 128, g, st);
-    return launch(zgemm_kernel<float, 64, 64, 16, float2>, 64, 64, g, st);
+    if (bt == 128) return launch(zgemm_kernel<float, 128, 128, 16, float2>, 128, 128, g, st);
+    if (bt == 64) return launch(zgemm_kernel<float, 64, 64, 16, float2>, 64, 64, g, st);
+    return launch(zgemm_kernel<float, 32, 32, 16, float2>, 32, 32, g, st);
   }
+
   if (prec == PREC_BF16X3) {
     if (g.nsplit > 1) {
       rc = launch_bf16<128, 128, float2>(g, st);
