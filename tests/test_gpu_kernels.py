@@ -74,12 +74,13 @@ def test_gemm(prec, tol, M, N, K, nb, opA, opB):
 
 @pytest.mark.parametrize("M,N,K,nb", [(37, 45, 29, 1), (130, 70, 200, 1), (128, 128, 64, 1), (300, 260, 72, 1),
                                       (1, 1, 1, 1), (256, 384, 1000, 1), (64, 64, 64, 3), (300, 260, 72, 8),
-                                      (1024, 1024, 64, 4)])
+                                      (1024, 1024, 64, 4), (4100, 2050, 40, 1), (2048, 2050, 40, 4)])
 @pytest.mark.parametrize("opA,opB", [(0, 0), (2, 0), (0, 2), (2, 2)])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_p4_gemm(M, N, K, nb, opA, opB, mode):
     """pre-split BF16 product: planes out (row-major / transposed), split-K partials out, and the
-    fused divide; relative to the largest entry, 3e-4 as for the on-the-fly BF16x3 product"""
+    fused divide; relative to the largest entry, 3e-4 as for the on-the-fly BF16x3 product.  The
+    two largest shapes are ragged in m and n over many tiles, one of them split-K."""
     if mode != 2 and nb != 1:
         pytest.skip("batched products only reduce into split-K partials")
     print(f"[case] p4 {M}x{N}x{K} nb={nb} ops={opA},{opB} mode={mode}", flush=True)
