@@ -133,3 +133,21 @@ def test_steady_expectation_autograd_scalar_parameters():
            (f(Dv, ev_, kv, gv + h) - f(Dv, ev_, kv, gv - h)) / (2 * h)]
     assert abs(J.item() - f(Dv, ev_, kv, gv)) < 1e-9
     assert np.allclose(th.grad.cpu().numpy(), ref, rtol=1e-6, atol=1e-8)
+
+
+def test_steady_expect_gradcheck_tiny():
+    """torch.autograd.gradcheck of SteadyExpect (adjoint gradient) against PyTorch's own central
+    differences of the GPU steady state, n = 4, d = 2, complex128.  H enters through its
+    Hermitian part (H = (A + A^H) / 2), so every perturbation gradcheck makes is a Lindbladian;
+    the jump operators are perturbed freely."""
+    from paper_2608_30860_amd import steady_expectation
+    print("[case] gradcheck SteadyExpect n=4 d=2", flush=True)
+    H, Ls = li.random_dense(4, 2, 7)
+    O = T(li.random_observable(4, seed=2))
+    A = T(H).requires_grad_()
+    Lt = T(np.stack(Ls)).requires_grad_()
+
+    def f(a, ls):
+        return steady_expectation(0.5 * (a + a.conj().T), ls, O, 1e-13)
+
+    assert torch.autograd.gradcheck(f, (A, Lt), eps=1e-6, atol=1e-6, rtol=1e-4)
