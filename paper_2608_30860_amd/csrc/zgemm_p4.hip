@@ -195,9 +195,10 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
     // the loads of this stage have landed (the barrier waits for every outstanding load), and
     // every wave is done with the other buffer, which the next stage may now overwrite
     __syncthreads();
-    if (it + 1 < total) issue(it + 1, buf ^ 1);
+    // fragment reads first, so the LDS works while the wave issues the next stage's DMA
     v8bf_p a[4][4], bb[TNW][4];
     frags(buf, a, bb);
+    if (it + 1 < total) issue(it + 1, buf ^ 1);
     compute(a, bb);
   }
 
