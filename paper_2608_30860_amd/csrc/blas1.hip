@@ -445,9 +445,44 @@ __global__ void k_gemv_c(const zd* A, int n, const zd* x, zd* y) {
   }
   y[j] = zmk(a, b);
 }
-int gemv(const zd* A, int n, int opA, const zd* x, zd* y, hipStream_t st) {
-  if (opA == OP_N) hipLaunchKernelGGL(k_gemv_n, dim3((n + 3) / 4), dim3(256), 0, st, A, n, x, y);
-  else hipLaunchKernelGGL(k_gemv_c, dim3((n + 63) / 64), dim3(64), 0, st, A, n, x, y);
+// A^H x in two passes for large n: workgroup (column block, row chunk) sums 128 rows of 64
+// columns into part[chunk][j]; the second pass adds the chunks (fixed order, deterministic)
+static constexpr int GEMV_RC = 128;
+__global__ void k_gemv_c_part(const zd* A, int n, const zd* x, zd* part) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  const int i0 = blockIdx.y * GEMV_RC;
+  if (j >= n) return;
+  const int i1 = min(n, i0 + GEMV_RC);
+  double a = 0, b = 0;
+  for (int i = i0; i < i1; ++i) {
+    zd p = zcmul(A[(long long)i * n + j], x[i]);
+    a += p.x;
+    b += p.y;
+  }
+  part[(long long)blockIdx.y * n + j] = zmk(a, b);
+}
+__global__ void k_gemv_c_sum(const zd* part, int n, int chunks, zd* y) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double a = 0, b = 0;
+  for (int c = 0; c < chunks; ++c) {
+    const zd p = part[(long long)c * n + j];
+    a += p.x;
+    b += p.y;
+  }
+  y[j] = zmk(a, b);
+}
+long long gemv_scratch_elems(int n) { return (long long)((n + GEMV_RC - 1) / GEMV_RC) * n; }
+int gemv(const zd* A, int n, int opA, const zd* x, zd* y, zd* scratch, hipStream_t st) {
+  if (opA == OP_N) {
+    hipLaunchKernelGGL(k_gemv_n, dim3((n + 3) / 4), dim3(256), 0, st, A, n, x, y);
+  } else if (scratch && n > 2 * GEMV_RC) {
+    const int chunks = (n + GEMV_RC - 1) / GEMV_RC;
+    hipLaunchKernelGGL(k_gemv_c_part, dim3((n + 63) / 64, chunks), dim3(64), 0, st, A, n, x, scratch);
+    hipLaunchKernelGGL(k_gemv_c_sum, dim3((n + 255) / 256), dim3(256), 0, st, (const zd*)scratch, n, chunks, y);
+  } else {
+    hipLaunchKernelGGL(k_gemv_c, dim3((n + 63) / 64), dim3(64), 0, st, A, n, x, y);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

@@ -112,7 +112,10 @@ int make_generator(const zd* H, const zd* W, zd* G, int n, hipStream_t st);
 int scale_cols(zd* X, int n, const double* s, int invert, hipStream_t st);
 int col_norms(const zd* X, int n, double* out, hipStream_t st);
 // y = A x for n x n A (opA = N or C), vectors of length n
-int gemv(const zd* A, int n, int opA, const zd* x, zd* y, hipStream_t st);
+// y = op(A) x (n x n A); A^H x for n > 256 runs in two passes through scratch, which holds
+// gemv_scratch_elems(n) entries (nullptr: one pass)
+int gemv(const zd* A, int n, int opA, const zd* x, zd* y, zd* scratch, hipStream_t st);
+long long gemv_scratch_elems(int n);
 // out[i] = conj(x[i]) for complex arrays (used for sigma-bar)
 int conj_copy(const zd* x, zd* y, long long len, hipStream_t st);
 // X <- J X^T J etc: reverse both indices and transpose-conjugate (adjoint triangular form)

@@ -116,8 +116,10 @@ static int power_norm(Ctx& c, const zd* M, zd* x, zd* y, int iters, double* out)
   const int n = c.n;
   double nrm = 0;
   for (int it = 0; it < iters; ++it) {
-    TRY(gemv(M, n, OP_N, x, y, c.st));
-    TRY(gemv(M, n, OP_C, y, x, c.st));
+    // y holds n entries of an n x n buffer; the rest is the scratch of the two-pass A^H x
+    zd* scratch = gemv_scratch_elems(n) <= (long long)n * n - n ? y + n : nullptr;
+    TRY(gemv(M, n, OP_N, x, y, nullptr, c.st));
+    TRY(gemv(M, n, OP_C, y, x, scratch, c.st));
     TRY(nrm2(x, n, (double*)c.dsc, c.dscr, c.st));
     TRY(scale_by_inv(x, n, (const double*)c.dsc, c.st));
     TRY(c.fetch(c.dsc, sizeof(double)));
