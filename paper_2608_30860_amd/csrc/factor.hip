@@ -29,6 +29,7 @@ static constexpr int WIN = 64;    // window rows
 static constexpr int STEP = 24;   // default window advance
 static constexpr int NSMAX = 19;  // default bulges per sweep (WIN >= step + 2 * bulges + 1)
 static constexpr int NSCAP = 23;  // most bulges one chase kernel holds
+static constexpr int CHASE_T = 512;  // threads of the chase kernel (8 waves, two per SIMD)
 static constexpr int MAXWIN = 256;
 static constexpr int AEDW = 32;   // default early-deflation window rows (<= WIN)
 
@@ -225,36 +226,37 @@ __device__ inline double bcast(double x, int l) {
 // order).  Rotations of one step act on disjoint row pairs and disjoint column pairs, and a
 // bulge's parameters only read entries that the other bulges of the same step do not touch.
 //
-// Bulge b belongs to wave b % 4 for the whole chase: lane b / 4 of that wave computes the
+// Bulge b belongs to wave b % 8 for the whole chase: lane b / 8 of that wave computes the
 // rotation, v_readlane hands it to the wave in scalar registers, and the same wave applies the
 // row rotation (lane = column) and then the column rotation of the window and of the window
 // unitary (lane = row).  The parameters of a bulge read rows q, q+1, which no other bulge's row
 // rotation of the same step writes, so one step needs a barrier only between the row and the
 // column rotations (other bulges' rows meet this bulge's columns) and at its end.
-__global__ __launch_bounds__(256) void k_chase(zd* A, int n, int ilo, int ihi, int r, int bw,
+__global__ __launch_bounds__(CHASE_T) void k_chase(zd* A, int n, int ilo, int ihi, int r, int bw,
                                                 const zd* shifts, int ns, int* cnt, zd* Uout) {
   __shared__ zd Hs[WIN * LDM];
   __shared__ zd Us[WIN * LDM];
-  constexpr int BPW = (NSCAP + 3) / 4;  // bulges per wave
+  constexpr int NWV = CHASE_T / 64;                // waves
+  constexpr int BPW = (NSCAP + NWV - 1) / NWV;  // bulges per wave
   const int t = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lane = t & 63;
   {
-    zd v[WIN * WIN / 256];
+    zd v[WIN * WIN / CHASE_T];
 #pragma unroll
-    for (int k = 0; k < WIN * WIN / 256; ++k) {
-      const int e = t + 256 * k, i = e >> 6, j = e & 63;
+    for (int k = 0; k < WIN * WIN / CHASE_T; ++k) {
+      const int e = t + CHASE_T * k, i = e >> 6, j = e & 63;
       v[k] = (i < bw && j < bw) ? A[(long long)(r + i) * n + r + j] : zmk(0, 0);
     }
 #pragma unroll
-    for (int k = 0; k < WIN * WIN / 256; ++k) {
-      const int e = t + 256 * k, i = e >> 6, j = e & 63;
+    for (int k = 0; k < WIN * WIN / CHASE_T; ++k) {
+      const int e = t + CHASE_T * k, i = e >> 6, j = e & 63;
       Hs[i * LDM + j] = v[k];
       Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
     }
   }
-  // lane u < BPW of wave w owns bulge b = w + 4u: its shift and its next pair
-  const int myb = w + 4 * lane;
+  // lane u < BPW of wave w owns bulge b = w + NWV u: its shift and its next pair
+  const int myb = w + NWV * lane;
   const bool own = lane < BPW && myb < ns;
   zd sh = zmk(0, 0);
   int nxt = 0;
@@ -363,8 +365,8 @@ __global__ __launch_bounds__(256) void k_chase(zd* A, int n, int ilo, int ihi, i
   }
   if (own) cnt[myb] = nxt - ilo;
 #pragma unroll
-  for (int k = 0; k < WIN * WIN / 256; ++k) {
-    const int e = t + 256 * k, i = e >> 6, j = e & 63;
+  for (int k = 0; k < WIN * WIN / CHASE_T; ++k) {
+    const int e = t + CHASE_T * k, i = e >> 6, j = e & 63;
     if (i < bw && j < bw) {
       A[(long long)(r + i) * n + r + j] = Hs[i * LDM + j];
       Uout[i * WIN + j] = Us[i * LDM + j];
@@ -881,7 +883,7 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
     for (int r = ilo;; r += step) {
       int bw = ihi + 1 - r < WIN ? ihi + 1 - r : WIN;
       zd* Uw = U + (long long)wl.nwin * WIN * WIN;
-      hipLaunchKernelGGL(k_chase, dim3(1), dim3(256), 0, st, A, n, ilo, ihi, r, bw, sh, ns, cnt, Uw);
+      hipLaunchKernelGGL(k_chase, dim3(1), dim3(CHASE_T), 0, st, A, n, ilo, ihi, r, bw, sh, ns, cnt, Uw);
       if (r + bw <= ihi)
         hipLaunchKernelGGL(k_left_apply, dim3((ihi - (r + bw) + 1 + 15) / 16), dim3(256), 0, st, A, n, r, bw, r + bw,
                            ihi, (const zd*)Uw);
