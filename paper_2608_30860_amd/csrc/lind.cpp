@@ -72,6 +72,16 @@ __global__ void k_nonfinite(const double* x, long long len, int* flag) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride)
     if (!isfinite(x[i])) flag[0] = 1;
 }
+// xi = -(G v + v G^H) for rho = v I: -v (G + G^H), elementwise
+__global__ void k_minus_herm_part(const zd* G, int n, double v, zd* xi) {
+  long long tot = (long long)n * n;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+    const long long i = t / n, j = t - i * n;
+    const zd a = G[t], b = G[j * n + i];
+    xi[t] = zmk(-v * (a.x + b.x), -v * (a.y - b.y));
+  }
+}
 __global__ void k_fill_identity_scaled(zd* X, int n, double v) {
   long long tot = (long long)n * n;
   long long stride = (long long)gridDim.x * blockDim.x;
@@ -528,9 +538,15 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   // first Krylov vector xi = -S(rho) / ||.|| from the state in rhoB; c_scale converts the Ritz
   // residual estimate into a bound on the state's residual
   double c_scale = 1.0;
+  bool rho_is_identity = !rho0;  // rhoB = I/n: -S(I/n) = -(G + G^H)/n needs no product
   auto start_from_rho = [&]() -> int {
-    TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, X->rhoB, n, OP_N, X->xiB, n, mone, 0));
-    TRY(op_gemm(c, PREC_F64, n, n, n, X->rhoB, n, OP_N, c.G, n, OP_C, X->xiB, n, mone, 1));
+    if (rho_is_identity) {
+      hipLaunchKernelGGL(k_minus_herm_part, dim3(1024), dim3(256), 0, c.st, (const zd*)c.G, n, 1.0 / n, X->xiB);
+      if (hipGetLastError() != hipSuccess) return LIND_EDEVICE;
+    } else {
+      TRY(op_gemm(c, PREC_F64, n, n, n, c.G, n, OP_N, X->rhoB, n, OP_N, X->xiB, n, mone, 0));
+      TRY(op_gemm(c, PREC_F64, n, n, n, X->rhoB, n, OP_N, c.G, n, OP_C, X->xiB, n, mone, 1));
+    }
     double xin = 0;
     TRY(op_nrm(c, X->xiB, &xin));
     if (!(xin > 0) || !std::isfinite(xin)) return c.fail(LIND_EINVAL, "start state gives xi_0 = 0 or non-finite");
@@ -693,6 +709,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     if (converged || !oscillation_stop || restarts_left <= 0) break;
     if (deadline > 0 && now_s() > deadline) break;
     TRY(copy((const zd*)rho_out, X->rhoB, n2, c.st));
+    rho_is_identity = false;
     TRY(start_from_rho());
     best_is_last = false;
   }
