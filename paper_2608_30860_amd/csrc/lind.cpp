@@ -560,7 +560,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   };
   TRY(start_from_rho());
 
-  const double eps_floor = (p == PREC_F64) ? 0.0 : (p == PREC_F32 ? 1e-6 : 3e-4);
+  const double eps_floor = (p == PREC_F64) ? 0.0 : (p == PREC_F32 ? 1e-6 : 3e-3);
   double best = 1e300, best_max = 0;
   bool converged = false;
   std::vector<cplx> Hh((size_t)(m + 1) * m), w, Y;
