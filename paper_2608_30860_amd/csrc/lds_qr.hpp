@@ -10,7 +10,18 @@ static constexpr int LDM = 65;  // LDS row stride for the <= 64 x 64 matrices
 
 __device__ inline double cabs1(zd a) { return fabs(a.x) + fabs(a.y); }
 
-// Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [f; g] = [r; 0].
+// 1/sqrt(x) for x in the normal range: the hardware estimate y refined by one Newton-Raphson
+// step carried to second order, y (1 + e/2 + 3 e^2/8) with e = 1 - x y^2 (the series of
+// (1 - e)^(-1/2)), which leaves an error of order e^3 below double rounding.
+__device__ inline double rsqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+// Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [f; g] = [r; 0].  It sits on the
+// serial path of every bulge step, so the common case takes two reciprocal square roots and no
+// division; squares near the ends of the exponent range take the exact square roots.
 __device__ inline void zlartg(zd f, zd g, double& c, zd& s, zd& r) {
   const double f2 = zabs2(f), g2 = zabs2(g);
   if (g2 == 0.0) {
@@ -24,8 +35,17 @@ __device__ inline void zlartg(zd f, zd g, double& c, zd& s, zd& r) {
     r = zmk(ag, 0);
     return;
   }
+  const double h2 = f2 + g2;
+  if (f2 > 1e-280 && g2 > 1e-280 && h2 < 1e280) {
+    const double ia = rsqrt_nr(f2), ih = rsqrt_nr(h2);
+    const zd ph = zscale(f, ia);  // f / |f|
+    c = (f2 * ia) * ih;
+    s = zscale(zmul(ph, zconj(g)), ih);
+    r = zscale(ph, h2 * ih);
+    return;
+  }
   const double af = sqrt(f2);
-  const double nrm = sqrt(f2 + g2);
+  const double nrm = sqrt(h2);
   const double inv_af = 1.0 / af, inv_n = 1.0 / nrm;
   const zd ph = zscale(f, inv_af);
   c = af * inv_n;
