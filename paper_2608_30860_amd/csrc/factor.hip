@@ -75,48 +75,39 @@ __global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, doub
   }
 }
 
-// partial[rc][j] = sum_{i in chunk rc, i > k} conj(u_i) A_ij, j > k
-__global__ __launch_bounds__(256) void k_hh_left_part(const zd* A, int n, int k, const zd* u, int rchunk,
-                                                      zd* part) {
+// The two one-sided updates of column k are applied in one pass.  With w = gam u^H A (left) and
+// A' = A - u w, the right update needs A' u = A u - u (w u), so A u can be formed from the matrix
+// before the left update, together with u^H A:
+//   A <- A - u w - y u^H,  y = gam (A u - u (w u));   Z <- Z - gam (Z u) u^H.
+// Pass 1 (k_hh_pass1): workgroups [0, ncb * nrc) form partial sums of u^H A over row chunks
+// (rows > k; workgroup (cb, rc) = (b % ncb, b / ncb), 64 columns each); the others form the raw
+// row sums (A u)_i and (Z u)_i, one row per wave (A rows first, then Z rows).
+__global__ __launch_bounds__(256) void k_hh_pass1(const zd* A, const zd* Z, int n, int k, const zd* u, int rchunk,
+                                                  int ncb, int nrc, zd* part, zd* y) {
   __shared__ zd ss[4][64];
-  int j = k + 1 + blockIdx.x * 64 + (threadIdx.x & 63);
-  int rg = threadIdx.x >> 6;
-  int r0 = k + 1 + blockIdx.y * rchunk;
-  int r1 = r0 + rchunk < n ? r0 + rchunk : n;
-  zd s = zmk(0, 0);
-  if (j < n)
-    for (int i = r0 + rg; i < r1; i += 4) s = zadd(s, zcmul(u[i], A[(long long)i * n + j]));
-  ss[rg][threadIdx.x & 63] = s;
-  __syncthreads();
-  if (rg == 0 && j < n) {
-    zd t = zadd(zadd(ss[0][threadIdx.x], ss[1][threadIdx.x]), zadd(ss[2][threadIdx.x], ss[3][threadIdx.x]));
-    part[(long long)blockIdx.y * n + j] = t;
+  const int nlp = ncb * nrc;
+  if ((int)blockIdx.x < nlp) {
+    const int cb = blockIdx.x % ncb, rc = blockIdx.x / ncb;
+    const int j = k + 1 + cb * 64 + (threadIdx.x & 63);
+    const int rg = threadIdx.x >> 6;
+    const int r0 = k + 1 + rc * rchunk;
+    const int r1 = r0 + rchunk < n ? r0 + rchunk : n;
+    zd s = zmk(0, 0);
+    if (j < n)
+      for (int i = r0 + rg; i < r1; i += 4) s = zadd(s, zcmul(u[i], A[(long long)i * n + j]));
+    ss[rg][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (rg == 0 && j < n) {
+      const zd t = zadd(zadd(ss[0][threadIdx.x], ss[1][threadIdx.x]), zadd(ss[2][threadIdx.x], ss[3][threadIdx.x]));
+      part[(long long)rc * n + j] = t;
+    }
+    return;
   }
-}
-__global__ void k_hh_left_reduce(const zd* part, int nrc, int n, int k, const double* gam, zd* w) {
-  int j = k + 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  zd s = zmk(0, 0);
-  for (int r = 0; r < nrc; ++r) s = zadd(s, part[(long long)r * n + j]);
-  w[j] = zscale(s, gam[0]);
-}
-__global__ void k_hh_left_update(zd* A, int n, int k, const zd* u, const zd* w) {
-  long long rows = n - k - 1;
-  long long tot = rows * rows;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-    int i = k + 1 + (int)(t / rows);
-    int j = k + 1 + (int)(t % rows);
-    A[(long long)i * n + j] = zsub(A[(long long)i * n + j], zmul(u[i], w[j]));
-  }
-}
-// y_i = gam * sum_{j > k} X_ij u_j for the rows of A (first n waves) and Z (next n waves)
-__global__ void k_hh_right_y(const zd* A, const zd* Z, int n, int k, const zd* u, const double* gam, zd* y) {
-  int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x - nlp) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (row >= 2 * n) return;
   const zd* X = row < n ? A : Z;
-  int i = row < n ? row : row - n;
+  const int i = row < n ? row : row - n;
   zd s = zmk(0, 0);
   for (int j = k + 1 + lane; j < n; j += 64) s = zadd(s, zmul(X[(long long)i * n + j], u[j]));
   double a = s.x, b = s.y;
@@ -124,18 +115,58 @@ __global__ void k_hh_right_y(const zd* A, const zd* Z, int n, int k, const zd* u
     a += __shfl_down(a, o, 64);
     b += __shfl_down(b, o, 64);
   }
-  if (lane == 0) y[row] = zscale(zmk(a, b), gam[0]);
+  if (lane == 0) y[row] = zmk(a, b);
 }
-__global__ void k_hh_right_update(zd* A, zd* Z, int n, int k, const zd* u, const zd* y) {
-  long long cols = n - k - 1;
-  long long tot = 2LL * n * cols;
-  long long stride = (long long)gridDim.x * blockDim.x;
+// w_j = gam sum_rc part[rc][j] (j > k), and the partial sums of w u of this workgroup's columns
+__global__ __launch_bounds__(256) void k_hh_wreduce(const zd* part, int nrc, int n, int k, const double* gam,
+                                                    const zd* u, zd* w, zd* wup) {
+  __shared__ zd red[4];
+  const int j = k + 1 + blockIdx.x * 256 + threadIdx.x;
+  zd wu = zmk(0, 0);
+  if (j < n) {
+    zd s = zmk(0, 0);
+    for (int r = 0; r < nrc; ++r) s = zadd(s, part[(long long)r * n + j]);
+    s = zscale(s, gam[0]);
+    w[j] = s;
+    wu = zmul(s, u[j]);
+  }
+  double a = wu.x, b = wu.y;
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = zmk(a, b);
+  __syncthreads();
+  if (threadIdx.x == 0) wup[blockIdx.x] = zadd(zadd(red[0], red[1]), zadd(red[2], red[3]));
+}
+// A <- A - u w - y u^H (all rows, columns > k) and Z <- Z - gam (Z u) u^H, one pass
+__global__ __launch_bounds__(256) void k_hh_update(zd* A, zd* Z, int n, int k, const zd* u, const zd* w, const zd* y,
+                                                   const zd* wup, int nwb, const double* gam) {
+  __shared__ zd s_wu;
+  if (threadIdx.x == 0) {
+    zd t = zmk(0, 0);
+    for (int b = 0; b < nwb; ++b) t = zadd(t, wup[b]);
+    s_wu = t;
+  }
+  __syncthreads();
+  const zd wu = s_wu;
+  const double g = gam[0];
+  const long long cols = n - k - 1;
+  const long long tot = 2LL * n * cols;
+  const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-    long long row = t / cols;
-    int j = k + 1 + (int)(t % cols);
-    zd* X = row < n ? A : Z;
-    long long i = row < n ? row : row - n;
-    X[i * n + j] = zsub(X[i * n + j], zmul(y[row], zconj(u[j])));
+    const long long row = t / cols;
+    const int j = k + 1 + (int)(t % cols);
+    const zd cu = zconj(u[j]);
+    if (row < n) {
+      const zd ui = u[row];
+      const zd yi = zscale(zsub(y[row], zmul(ui, wu)), g);
+      const long long e = row * n + j;
+      A[e] = zsub(zsub(A[e], zmul(ui, w[j])), zmul(yi, cu));
+    } else {
+      const long long e = (row - n) * n + j;
+      Z[e] = zsub(Z[e], zmul(zscale(y[row], g), cu));
+    }
   }
 }
 
@@ -145,17 +176,20 @@ static int gridN(long long len) {
   return (int)(nb < 1 ? 1 : nb);
 }
 
+// y holds 2 n row sums and, after them, the partial sums of w u (one per workgroup of k_hh_wreduce)
 static int hessenberg(zd* A, zd* Z, int n, zd* u, double* gam, zd* part, zd* w, zd* y, hipStream_t st) {
   const int nrc = 16;
   for (int k = 0; k + 2 < n; ++k) {
-    int rows = n - k - 1;
-    int rchunk = (rows + nrc - 1) / nrc;
+    const int rows = n - k - 1;
+    const int rchunk = (rows + nrc - 1) / nrc;
+    const int ncb = (rows + 63) / 64;
+    const int nwb = (rows + 255) / 256;
     hipLaunchKernelGGL(k_hh_vec, dim3(1), dim3(256), 0, st, A, n, k, u, gam);
-    hipLaunchKernelGGL(k_hh_left_part, dim3((rows + 63) / 64, nrc), dim3(256), 0, st, A, n, k, u, rchunk, part);
-    hipLaunchKernelGGL(k_hh_left_reduce, dim3((rows + 255) / 256), dim3(256), 0, st, part, nrc, n, k, gam, w);
-    hipLaunchKernelGGL(k_hh_left_update, dim3(gridN((long long)rows * rows)), dim3(256), 0, st, A, n, k, u, w);
-    hipLaunchKernelGGL(k_hh_right_y, dim3((2 * n + 3) / 4), dim3(256), 0, st, A, Z, n, k, u, gam, y);
-    hipLaunchKernelGGL(k_hh_right_update, dim3(gridN(2LL * n * rows)), dim3(256), 0, st, A, Z, n, k, u, y);
+    hipLaunchKernelGGL(k_hh_pass1, dim3(ncb * nrc + (2 * n + 3) / 4), dim3(256), 0, st, A, Z, n, k, u, rchunk, ncb,
+                       nrc, part, y);
+    hipLaunchKernelGGL(k_hh_wreduce, dim3(nwb), dim3(256), 0, st, part, nrc, n, k, gam, u, w, y + 2 * n);
+    hipLaunchKernelGGL(k_hh_update, dim3(gridN(2LL * n * rows)), dim3(256), 0, st, A, Z, n, k, u, w, y, y + 2 * n,
+                       nwb, gam);
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
@@ -486,49 +520,63 @@ __global__ __launch_bounds__(64) void k_aed(zd* A, int n, int kw, int ihi, zd* U
       }
     }
     __syncthreads();
-    // Householder reduction of T[:nu, :nu] to Hessenberg form
+    // Householder reduction of T[:nu, :nu] to Hessenberg form.  The column norm is a wave
+    // reduction (every lane holds the result); the sums of the two updates run on four
+    // independent accumulators to shorten their dependency chains.
     for (int k = 0; k + 2 < nu; ++k) {
       __syncthreads();
-      if (t == 0) {
-        double nrm2 = 0;
-        for (int i = k + 1; i < nu; ++i) nrm2 += zabs2(Hs[i * LDM + k]);
-        const zd x0 = Hs[(k + 1) * LDM + k];
-        const double ax0 = sqrt(zabs2(x0));
-        const double tail = nrm2 - ax0 * ax0;
-        if (tail > 0) {
-          const double nrm = sqrt(nrm2);
-          const zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
+      double nrm2 = (t > k && t < nu) ? zabs2(Hs[t * LDM + k]) : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) nrm2 += __shfl_xor(nrm2, o, 64);
+      nrm2 = __shfl(nrm2, 0, 64);  // one value for the whole wave: the branch below is uniform
+      const zd x0 = Hs[(k + 1) * LDM + k];
+      const double ax0 = sqrt(zabs2(x0));
+      const double tail = nrm2 - ax0 * ax0;
+      const double gam = tail > 0 ? 1.0 / (sqrt(nrm2) * (sqrt(nrm2) + ax0)) : 0.0;  // I - gam u u^H
+      if (gam != 0.0) {
+        const double nrm = sqrt(nrm2);
+        const zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
+        if (t == 0) {
           hv[k + 1] = zadd(x0, zscale(ph, nrm));
-          red[0] = 1.0 / (nrm * (nrm + ax0));  // gamma of I - gamma u u^H
           red[1] = -nrm;
           hv[0] = ph;
-        } else {
-          red[0] = 0.0;
         }
-      }
-      __syncthreads();
-      const double gam = red[0];
-      if (gam != 0.0) {
         for (int i = k + 2 + t; i < nu; i += 64) hv[i] = Hs[i * LDM + k];
         __syncthreads();
         // rows k+1 .. nu-1, columns k+1 .. jw-1 from the left
         for (int j = k + 1 + t; j < jw; j += 64) {
-          zd w = zmk(0, 0);
-          for (int i = k + 1; i < nu; ++i) w = zadd(w, zcmul(hv[i], Hs[i * LDM + j]));
-          w = zscale(w, gam);
-          for (int i = k + 1; i < nu; ++i) Hs[i * LDM + j] = zsub(Hs[i * LDM + j], zmul(hv[i], w));
+          zd w0 = zmk(0, 0), w1 = zmk(0, 0), w2 = zmk(0, 0), w3 = zmk(0, 0);
+          int i = k + 1;
+          for (; i + 3 < nu; i += 4) {
+            w0 = zadd(w0, zcmul(hv[i], Hs[i * LDM + j]));
+            w1 = zadd(w1, zcmul(hv[i + 1], Hs[(i + 1) * LDM + j]));
+            w2 = zadd(w2, zcmul(hv[i + 2], Hs[(i + 2) * LDM + j]));
+            w3 = zadd(w3, zcmul(hv[i + 3], Hs[(i + 3) * LDM + j]));
+          }
+          for (; i < nu; ++i) w0 = zadd(w0, zcmul(hv[i], Hs[i * LDM + j]));
+          const zd w = zscale(zadd(zadd(w0, w1), zadd(w2, w3)), gam);
+          for (i = k + 1; i < nu; ++i) Hs[i * LDM + j] = zsub(Hs[i * LDM + j], zmul(hv[i], w));
         }
         __syncthreads();
         // columns k+1 .. nu-1 from the right: rows 0 .. nu-1 of T, all rows of V
         for (int i = t; i < jw; i += 64) {
-          zd y = zmk(0, 0), yv = zmk(0, 0);
-          for (int j = k + 1; j < nu; ++j) {
-            if (i < nu) y = zadd(y, zmul(Hs[i * LDM + j], hv[j]));
-            yv = zadd(yv, zmul(Us[i * LDM + j], hv[j]));
+          zd y0 = zmk(0, 0), y1 = zmk(0, 0), v0 = zmk(0, 0), v1 = zmk(0, 0);
+          int j = k + 1;
+          for (; j + 1 < nu; j += 2) {
+            if (i < nu) {
+              y0 = zadd(y0, zmul(Hs[i * LDM + j], hv[j]));
+              y1 = zadd(y1, zmul(Hs[i * LDM + j + 1], hv[j + 1]));
+            }
+            v0 = zadd(v0, zmul(Us[i * LDM + j], hv[j]));
+            v1 = zadd(v1, zmul(Us[i * LDM + j + 1], hv[j + 1]));
           }
-          y = zscale(y, gam);
-          yv = zscale(yv, gam);
-          for (int j = k + 1; j < nu; ++j) {
+          if (j < nu) {
+            if (i < nu) y0 = zadd(y0, zmul(Hs[i * LDM + j], hv[j]));
+            v0 = zadd(v0, zmul(Us[i * LDM + j], hv[j]));
+          }
+          const zd y = zscale(zadd(y0, y1), gam);
+          const zd yv = zscale(zadd(v0, v1), gam);
+          for (j = k + 1; j < nu; ++j) {
             if (i < nu) Hs[i * LDM + j] = zsub(Hs[i * LDM + j], zmul(y, zconj(hv[j])));
             Us[i * LDM + j] = zsub(Us[i * LDM + j], zmul(yv, zconj(hv[j])));
           }
@@ -750,7 +798,7 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
     hipFree(gam); hipFree(cnt); hipFree(info);
   };
   if (hipMalloc(&u, sizeof(zd) * n) != hipSuccess || hipMalloc(&part, sizeof(zd) * (size_t)nrc * n) != hipSuccess ||
-      hipMalloc(&w, sizeof(zd) * n) != hipSuccess || hipMalloc(&y, sizeof(zd) * 2 * n) != hipSuccess ||
+      hipMalloc(&w, sizeof(zd) * n) != hipSuccess || hipMalloc(&y, sizeof(zd) * (2 * (size_t)n + (n + 255) / 256 + 1)) != hipSuccess ||
       hipMalloc(&Ubuf, sizeof(zd) * 2 * (size_t)MAXWIN * WIN * WIN) != hipSuccess ||
       hipMalloc(&shifts, sizeof(zd) * 2 * WIN) != hipSuccess || hipMalloc(&ds, sizeof(zd) * 2 * n) != hipSuccess ||
       hipMalloc(&gam, sizeof(double) * 4) != hipSuccess || hipMalloc(&cnt, sizeof(int) * 64) != hipSuccess ||
