@@ -664,32 +664,53 @@ __global__ __launch_bounds__(256) void k_left_apply(zd* A, int n, int r, int bw,
   }
 }
 
+// Window unitary `win` of a list (bw x bw, zero-padded to WIN x WIN) through registers: thread t
+// holds entries t + 256 k, k < 16.
+__device__ inline void load_unitary(const zd* Ubuf, const WinList& wl, int win, int t, zd ru[16]) {
+  const zd* U = Ubuf + (long long)win * WIN * WIN;
+  const int bw = wl.bw[win];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = t + 256 * k;
+    const int i = e >> 6, j = e & 63;
+    ru[k] = (i < bw && j < bw) ? U[i * WIN + j] : zmk(0, 0);
+  }
+}
+__device__ inline void store_unitary(zd* Ul, int t, const zd ru[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = t + 256 * k;
+    Ul[(e >> 6) * LDM + (e & 63)] = ru[k];
+  }
+}
+
 // Deferred right updates: for each window w in order, rows i of X (i < limit_w) get
 // X[i, r_w : r_w+bw_w] <- X[i, r_w : r_w+bw_w] U_w.  limit_w = r_w (mode 1) or nrows (mode 0).
-// One workgroup per 16 rows; wave w owns output columns 16w .. 16w+15.
-__global__ __launch_bounds__(256) void k_right_apply_seq(zd* X, int ldx, int nrows, WinList wl, const zd* Ubuf,
-                                                         int mode) {
-  __shared__ zd Ul[WIN * LDM];
-  __shared__ zd Xs[16 * LDM];
+// One workgroup per 16 rows (first row rb); wave w owns output columns 16w .. 16w+15.
+__device__ inline void right_apply_rows(zd* X, int ldx, int nrows, const WinList& wl, const zd* Ubuf, int mode,
+                                        int rb, zd* Ul, zd* Xs) {
   const int t = threadIdx.x;
   const int w = t >> 6, lane = t & 63;
-  const int rb = blockIdx.x * 16;
-  for (int win = 0; win < wl.nwin; ++win) {
+  // the windows a block takes part in form a suffix of the list (the window origins increase)
+  int win0 = 0;
+  if (mode)
+    while (win0 < wl.nwin && rb >= wl.r[win0]) ++win0;
+  if (win0 >= wl.nwin) return;  // uniform over the block
+  // the next window's unitary is loaded into registers while the current one is applied
+  zd ru[16];
+  load_unitary(Ubuf, wl, win0, t, ru);
+  for (int win = win0; win < wl.nwin; ++win) {
     const int r = wl.r[win], bw = wl.bw[win];
     const int lim = mode ? r : nrows;
-    if (rb >= lim) continue;  // uniform over the block
-    const zd* U = Ubuf + (long long)win * WIN * WIN;
     __syncthreads();
-    for (int e = t; e < WIN * WIN; e += 256) {
-      int i = e >> 6, j = e & 63;
-      Ul[i * LDM + j] = (i < bw && j < bw) ? U[i * WIN + j] : zmk(0, 0);
-    }
+    store_unitary(Ul, t, ru);
     for (int e = t; e < 16 * WIN; e += 256) {
       int i = e >> 6, j = e & 63;
       int row = rb + i;
       Xs[i * LDM + j] = (row < lim && j < bw) ? X[(long long)row * ldx + r + j] : zmk(0, 0);
     }
     __syncthreads();
+    if (win + 1 < wl.nwin) load_unitary(Ubuf, wl, win + 1, t, ru);
     if (16 * w < bw) {
       v4d_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
       const int Kp = (bw + 3) & ~3;
@@ -703,28 +724,25 @@ __global__ __launch_bounds__(256) void k_right_apply_seq(zd* X, int ldx, int nro
   }
 }
 
-// Deferred left updates of the columns right of the active block: columns (hi, n).
-// One workgroup per 16 columns; wave w owns output rows 16w .. 16w+15 of each window.
-__global__ __launch_bounds__(256) void k_left_apply_seq(zd* A, int n, int c0, WinList wl, const zd* Ubuf) {
-  __shared__ zd Ul[WIN * LDM];
-  __shared__ zd Xs[WIN * 17];
+// Deferred left updates of the columns right of the active block: columns (hi, n), 16 per
+// workgroup from column cb; wave w owns output rows 16w .. 16w+15 of each window.
+__device__ inline void left_apply_cols(zd* A, int n, const WinList& wl, const zd* Ubuf, int cb, zd* Ul, zd* Xs) {
   const int t = threadIdx.x;
   const int w = t >> 6, lane = t & 63;
-  const int cb = c0 + blockIdx.x * 16;
+  if (wl.nwin <= 0) return;
+  zd ru[16];
+  load_unitary(Ubuf, wl, 0, t, ru);
   for (int win = 0; win < wl.nwin; ++win) {
     const int r = wl.r[win], bw = wl.bw[win];
-    const zd* U = Ubuf + (long long)win * WIN * WIN;
     __syncthreads();
-    for (int e = t; e < WIN * WIN; e += 256) {
-      int i = e >> 6, j = e & 63;
-      Ul[i * LDM + j] = (i < bw && j < bw) ? U[i * WIN + j] : zmk(0, 0);
-    }
+    store_unitary(Ul, t, ru);
     for (int e = t; e < WIN * 16; e += 256) {
       int i = e >> 4, c = e & 15;
       int col = cb + c;
       Xs[i * 17 + c] = (i < bw && col < n) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
     }
     __syncthreads();
+    if (win + 1 < wl.nwin) load_unitary(Ubuf, wl, win + 1, t, ru);
     if (16 * w < bw) {
       v4d_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
       const int Kp = (bw + 3) & ~3;
@@ -736,6 +754,26 @@ __global__ __launch_bounds__(256) void k_left_apply_seq(zd* A, int n, int c0, Wi
       }
     }
   }
+}
+
+static constexpr int XS_ELEMS = (16 * LDM > WIN * 17) ? 16 * LDM : WIN * 17;
+
+__global__ __launch_bounds__(256) void k_right_apply_seq(zd* X, int ldx, int nrows, WinList wl, const zd* Ubuf,
+                                                         int mode) {
+  __shared__ zd Ul[WIN * LDM];
+  __shared__ zd Xs[XS_ELEMS];
+  right_apply_rows(X, ldx, nrows, wl, Ubuf, mode, blockIdx.x * 16, Ul, Xs);
+}
+
+// The two deferred updates of A in one launch (they touch disjoint parts of A): workgroups
+// [0, nrb) update the rows above the windows, the others the columns right of the active block.
+__global__ __launch_bounds__(256) void k_apply_seq_a(zd* A, int n, int nrb, int c0, WinList wl, const zd* Ubuf) {
+  __shared__ zd Ul[WIN * LDM];
+  __shared__ zd Xs[XS_ELEMS];
+  if ((int)blockIdx.x < nrb)
+    right_apply_rows(A, n, n, wl, Ubuf, 1, blockIdx.x * 16, Ul, Xs);
+  else
+    left_apply_cols(A, n, wl, Ubuf, c0 + (blockIdx.x - nrb) * 16, Ul, Xs);
 }
 
 // Deferred updates of one sweep (or one early deflation / small block).  Z is never read by the
@@ -751,10 +789,11 @@ static void apply_deferred(zd* A, zd* Z, int n, int hi, const WinList& wl, const
   // A: rows above each window
   int maxr = 0;
   for (int w = 0; w < wl.nwin; ++w) maxr = wl.r[w] > maxr ? wl.r[w] : maxr;
-  if (maxr > 0) hipLaunchKernelGGL(k_right_apply_seq, dim3((maxr + 15) / 16), dim3(256), 0, st, A, n, maxr, wl, Ubuf, 1);
-  // A: columns right of the active block
-  if (hi + 1 < n)
-    hipLaunchKernelGGL(k_left_apply_seq, dim3((n - hi - 1 + 15) / 16), dim3(256), 0, st, A, n, hi + 1, wl, Ubuf);
+  // and columns right of the active block, in one launch
+  const int nrb = maxr > 0 ? (maxr + 15) / 16 : 0;
+  const int ncb = hi + 1 < n ? (n - hi - 1 + 15) / 16 : 0;
+  if (nrb + ncb > 0)
+    hipLaunchKernelGGL(k_apply_seq_a, dim3(nrb + ncb), dim3(256), 0, st, A, n, nrb, hi + 1, wl, Ubuf);
 }
 
 static inline double h_cabs1(zd a) { return fabs(a.x) + fabs(a.y); }
