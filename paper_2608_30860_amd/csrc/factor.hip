@@ -255,6 +255,64 @@ __device__ inline double bcast(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+// One wave accumulates a 16 x 16 complex tile C = sum_k A(i, k) B(k, j) over k < K (K padded
+// to a multiple of 4 with zeros by the caller) with FP64 MFMA; A(i, k) and B(k, j) are read from
+// LDS through the accessors.  Accumulator layout: lane l, register r holds row 4r + l/16,
+// column l % 16.
+template <typename FA, typename FB>
+__device__ inline void tile16_mfma(FA getA, FB getB, int K, v4d_t& cr, v4d_t& ci) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kk = lane >> 4;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    zd a = getA(i, k0 + kk);
+    zd b = getB(k0 + kk, i);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+  }
+}
+
+// rows [rp, rp+bwp) x columns [c0, c1] of A <- U^H (those rows), 64 columns at a time, by a
+// workgroup of CHASE_T threads: U in Ul (row stride LDM), the columns in Xs (row stride LDM);
+// wave w computes output rows 16 (w & 3) .. +15 and columns 16 (w >> 2) .. +15 of each 32-column
+// half.  Ends with a barrier, so the caller may reuse Ul and Xs.
+__device__ inline void left_update_block(zd* A, int n, int rp, int bwp, int c0, int c1, const zd* U, zd* Ul,
+                                         zd* Xs) {
+  const int t = threadIdx.x;
+  const int w = t >> 6, lane = t & 63;
+  for (int e = t; e < WIN * WIN; e += CHASE_T) {
+    const int i = e >> 6, j = e & 63;
+    Ul[i * LDM + j] = (i < bwp && j < bwp) ? U[i * WIN + j] : zmk(0, 0);
+  }
+  for (int cb = c0; cb <= c1; cb += 64) {
+    for (int e = t; e < WIN * 64; e += CHASE_T) {
+      const int i = e >> 6, c = e & 63;
+      Xs[i * LDM + c] = (i < bwp && cb + c <= c1) ? A[(long long)(rp + i) * n + cb + c] : zmk(0, 0);
+    }
+    __syncthreads();
+    const int ro = 16 * (w & 3);
+    if (ro < bwp) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int co = 32 * h + 16 * (w >> 2);
+        if (cb + co > c1) continue;
+        v4d_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        const int Kp = (bwp + 3) & ~3;
+        tile16_mfma([&](int i, int k) { return zconj(Ul[k * LDM + ro + i]); },
+                    [&](int k, int j) { return Xs[k * LDM + co + j]; }, Kp, cr, ci);
+        for (int q = 0; q < 4; ++q) {
+          const int row = ro + 4 * q + (lane >> 4), col = cb + co + (lane & 15);
+          if (row < bwp && col <= c1) A[(long long)(rp + row) * n + col] = zmk(cr[q], ci[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Chase the bulge chain through window rows/cols [r, r+bw).  All bulges move in lockstep: at
 // step t bulge b rotates at pair P0 + t - 2b (front bulge first in the equivalent sequential
 // order).  Rotations of one step act on disjoint row pairs and disjoint column pairs, and a
@@ -266,8 +324,14 @@ __device__ inline double bcast(double x, int l) {
 // unitary (lane = row).  The parameters of a bulge read rows q, q+1, which no other bulge's row
 // rotation of the same step writes, so one step needs a barrier only between the row and the
 // column rotations (other bulges' rows meet this bulge's columns) and at its end.
+//
+// The launch also finishes the left update of the previous window of the sweep (unitary Up, rows
+// [rp, rp+bwp); none if Up is null): workgroup 0 applies it to the columns this window adds,
+// [rp+bwp, r+bw), before loading the window; workgroups 1 .. apply it to 64 columns each from
+// r+bw up to ihi, which this window does not touch.
 __global__ __launch_bounds__(CHASE_T) void k_chase(zd* A, int n, int ilo, int ihi, int r, int bw,
-                                                const zd* shifts, int ns, int* cnt, zd* Uout) {
+                                                const zd* shifts, int ns, int* cnt, zd* Uout, const zd* Up,
+                                                int rp, int bwp) {
   __shared__ zd Hs[WIN * LDM];
   __shared__ zd Us[WIN * LDM];
   constexpr int NWV = CHASE_T / 64;                // waves
@@ -275,6 +339,16 @@ __global__ __launch_bounds__(CHASE_T) void k_chase(zd* A, int n, int ilo, int ih
   const int t = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lane = t & 63;
+  if (blockIdx.x > 0) {
+    const int c0 = r + bw + 64 * (blockIdx.x - 1);
+    const int c1 = c0 + 63 < ihi ? c0 + 63 : ihi;
+    if (Up && c0 <= c1) left_update_block(A, n, rp, bwp, c0, c1, Up, Us, Hs);
+    return;
+  }
+  if (Up) {
+    const int c1 = r + bw - 1 < ihi ? r + bw - 1 : ihi;
+    if (rp + bwp <= c1) left_update_block(A, n, rp, bwp, rp + bwp, c1, Up, Us, Hs);
+  }
   {
     zd v[WIN * WIN / CHASE_T];
 #pragma unroll
@@ -615,55 +689,6 @@ __global__ __launch_bounds__(64) void k_small_block(zd* A, int n, int lo, int hi
     }
 }
 
-typedef double v4d_t __attribute__((ext_vector_type(4)));
-
-// One wave accumulates a 16 x 16 complex tile C = sum_k A(i, k) B(k, j) over k < K (K padded
-// to a multiple of 4 with zeros by the caller) with FP64 MFMA; A(i, k) and B(k, j) are read from
-// LDS through the accessors.  Accumulator layout: lane l, register r holds row 4r + l/16,
-// column l % 16.
-template <typename FA, typename FB>
-__device__ inline void tile16_mfma(FA getA, FB getB, int K, v4d_t& cr, v4d_t& ci) {
-  const int lane = threadIdx.x & 63;
-  const int i = lane & 15, kk = lane >> 4;
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    zd a = getA(i, k0 + kk);
-    zd b = getB(k0 + kk, i);
-    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
-  }
-}
-
-// rows [r, r+bw) x columns [c0, c1] <- U^H (those rows).  One workgroup per 16 columns; wave w
-// owns output rows 16w .. 16w+15.
-__global__ __launch_bounds__(256) void k_left_apply(zd* A, int n, int r, int bw, int c0, int c1, const zd* U) {
-  __shared__ zd Ul[WIN * LDM];
-  __shared__ zd Xs[WIN * 17];
-  const int t = threadIdx.x;
-  const int cb = c0 + blockIdx.x * 16;
-  for (int e = t; e < WIN * WIN; e += 256) {
-    int i = e >> 6, j = e & 63;
-    Ul[i * LDM + j] = (i < bw && j < bw) ? U[i * WIN + j] : zmk(0, 0);
-  }
-  for (int e = t; e < WIN * 16; e += 256) {
-    int i = e >> 4, c = e & 15;
-    int col = cb + c;
-    Xs[i * 17 + c] = (i < bw && col <= c1) ? A[(long long)(r + i) * n + col] : zmk(0, 0);
-  }
-  __syncthreads();
-  const int w = t >> 6, lane = t & 63;
-  if (16 * w >= bw) return;
-  v4d_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-  const int Kp = (bw + 3) & ~3;
-  tile16_mfma([&](int i, int k) { return zconj(Ul[k * LDM + 16 * w + i]); },
-              [&](int k, int j) { return Xs[k * 17 + j]; }, Kp, cr, ci);
-  for (int q = 0; q < 4; ++q) {
-    const int row = 16 * w + 4 * q + (lane >> 4), col = cb + (lane & 15);
-    if (row < bw && col <= c1) A[(long long)(r + row) * n + col] = zmk(cr[q], ci[q]);
-  }
-}
-
 // Window unitary `win` of a list (bw x bw, zero-padded to WIN x WIN) through registers: thread t
 // holds entries t + 256 k, k < 16.
 __device__ inline void load_unitary(const zd* Ubuf, const WinList& wl, int win, int t, zd ru[16]) {
@@ -970,10 +995,12 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
     for (int r = ilo;; r += step) {
       int bw = ihi + 1 - r < WIN ? ihi + 1 - r : WIN;
       zd* Uw = U + (long long)wl.nwin * WIN * WIN;
-      hipLaunchKernelGGL(k_chase, dim3(1), dim3(CHASE_T), 0, st, A, n, ilo, ihi, r, bw, sh, ns, cnt, Uw);
-      if (r + bw <= ihi)
-        hipLaunchKernelGGL(k_left_apply, dim3((ihi - (r + bw) + 1 + 15) / 16), dim3(256), 0, st, A, n, r, bw, r + bw,
-                           ihi, (const zd*)Uw);
+      // the previous window's left update rides along (its right part on extra workgroups)
+      const zd* Up = wl.nwin > 0 ? Uw - (long long)WIN * WIN : nullptr;
+      const int rp = wl.nwin > 0 ? wl.r[wl.nwin - 1] : 0, bwp = wl.nwin > 0 ? wl.bw[wl.nwin - 1] : 0;
+      const int nright = (Up && r + bw <= ihi) ? (ihi - (r + bw) + 1 + 63) / 64 : 0;
+      hipLaunchKernelGGL(k_chase, dim3(1 + nright), dim3(CHASE_T), 0, st, A, n, ilo, ihi, r, bw, sh, ns, cnt, Uw, Up,
+                         rp, bwp);
       wl.r[wl.nwin] = r;
       wl.bw[wl.nwin] = bw;
       ++wl.nwin;
