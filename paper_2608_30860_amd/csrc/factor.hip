@@ -13,7 +13,7 @@
 //    are deferred to the end of the sweep and applied window after window by row/column-parallel
 //    kernels (those of Z on a second stream, since the iteration never reads Z).  Active blocks of at most 64 rows are finished in LDS by one wave.  Before each
 //    sweep, aggressive early deflation (Braman, Byers and Mathias, SIAM J. Matrix Anal. Appl. 23,
-//    2002) brings the trailing 32 x 32 window to Schur form in LDS, splits off the eigenvalues
+//    2002) brings the trailing 24 x 24 window to Schur form in LDS, splits off the eigenvalues
 //    whose coupling to the rest of the matrix is below machine precision, and hands the window's
 //    remaining eigenvalues to the sweep as shifts; when many deflate the sweep is skipped.
 // 3. Eigenvectors of T by back substitution (one wave per column) and the inverse of the unit
@@ -31,7 +31,7 @@ static constexpr int NSMAX = 19;  // default bulges per sweep (WIN >= step + 2 *
 static constexpr int NSCAP = 23;  // most bulges one chase kernel holds
 static constexpr int CHASE_T = 512;  // threads of the chase kernel (8 waves, two per SIMD)
 static constexpr int MAXWIN = 256;
-static constexpr int AEDW = 32;   // default early-deflation window rows (<= WIN)
+static constexpr int AEDW = 24;   // default early-deflation window rows (<= WIN)
 
 struct WinList {
   int nwin;
