@@ -345,22 +345,62 @@ __global__ __launch_bounds__(CHASE_T) void k_chase(zd* A, int n, int ilo, int ih
     if (Up && c0 <= c1) left_update_block(A, n, rp, bwp, c0, c1, Up, Us, Hs);
     return;
   }
-  if (Up) {
-    const int c1 = r + bw - 1 < ihi ? r + bw - 1 : ihi;
-    if (rp + bwp <= c1) left_update_block(A, n, rp, bwp, rp + bwp, c1, Up, Us, Hs);
-  }
   {
+    // The window and the operands of the prologue (the previous window's unitary and the columns
+    // [c0p, c1p] this window adds, rows [rp, rp+bwp)) are loaded together.  The prologue's
+    // results land in Hs for the rows inside the window and in A for the rows above it; the
+    // window entries they replace are not stored from v.
+    const int c1p = r + bw - 1;
+    const int c0p = Up ? rp + bwp : c1p + 1;  // empty range without a previous window
     zd v[WIN * WIN / CHASE_T];
 #pragma unroll
     for (int k = 0; k < WIN * WIN / CHASE_T; ++k) {
       const int e = t + CHASE_T * k, i = e >> 6, j = e & 63;
       v[k] = (i < bw && j < bw) ? A[(long long)(r + i) * n + r + j] : zmk(0, 0);
     }
+    v4d_t pr[2], pi[2];
+    const int ro = 16 * (w & 3);
+    if (c0p <= c1p) {
+      for (int e = t; e < WIN * WIN; e += CHASE_T) {
+        const int i = e >> 6, j = e & 63;
+        Us[i * LDM + j] = (i < bwp && j < bwp) ? Up[i * WIN + j] : zmk(0, 0);
+        Hs[i * LDM + j] = (i < bwp && c0p + j <= c1p) ? A[(long long)(rp + i) * n + c0p + j] : zmk(0, 0);
+      }
+      __syncthreads();
+      const int Kp = (bwp + 3) & ~3;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        pr[h] = v4d_t{0, 0, 0, 0};
+        pi[h] = v4d_t{0, 0, 0, 0};
+        const int co = 32 * h + 16 * (w >> 2);
+        if (ro < bwp && c0p + co <= c1p)
+          tile16_mfma([&](int i, int k) { return zconj(Us[k * LDM + ro + i]); },
+                      [&](int k, int j) { return Hs[k * LDM + co + j]; }, Kp, pr[h], pi[h]);
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int k = 0; k < WIN * WIN / CHASE_T; ++k) {
       const int e = t + CHASE_T * k, i = e >> 6, j = e & 63;
-      Hs[i * LDM + j] = v[k];
+      const bool repl = (r + i < rp + bwp) && (r + j >= c0p);
+      if (!repl) Hs[i * LDM + j] = v[k];
       Us[i * LDM + j] = (i == j) ? zmk(1, 0) : zmk(0, 0);
+    }
+    if (c0p <= c1p && ro < bwp) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int co = 32 * h + 16 * (w >> 2);
+        if (c0p + co > c1p) continue;
+        for (int q = 0; q < 4; ++q) {
+          const int row = rp + ro + 4 * q + (lane >> 4), col = c0p + co + (lane & 15);
+          if (row >= rp + bwp || col > c1p) continue;
+          const zd val = zmk(pr[h][q], pi[h][q]);
+          if (row >= r)
+            Hs[(row - r) * LDM + (col - r)] = val;
+          else
+            A[(long long)row * n + col] = val;
+        }
+      }
     }
   }
   // lane u < BPW of wave w owns bulge b = w + NWV u: its shift and its next pair
