@@ -32,6 +32,7 @@ static constexpr int NSCAP = 23;  // most bulges one chase kernel holds
 static constexpr int CHASE_T = 512;  // threads of the chase kernel (8 waves, two per SIMD)
 static constexpr int MAXWIN = 256;
 static constexpr int AEDW = 24;   // default early-deflation window rows (<= WIN)
+static constexpr int WYB = 64;    // Householder reflectors applied to Z per block
 
 struct WinList {
   int nwin;
@@ -41,7 +42,8 @@ struct WinList {
 
 // ------------------------------------------------------------------ Hessenberg reduction -----
 // Reflector for column k: P = I - gam u u^H with u = x + ph*||x|| e_{k+1}, P x = -ph*||x|| e_{k+1}.
-__global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, double* gam) {
+__global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, double* gam, zd* vb, int c,
+                                                double* gb) {
   __shared__ double sh[4];
   __shared__ double tot;
   double s = 0;
@@ -63,11 +65,13 @@ __global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, doub
     if (!skip && i > k) v = A[(long long)i * n + k];
     if (!skip && i == k + 1) v = zadd(x0, zscale(ph, nrm));
     u[i] = v;
+    vb[(long long)i * WYB + c] = v;  // column c of the block of reflectors applied to Z later
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     // u^H u = 2 ||x|| (||x|| + |x0|)
     gam[0] = skip ? 0.0 : 1.0 / (nrm * (nrm + ax0));
+    gb[c] = gam[0];
   }
   if (!skip) {
     for (int i = k + 1 + threadIdx.x; i < n; i += 256)
@@ -79,11 +83,12 @@ __global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, doub
 // A' = A - u w, the right update needs A' u = A u - u (w u), so A u can be formed from the matrix
 // before the left update, together with u^H A:
 //   A <- A - u w - y u^H,  y = gam (A u - u (w u));   Z <- Z - gam (Z u) u^H.
+// Z is updated by blocks of reflectors (k_wy_t and three products, see hessenberg()).
 // Pass 1 (k_hh_pass1): workgroups [0, ncb * nrc) form partial sums of u^H A over row chunks
 // (rows > k; workgroup (cb, rc) = (b % ncb, b / ncb), 64 columns each); the others form the raw
-// row sums (A u)_i and (Z u)_i, one row per wave (A rows first, then Z rows).
-__global__ __launch_bounds__(256) void k_hh_pass1(const zd* A, const zd* Z, int n, int k, const zd* u, int rchunk,
-                                                  int ncb, int nrc, zd* part, zd* y) {
+// row sums (A u)_i, one row per wave.
+__global__ __launch_bounds__(256) void k_hh_pass1(const zd* A, int n, int k, const zd* u, int rchunk, int ncb,
+                                                  int nrc, zd* part, zd* y) {
   __shared__ zd ss[4][64];
   const int nlp = ncb * nrc;
   if ((int)blockIdx.x < nlp) {
@@ -105,11 +110,9 @@ __global__ __launch_bounds__(256) void k_hh_pass1(const zd* A, const zd* Z, int 
   }
   const int row = (blockIdx.x - nlp) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= 2 * n) return;
-  const zd* X = row < n ? A : Z;
-  const int i = row < n ? row : row - n;
+  if (row >= n) return;
   zd s = zmk(0, 0);
-  for (int j = k + 1 + lane; j < n; j += 64) s = zadd(s, zmul(X[(long long)i * n + j], u[j]));
+  for (int j = k + 1 + lane; j < n; j += 64) s = zadd(s, zmul(A[(long long)row * n + j], u[j]));
   double a = s.x, b = s.y;
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_down(a, o, 64);
@@ -139,8 +142,8 @@ __global__ __launch_bounds__(256) void k_hh_wreduce(const zd* part, int nrc, int
   __syncthreads();
   if (threadIdx.x == 0) wup[blockIdx.x] = zadd(zadd(red[0], red[1]), zadd(red[2], red[3]));
 }
-// A <- A - u w - y u^H (all rows, columns > k) and Z <- Z - gam (Z u) u^H, one pass
-__global__ __launch_bounds__(256) void k_hh_update(zd* A, zd* Z, int n, int k, const zd* u, const zd* w, const zd* y,
+// A <- A - u w - y u^H (all rows, columns > k), one pass
+__global__ __launch_bounds__(256) void k_hh_update(zd* A, int n, int k, const zd* u, const zd* w, const zd* y,
                                                    const zd* wup, int nwb, const double* gam) {
   __shared__ zd s_wu;
   if (threadIdx.x == 0) {
@@ -152,22 +155,44 @@ __global__ __launch_bounds__(256) void k_hh_update(zd* A, zd* Z, int n, int k, c
   const zd wu = s_wu;
   const double g = gam[0];
   const long long cols = n - k - 1;
-  const long long tot = 2LL * n * cols;
+  const long long tot = (long long)n * cols;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
     const long long row = t / cols;
     const int j = k + 1 + (int)(t % cols);
     const zd cu = zconj(u[j]);
-    if (row < n) {
-      const zd ui = u[row];
-      const zd yi = zscale(zsub(y[row], zmul(ui, wu)), g);
-      const long long e = row * n + j;
-      A[e] = zsub(zsub(A[e], zmul(ui, w[j])), zmul(yi, cu));
-    } else {
-      const long long e = (row - n) * n + j;
-      Z[e] = zsub(Z[e], zmul(zscale(y[row], g), cu));
-    }
+    const zd ui = u[row];
+    const zd yi = zscale(zsub(y[row], zmul(ui, wu)), g);
+    const long long e = row * n + j;
+    A[e] = zsub(zsub(A[e], zmul(ui, w[j])), zmul(yi, cu));
   }
+}
+
+// Compact WY form of a block of nb reflectors (Schreiber and Van Loan): H_0 H_1 ... H_{nb-1} =
+// I - V T V^H with T upper triangular, T_ii = gam_i and T[0:i, i] = -gam_i T[0:i, 0:i] (V^H v_i).
+// gr holds V^H V (row stride WYB), staged in LDS; one wave (lane j: row j of T), column i of T
+// after column i - 1.
+__global__ __launch_bounds__(64) void k_wy_t(const zd* gr, const double* gb, int nb, zd* tb) {
+  __shared__ zd Ts[WYB * (WYB + 1)];
+  __shared__ zd Gs[WYB * (WYB + 1)];
+  const int j = threadIdx.x;
+  for (int e = j; e < WYB * WYB; e += 64) {
+    const int r = e / WYB, c = e % WYB;
+    Ts[r * (WYB + 1) + c] = zmk(0, 0);
+    Gs[r * (WYB + 1) + c] = (r < nb && c < nb) ? gr[e] : zmk(0, 0);
+  }
+  __syncthreads();
+  for (int i = 0; i < nb; ++i) {
+    const double gi = gb[i];
+    if (j < i) {
+      zd acc = zmk(0, 0);
+      for (int l = j; l < i; ++l) acc = zadd(acc, zmul(Ts[j * (WYB + 1) + l], Gs[l * (WYB + 1) + i]));
+      Ts[j * (WYB + 1) + i] = zscale(acc, -gi);
+    }
+    if (j == i) Ts[i * (WYB + 1) + i] = zmk(gi, 0);
+    __syncthreads();
+  }
+  for (int e = j; e < WYB * WYB; e += 64) tb[e] = Ts[(e / WYB) * (WYB + 1) + e % WYB];
 }
 
 static int gridN(long long len) {
@@ -176,20 +201,82 @@ static int gridN(long long len) {
   return (int)(nb < 1 ? 1 : nb);
 }
 
-// y holds 2 n row sums and, after them, the partial sums of w u (one per workgroup of k_hh_wreduce)
-static int hessenberg(zd* A, zd* Z, int n, zd* u, double* gam, zd* part, zd* w, zd* y, hipStream_t st) {
+// y holds the n row sums and, after 2 n entries, the partial sums of w u (one per workgroup of
+// k_hh_wreduce).  The reflectors reach Z in blocks of WYB: with V (n x nb, row stride WYB; rows
+// <= k0 are zero) and T from k_wy_t, Z <- Z - ((Z V) T) V^H.  The products over the rows of V are
+// split into NBK row chunks (batches summed through the workspace) so that they fill the chip.
+struct WyBufs {
+  zd* vb;    // n x WYB
+  double* gb;  // WYB
+  zd* gr;    // WYB x WYB
+  zd* tb;    // WYB x WYB
+  zd* w1;    // n x WYB
+  zd* w2;    // n x WYB
+  zd* ws;    // split-K partials
+  long long ws_bytes;
+};
+static constexpr int WY_NBK = 8;
+static long long wy_ws_bytes(int n) {
+  const long long a = gemm_ws_bytes(PREC_F64, n, WYB, WY_NBK), b = gemm_ws_bytes(PREC_F64, WYB, WYB, WY_NBK);
+  return a > b ? a : b;
+}
+static int wy_flush(zd* Z, int n, int k0, int nb, const WyBufs& wy, hipStream_t st) {
+  // rows s0 .. n-1 of V: from k0 + 1, extended downwards over zero rows to a multiple of WY_NBK
+  int nbk = WY_NBK;
+  int kr = n - (k0 + 1);
+  int s0 = n - ((kr + nbk - 1) / nbk) * nbk;
+  if (s0 < 0) {
+    nbk = 1;
+    s0 = k0 + 1;
+  }
+  const int kt = n - s0, kc = kt / nbk;
+  const zd* V = wy.vb + (long long)s0 * WYB;
+  GemmDesc g;  // V^H V
+  g.M = nb; g.N = nb; g.K = kc; g.nbatch = nbk;
+  g.A = V; g.lda = WYB; g.sA = (long long)kc * WYB; g.opA = OP_C;
+  g.B = V; g.ldb = WYB; g.sB = (long long)kc * WYB; g.opB = OP_N;
+  g.C = wy.gr; g.ldc = WYB; g.ws = wy.ws; g.ws_bytes = wy.ws_bytes;
+  if (gemm(PREC_F64, g, st)) return -4;
+  hipLaunchKernelGGL(k_wy_t, dim3(1), dim3(64), 0, st, (const zd*)wy.gr, (const double*)wy.gb, nb, wy.tb);
+  GemmDesc h;  // W1 = Z[:, s0:] V
+  h.M = n; h.N = nb; h.K = kc; h.nbatch = nbk;
+  h.A = Z + s0; h.lda = n; h.sA = kc; h.opA = OP_N;
+  h.B = V; h.ldb = WYB; h.sB = (long long)kc * WYB; h.opB = OP_N;
+  h.C = wy.w1; h.ldc = WYB; h.ws = wy.ws; h.ws_bytes = wy.ws_bytes;
+  if (gemm(PREC_F64, h, st)) return -4;
+  GemmDesc q;  // W2 = W1 T
+  q.M = n; q.N = nb; q.K = nb;
+  q.A = wy.w1; q.lda = WYB; q.opA = OP_N;
+  q.B = wy.tb; q.ldb = WYB; q.opB = OP_N;
+  q.C = wy.w2; q.ldc = WYB;
+  if (gemm(PREC_F64, q, st)) return -4;
+  GemmDesc z;  // Z[:, s0:] -= W2 V^H
+  z.M = n; z.N = kt; z.K = nb;
+  z.A = wy.w2; z.lda = WYB; z.opA = OP_N;
+  z.B = V; z.ldb = WYB; z.opB = OP_C;
+  z.C = Z + s0; z.ldc = n; z.ar = -1.0; z.beta = 1;
+  return gemm(PREC_F64, z, st) ? -4 : 0;
+}
+
+static int hessenberg(zd* A, zd* Z, int n, zd* u, double* gam, zd* part, zd* w, zd* y, const WyBufs& wy,
+                      hipStream_t st) {
   const int nrc = 16;
+  int k0 = 0;
   for (int k = 0; k + 2 < n; ++k) {
     const int rows = n - k - 1;
     const int rchunk = (rows + nrc - 1) / nrc;
     const int ncb = (rows + 63) / 64;
     const int nwb = (rows + 255) / 256;
-    hipLaunchKernelGGL(k_hh_vec, dim3(1), dim3(256), 0, st, A, n, k, u, gam);
-    hipLaunchKernelGGL(k_hh_pass1, dim3(ncb * nrc + (2 * n + 3) / 4), dim3(256), 0, st, A, Z, n, k, u, rchunk, ncb,
-                       nrc, part, y);
+    hipLaunchKernelGGL(k_hh_vec, dim3(1), dim3(256), 0, st, A, n, k, u, gam, wy.vb, k - k0, wy.gb);
+    hipLaunchKernelGGL(k_hh_pass1, dim3(ncb * nrc + (n + 3) / 4), dim3(256), 0, st, A, n, k, u, rchunk, ncb, nrc,
+                       part, y);
     hipLaunchKernelGGL(k_hh_wreduce, dim3(nwb), dim3(256), 0, st, part, nrc, n, k, gam, u, w, y + 2 * n);
-    hipLaunchKernelGGL(k_hh_update, dim3(gridN(2LL * n * rows)), dim3(256), 0, st, A, Z, n, k, u, w, y, y + 2 * n,
+    hipLaunchKernelGGL(k_hh_update, dim3(gridN((long long)n * rows)), dim3(256), 0, st, A, n, k, u, w, y, y + 2 * n,
                        nwb, gam);
+    if (k - k0 + 1 == WYB || k + 3 >= n) {
+      if (wy_flush(Z, n, k0, k - k0 + 1, wy, st)) return -4;
+      k0 = k + 1;
+    }
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
@@ -890,6 +977,7 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
   hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   double* gam = nullptr;
   int *cnt = nullptr, *info = nullptr;
+  WyBufs wy{};
   const int nrc = 16;
   auto cleanup = [&]() {
     if (zs) hipStreamSynchronize(zs);
@@ -900,13 +988,18 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
     if (zs) hipStreamDestroy(zs);
     hipFree(u); hipFree(part); hipFree(w); hipFree(y); hipFree(Ubuf); hipFree(shifts); hipFree(ds);
     hipFree(gam); hipFree(cnt); hipFree(info);
+    hipFree(wy.vb); hipFree(wy.gb); hipFree(wy.gr); hipFree(wy.tb); hipFree(wy.w1); hipFree(wy.w2); hipFree(wy.ws);
   };
   if (hipMalloc(&u, sizeof(zd) * n) != hipSuccess || hipMalloc(&part, sizeof(zd) * (size_t)nrc * n) != hipSuccess ||
       hipMalloc(&w, sizeof(zd) * n) != hipSuccess || hipMalloc(&y, sizeof(zd) * (2 * (size_t)n + (n + 255) / 256 + 1)) != hipSuccess ||
       hipMalloc(&Ubuf, sizeof(zd) * 2 * (size_t)MAXWIN * WIN * WIN) != hipSuccess ||
       hipMalloc(&shifts, sizeof(zd) * 2 * WIN) != hipSuccess || hipMalloc(&ds, sizeof(zd) * 2 * n) != hipSuccess ||
       hipMalloc(&gam, sizeof(double) * 4) != hipSuccess || hipMalloc(&cnt, sizeof(int) * 64) != hipSuccess ||
-      hipMalloc(&info, sizeof(int) * 4) != hipSuccess) {
+      hipMalloc(&info, sizeof(int) * 4) != hipSuccess || hipMalloc(&wy.vb, sizeof(zd) * (size_t)n * WYB) != hipSuccess ||
+      hipMalloc(&wy.gb, sizeof(double) * WYB) != hipSuccess || hipMalloc(&wy.gr, sizeof(zd) * WYB * WYB) != hipSuccess ||
+      hipMalloc(&wy.tb, sizeof(zd) * WYB * WYB) != hipSuccess || hipMalloc(&wy.w1, sizeof(zd) * (size_t)n * WYB) != hipSuccess ||
+      hipMalloc(&wy.w2, sizeof(zd) * (size_t)n * WYB) != hipSuccess ||
+      hipMalloc(&wy.ws, (size_t)(wy.ws_bytes = wy_ws_bytes(n) > 16 ? wy_ws_bytes(n) : 16)) != hipSuccess) {
     cleanup();
     return -5;
   }
@@ -936,13 +1029,13 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
   };
   auto t0 = std::chrono::steady_clock::now();
   hipLaunchKernelGGL(k_identity, dim3(gridN((long long)n * n)), dim3(256), 0, st, Z, n);
-  if (n > 2) hessenberg(A, Z, n, u, gam, part, w, y, st);
+  const int hrc = n > 2 ? hessenberg(A, Z, n, u, gam, part, w, y, wy, st) : 0;
   hipStreamSynchronize(st);
   auto t1 = std::chrono::steady_clock::now();
   if (t_hess) *t_hess = std::chrono::duration<double>(t1 - t0).count();
-  if (stop_after_hessenberg) {
+  if (hrc || stop_after_hessenberg) {
     cleanup();
-    return hipGetLastError() == hipSuccess ? 0 : -4;
+    return (hrc == 0 && hipGetLastError() == hipSuccess) ? 0 : -4;
   }
 
   const double ulp = 2.220446049250313e-16;
