@@ -210,19 +210,33 @@ __device__ inline int qr_lds(zd* H, zd* Q, int m, int full) {
         H[p * LDM + lane] = zadd(zscale(x, cs), zmul(sn, y));
         H[(p + 1) * LDM + lane] = (p > l && lane == p - 1) ? zmk(0, 0) : zsub(zscale(y, cs), zmul(zconj(sn), x));
       }
-      // columns p, p+1 for rows r0 .. min(p+2, ihi), and of Q
+      // columns p, p+1 for rows r0 .. min(p+2, ihi), and of Q; for m <= 32 the rows of Q ride
+      // in lanes 32 .. 63 of the same instructions
       const int r1 = p + 2 < ihi ? p + 2 : ihi;
       zd nx = zmk(0, 0);
-      if (lane >= r0 && lane <= r1) {
-        const zd x = H[lane * LDM + p], y = H[lane * LDM + p + 1];
-        nx = zadd(zscale(x, cs), zmul(zconj(sn), y));
-        H[lane * LDM + p] = nx;
-        H[lane * LDM + p + 1] = zsub(zscale(y, cs), zmul(sn, x));
-      }
-      if (Q && lane < m) {
-        const zd x = Q[lane * LDM + p], y = Q[lane * LDM + p + 1];
-        Q[lane * LDM + p] = zadd(zscale(x, cs), zmul(zconj(sn), y));
-        Q[lane * LDM + p + 1] = zsub(zscale(y, cs), zmul(sn, x));
+      if (Q && m <= 32) {
+        const bool qh = lane >= 32;
+        const int rr = lane & 31;
+        zd* M = qh ? Q : H;
+        if (qh ? rr < m : (rr >= r0 && rr <= r1)) {
+          const zd x = M[rr * LDM + p], y = M[rr * LDM + p + 1];
+          const zd nv = zadd(zscale(x, cs), zmul(zconj(sn), y));
+          M[rr * LDM + p] = nv;
+          M[rr * LDM + p + 1] = zsub(zscale(y, cs), zmul(sn, x));
+          if (!qh) nx = nv;
+        }
+      } else {
+        if (lane >= r0 && lane <= r1) {
+          const zd x = H[lane * LDM + p], y = H[lane * LDM + p + 1];
+          nx = zadd(zscale(x, cs), zmul(zconj(sn), y));
+          H[lane * LDM + p] = nx;
+          H[lane * LDM + p + 1] = zsub(zscale(y, cs), zmul(sn, x));
+        }
+        if (Q && lane < m) {
+          const zd x = Q[lane * LDM + p], y = Q[lane * LDM + p + 1];
+          Q[lane * LDM + p] = zadd(zscale(x, cs), zmul(zconj(sn), y));
+          Q[lane * LDM + p + 1] = zsub(zscale(y, cs), zmul(sn, x));
+        }
       }
       if (p + 1 < ihi) {
         f = zreadlane(nx, p + 1);
