@@ -46,16 +46,18 @@ __global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, doub
                                                 double* gb) {
   __shared__ double sh[4];
   __shared__ double tot;
+  // the part below x0 is summed on its own: ||x||^2 - |x0|^2 cancels to zero when that part is
+  // small against x0, and the column would be left unreduced
   double s = 0;
-  for (int i = k + 1 + threadIdx.x; i < n; i += 256) s += zabs2(A[(long long)i * n + k]);
+  for (int i = k + 2 + threadIdx.x; i < n; i += 256) s += zabs2(A[(long long)i * n + k]);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) tot = sh[0] + sh[1] + sh[2] + sh[3];
   __syncthreads();
-  double nrm2 = tot;
+  const double tail = tot;
   zd x0 = A[(long long)(k + 1) * n + k];
-  double tail = nrm2 - zabs2(x0);
+  double nrm2 = zabs2(x0) + tail;
   double nrm = sqrt(nrm2);
   double ax0 = sqrt(zabs2(x0));
   zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
@@ -726,13 +728,14 @@ __global__ __launch_bounds__(64) void k_aed(zd* A, int n, int kw, int ihi, zd* U
     // independent accumulators to shorten their dependency chains.
     for (int k = 0; k + 2 < nu; ++k) {
       __syncthreads();
-      double nrm2 = (t > k && t < nu) ? zabs2(Hs[t * LDM + k]) : 0.0;
+      // the part below x0 on its own (see k_hh_vec)
+      double tail = (t > k + 1 && t < nu) ? zabs2(Hs[t * LDM + k]) : 0.0;
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) nrm2 += __shfl_xor(nrm2, o, 64);
-      nrm2 = __shfl(nrm2, 0, 64);  // one value for the whole wave: the branch below is uniform
+      for (int o = 32; o > 0; o >>= 1) tail += __shfl_xor(tail, o, 64);
+      tail = __shfl(tail, 0, 64);  // one value for the whole wave: the branch below is uniform
       const zd x0 = Hs[(k + 1) * LDM + k];
       const double ax0 = sqrt(zabs2(x0));
-      const double tail = nrm2 - ax0 * ax0;
+      const double nrm2 = zabs2(x0) + tail;
       const double gam = tail > 0 ? 1.0 / (sqrt(nrm2) * (sqrt(nrm2) + ax0)) : 0.0;  // I - gam u u^H
       if (gam != 0.0) {
         const double nrm = sqrt(nrm2);
@@ -1104,7 +1107,7 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
       }
       if (nd > 0) stall = 0;
       // many deflations: look again before sweeping
-      if (100 * nd > 14 * jw) continue;
+      if (100 * nd > 20 * jw) continue;
       ihi -= nd;
       size = ihi - ilo + 1;
       if (size <= WIN) continue;

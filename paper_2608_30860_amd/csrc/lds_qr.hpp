@@ -80,10 +80,12 @@ __device__ inline void hessenberg_lds(zd* A, zd* Q, int m, zd* u) {
   const int t = threadIdx.x & 63;
   for (int k = 0; k + 2 < m; ++k) {
     // column below the subdiagonal
-    double nrm2 = 0;
-    for (int i = k + 1; i < m; ++i) nrm2 += zabs2(A[i * LDM + k]);
-    double tail = nrm2 - zabs2(A[(k + 1) * LDM + k]);
-    if (tail <= 0.0) continue;  // already reduced
+    // the part below the subdiagonal on its own: ||x||^2 - |x0|^2 cancels to zero when it is
+    // small against x0, and the column would be left unreduced
+    double tail = 0;
+    for (int i = k + 2; i < m; ++i) tail += zabs2(A[i * LDM + k]);
+    if (!(tail > 0.0)) continue;  // already reduced
+    const double nrm2 = zabs2(A[(k + 1) * LDM + k]) + tail;
     double nrm = sqrt(nrm2);
     zd x0 = A[(k + 1) * LDM + k];
     double ax0 = sqrt(zabs2(x0));

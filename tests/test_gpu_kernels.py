@@ -174,6 +174,28 @@ def test_hessenberg_and_schur(n):
             assert np.max(np.abs(np.tril(An, -1))) == 0
 
 
+@pytest.mark.parametrize("n", [40, 96])
+def test_hessenberg_and_schur_small_tail(n):
+    """Columns whose entries below the subdiagonal are tiny against the subdiagonal (1e-10 against
+    O(1)): the reflector must still annihilate them (a norm formed as ||x||^2 - |x0|^2 cancels to
+    zero there, and the entries would be dropped later)."""
+    print(f"[case] schur small tail n={n}", flush=True)
+    rng = np.random.default_rng(n + 11)
+    G = np.triu(crand(rng, n, n)) / np.sqrt(n)
+    i = np.arange(1, n)
+    G[i, i - 1] = crand(rng, n - 1)
+    G = G + 1e-10 * np.tril(crand(rng, n, n), -2)
+    for stop in (1, 0):
+        A = T(G)
+        Z = T(np.zeros((n, n)))
+        assert lib().lindx_schur(P(A), P(Z), n, stop, None) == 0
+        torch.cuda.synchronize()
+        An, Zn = A.cpu().numpy(), Z.cpu().numpy()
+        assert np.max(np.abs(Zn.conj().T @ Zn - np.eye(n))) < 1e-12
+        assert np.max(np.abs(Zn @ An @ Zn.conj().T - G)) < 1e-12
+        assert np.max(np.abs(np.tril(An, -2 if stop else -1))) == 0.0
+
+
 @pytest.mark.parametrize("m", [1, 2, 7, 30, 64])
 def test_small_eig(m):
     rng = np.random.default_rng(m)
