@@ -95,8 +95,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the path's "
-              "multi-GPU sharding is described in DESIGN.md and is not run here.", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); sharding the path "
+              "over several GPUs is a design, not an implementation.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
