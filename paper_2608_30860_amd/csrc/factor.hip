@@ -2,20 +2,24 @@
 //
 //   G = Z T Z^H    (complex Schur form, Z unitary, T upper triangular)
 //
-// 1. Householder reduction to upper Hessenberg form (one reflector per column; the reflector
-//    build is one workgroup, the two-sided updates are bandwidth-bound multi-workgroup kernels).
+// 1. Householder reduction to upper Hessenberg form: per column, one workgroup builds the
+//    reflector and two bandwidth-bound passes apply it to both sides of A (A u is formed before
+//    the left update, so one read-write pass does both); the reflectors reach Z in blocks of 64
+//    in compact WY form, by three FP64 products.
 // 2. Multishift QR iteration (complex single-shift bulges, up to 19 per sweep, shifts from the
 //    eigenvalues of the trailing block).  A chain of bulges is chased down the diagonal in
 //    64 x 64 windows that advance by 24 rows: each window is chased in LDS by one workgroup that
-//    accumulates the window's unitary U_w; the product of U_w^H with the rest of the window's
-//    rows inside the active block is applied at once (the next window reads it), while the
-//    updates of the rows above the window, of the columns right of the active block, and of Z
-//    are deferred to the end of the sweep and applied window after window by row/column-parallel
-//    kernels (those of Z on a second stream, since the iteration never reads Z).  Active blocks of at most 64 rows are finished in LDS by one wave.  Before each
-//    sweep, aggressive early deflation (Braman, Byers and Mathias, SIAM J. Matrix Anal. Appl. 23,
-//    2002) brings the trailing 24 x 24 window to Schur form in LDS, splits off the eigenvalues
-//    whose coupling to the rest of the matrix is below machine precision, and hands the window's
-//    remaining eigenvalues to the sweep as shifts; when many deflate the sweep is skipped.
+//    accumulates the window's unitary U_w; the launch of the next window first applies U_w^H to
+//    the rest of the window's rows inside the active block (the columns the next window adds in
+//    its own prologue, the columns beyond it on extra workgroups), while the updates of the rows
+//    above the windows, of the columns right of the active block, and of Z are deferred to the
+//    end of the sweep and applied window after window by row/column-parallel kernels (those of Z
+//    on a second stream, since the iteration never reads Z).  Active blocks of at most 64 rows
+//    are finished in LDS by one wave.  Before each sweep, aggressive early deflation (Braman,
+//    Byers and Mathias, SIAM J. Matrix Anal. Appl. 23, 2002) brings the trailing 24 x 24 window
+//    to Schur form in LDS, splits off the eigenvalues whose coupling to the rest of the matrix is
+//    below machine precision, and hands the window's remaining eigenvalues to the sweep as
+//    shifts; when many deflate the sweep is skipped.
 // 3. Eigenvectors of T by back substitution (one wave per column) and the inverse of the unit
 //    upper-triangular eigenvector matrix, giving the eigenbasis route G = U diag(s) U^{-1}.
 #include <vector>
