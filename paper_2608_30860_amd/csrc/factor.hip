@@ -1161,43 +1161,77 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
 }
 
 // ------------------------------------------------------------------ triangular solves --------
-// mode 0 (eigenvectors of T): column j solves (T - T_jj I) y = 0, y_j = 1.
+// mode 0 (eigenvectors of T): column j solves (T - T_jj I) y = 0 with y_j = 1.
 // mode 1 (inverse of a unit upper-triangular M): column j solves M x = e_j.
-// One wave per column; y lives in LDS; x_i = -(sum_{k=i+1..j} M_ik x_k) / d_i.
-__global__ __launch_bounds__(64) void k_upper_backsolve(const zd* M, zd* X, int n, int mode) {
+// Both are back substitutions x_i = -(sum_{k=i+1..j} M_ik x_k) / d_i, d_i = M_ii - M_jj (tiny
+// values lifted to ulp |M_jj|) or 1.  One work-group per column, longest columns first; the
+// right-hand sides of the rows not yet solved live in LDS.  Rows are solved BS_B at a time: the
+// diagonal block sits in the registers of wave 0 (lane r owns row k0 + r, each solved value is
+// broadcast with v_readlane), then the block's contribution to every row above it is one
+// rank-BS_B update spread over the work-group, so no step waits on a global load or a reduction.
+constexpr int BS_T = 256, BS_B = 16;
+__global__ __launch_bounds__(BS_T) void k_upper_backsolve(const zd* M, zd* X, int n, int mode) {
   extern __shared__ zd ys[];
-  const int j = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int j = n - 1 - (int)blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
   const double ulp = 2.220446049250313e-16;
-  zd mjj = M[(long long)j * n + j];
-  double smin = fmax(ulp * cabs1(mjj), 1e-290);
-  if (lane == 0) ys[j] = zmk(1, 0);
-  __syncthreads();
-  for (int i = j - 1; i >= 0; --i) {
-    double a = 0, b = 0;
-    const zd* row = M + (long long)i * n;
-    for (int k = i + 1 + lane; k <= j; k += 64) {
-      zd p = zmul(row[k], ys[k]);
-      a += p.x;
-      b += p.y;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      a += __shfl_xor(a, o, 64);
-      b += __shfl_xor(b, o, 64);
-    }
-    zd acc = zmk(-a, -b);
-    zd xi;
-    if (mode == 0) {
-      zd den = zsub(row[i], mjj);
-      if (cabs1(den) < smin) den = zmk(smin, 0);
-      xi = zdiv(acc, den);
-    } else {
-      xi = acc;
-    }
-    if (lane == 0) ys[i] = xi;
-    __syncthreads();
+  const zd mjj = M[(long long)j * n + j];
+  const double smin = fmax(ulp * cabs1(mjj), 1e-290);
+  for (int i = t; i < j; i += BS_T) {
+    const zd v = M[(long long)i * n + j];
+    ys[i] = zmk(-v.x, -v.y);
   }
-  for (int i = lane; i < n; i += 64) X[(long long)i * n + j] = (i <= j) ? ys[i] : zmk(0, 0);
+  if (t == 0) ys[j] = zmk(1, 0);
+  __syncthreads();
+  for (int top = j; top > 0;) {
+    const int nb = min(BS_B, top), k0 = top - nb;
+    if (t < 64) {
+      const bool own = lane < nb;
+      const zd* row = M + (long long)(k0 + (own ? lane : 0)) * n + k0;
+      zd m[BS_B];
+#pragma unroll
+      for (int c = 0; c < BS_B; ++c) m[c] = (own && c < nb) ? row[c] : zmk(0, 0);
+      zd acc = own ? ys[k0 + lane] : zmk(0, 0);
+      zd rd = zmk(1, 0);
+      if (mode == 0 && own) {
+        zd den = zsub(row[lane], mjj);
+        if (cabs1(den) < smin) den = zmk(smin, 0);
+        rd = zdiv(zmk(1, 0), den);
+      }
+#pragma unroll
+      for (int c = BS_B - 1; c >= 0; --c) {
+        if (c < nb) {
+          const zd xl = mode == 0 ? zmul(acc, rd) : acc;
+          const zd x = zmk(bcast(xl.x, c), bcast(xl.y, c));
+          if (lane < c) acc = zsub(acc, zmul(m[c], x));
+          if (lane == c) acc = x;
+        }
+      }
+      if (own) ys[k0 + lane] = acc;
+    }
+    __syncthreads();
+    if (k0 > 0) {  // then nb == BS_B
+      zd xv[BS_B];
+#pragma unroll
+      for (int c = 0; c < BS_B; ++c) xv[c] = ys[k0 + c];
+      for (int i = t; i < k0; i += BS_T) {
+        const zd* row = M + (long long)i * n + k0;
+        double ar = ys[i].x, ai = ys[i].y;
+#pragma unroll
+        for (int c = 0; c < BS_B; ++c) {
+          const zd mv = row[c];
+          ar = fma(-mv.x, xv[c].x, ar);
+          ar = fma(mv.y, xv[c].y, ar);
+          ai = fma(-mv.x, xv[c].y, ai);
+          ai = fma(-mv.y, xv[c].x, ai);
+        }
+        ys[i] = zmk(ar, ai);
+      }
+      __syncthreads();
+    }
+    top = k0;
+  }
+  for (int i = t; i < n; i += BS_T) X[(long long)i * n + j] = (i <= j) ? ys[i] : zmk(0, 0);
 }
 
 static int backsolve_lds_attr(size_t lds) {
@@ -1211,13 +1245,13 @@ static int backsolve_lds_attr(size_t lds) {
 int trevec(const zd* T, zd* Y, int n, hipStream_t st) {
   size_t lds = sizeof(zd) * (size_t)n;
   if (backsolve_lds_attr(lds)) return -1;
-  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(64), lds, st, T, Y, n, 0);
+  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(BS_T), lds, st, T, Y, n, 0);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 int triinv_unit(const zd* Y, zd* Yinv, int n, hipStream_t st) {
   size_t lds = sizeof(zd) * (size_t)n;
   if (backsolve_lds_attr(lds)) return -1;
-  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(64), lds, st, Y, Yinv, n, 1);
+  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(BS_T), lds, st, Y, Yinv, n, 1);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 __global__ void k_diag(const zd* T, zd* s, int n) {

@@ -211,7 +211,7 @@ def test_small_eig(m):
         assert np.min(np.abs(wn - z)) < 1e-10
 
 
-@pytest.mark.parametrize("n", [1, 5, 64, 130])
+@pytest.mark.parametrize("n", [1, 5, 17, 64, 130, 600])
 def test_trevec_triinv(n):
     rng = np.random.default_rng(n + 1)
     Tm = np.triu(crand(rng, n, n)) + np.diag(np.arange(n) * 0.5)
