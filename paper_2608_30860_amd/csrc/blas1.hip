@@ -407,15 +407,26 @@ int scale_cols(zd* X, int n, const double* s, int invert, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_cols, dim3(grid_for(len)), dim3(RB), 0, st, X, n, s, invert);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
-__global__ void k_col_norms(const zd* X, int n, double* out) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// Euclidean norm of every column: 16 waves per block of 64 columns, wave w summing rows
+// i = w (mod 16); the partial sums are added in a fixed order (deterministic).
+static constexpr int CN_W = 16;
+__global__ __launch_bounds__(64 * CN_W) void k_col_norms(const zd* X, int n, double* out) {
+  __shared__ double ps[CN_W][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   double s = 0;
-  for (int i = 0; i < n; ++i) s += zabs2(X[(long long)i * n + j]);
-  out[j] = sqrt(s);
+  if (j < n)
+    for (int i = w; i < n; i += CN_W) s += zabs2(X[(long long)i * n + j]);
+  ps[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < n) {
+    double t = 0;
+    for (int q = 0; q < CN_W; ++q) t += ps[q][lane];
+    out[j] = sqrt(t);
+  }
 }
 int col_norms(const zd* X, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_col_norms, dim3((n + 63) / 64), dim3(64), 0, st, X, n, out);
+  hipLaunchKernelGGL(k_col_norms, dim3((n + 63) / 64), dim3(64 * CN_W), 0, st, X, n, out);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
@@ -445,9 +456,9 @@ __global__ void k_gemv_c(const zd* A, int n, const zd* x, zd* y) {
   }
   y[j] = zmk(a, b);
 }
-// A^H x in two passes for large n: workgroup (column block, row chunk) sums 128 rows of 64
+// A^H x in two passes for large n: workgroup (column block, row chunk) sums 32 rows of 64
 // columns into part[chunk][j]; the second pass adds the chunks (fixed order, deterministic)
-static constexpr int GEMV_RC = 128;
+static constexpr int GEMV_RC = 32;
 __global__ void k_gemv_c_part(const zd* A, int n, const zd* x, zd* part) {
   const int j = blockIdx.x * 64 + threadIdx.x;
   const int i0 = blockIdx.y * GEMV_RC;

@@ -1164,34 +1164,60 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
 // mode 0 (eigenvectors of T): column j solves (T - T_jj I) y = 0 with y_j = 1.
 // mode 1 (inverse of a unit upper-triangular M): column j solves M x = e_j.
 // Both are back substitutions x_i = -(sum_{k=i+1..j} M_ik x_k) / d_i, d_i = M_ii - M_jj (tiny
-// values lifted to ulp |M_jj|) or 1.  One work-group per column, longest columns first; the
-// right-hand sides of the rows not yet solved live in LDS.  Rows are solved BS_B at a time: the
-// diagonal block sits in the registers of wave 0 (lane r owns row k0 + r, each solved value is
-// broadcast with v_readlane), then the block's contribution to every row above it is one
-// rank-BS_B update spread over the work-group, so no step waits on a global load or a reduction.
-constexpr int BS_T = 256, BS_B = 16;
+// values lifted to ulp |M_jj|) or 1.  One work-group per column; the right-hand sides of the rows
+// not yet solved live in LDS.  Rows go in blocks of BS_B aligned to multiples of BS_B (x_j = 1
+// enters through the first block like a solved value): the diagonal block sits in the registers
+// of wave 0 (lane r owns row kb + r, each solved value is broadcast with v_readlane), then the
+// block's contribution to every row above is one rank-BS_B update over the work-group, so no step
+// waits on a global load or a reduction.  Work-groups are dispatched to the 8 XCDs in turn; the
+// column map gives each XCD runs of BS_R neighbouring columns, longest first, which sweep the
+// same aligned row segments at about the same time and so share them in that XCD's L2.
+constexpr int BS_T = 256, BS_B = 16, BS_R = 16;
+static int backsolve_grid(int n) { return ((n + 8 * BS_R - 1) / (8 * BS_R)) * 8 * BS_R; }
+
+// ys[i] -= sum_c M[i][kb + c] x[kb + c] for i < kb; FIRST: the block holding x_j = 1, whose
+// columns beyond j are not read.
+template <bool FIRST>
+__device__ inline void backsolve_bulk(const zd* M, zd* ys, int n, int j, int kb, int t) {
+  zd xv[BS_B];
+#pragma unroll
+  for (int c = 0; c < BS_B; ++c) xv[c] = (!FIRST || kb + c <= j) ? ys[kb + c] : zmk(0, 0);
+  for (int i = t; i < kb; i += BS_T) {
+    const zd* row = M + (long long)i * n + kb;
+    double ar = ys[i].x, ai = ys[i].y;
+#pragma unroll
+    for (int c = 0; c < BS_B; ++c) {
+      if (!FIRST || kb + c <= j) {
+        const zd mv = row[c];
+        ar = fma(-mv.x, xv[c].x, ar);
+        ar = fma(mv.y, xv[c].y, ar);
+        ai = fma(-mv.x, xv[c].y, ai);
+        ai = fma(-mv.y, xv[c].x, ai);
+      }
+    }
+    ys[i] = zmk(ar, ai);
+  }
+}
+
 __global__ __launch_bounds__(BS_T) void k_upper_backsolve(const zd* M, zd* X, int n, int mode) {
   extern __shared__ zd ys[];
-  const int j = n - 1 - (int)blockIdx.x;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int j = n - 1 - ((slot / BS_R) * 8 * BS_R + xcd * BS_R + slot % BS_R);
+  if (j < 0) return;  // padding of the grid to whole rounds (uniform over the work-group)
   const int t = threadIdx.x, lane = t & 63;
   const double ulp = 2.220446049250313e-16;
   const zd mjj = M[(long long)j * n + j];
   const double smin = fmax(ulp * cabs1(mjj), 1e-290);
-  for (int i = t; i < j; i += BS_T) {
-    const zd v = M[(long long)i * n + j];
-    ys[i] = zmk(-v.x, -v.y);
-  }
-  if (t == 0) ys[j] = zmk(1, 0);
+  for (int i = t; i <= j; i += BS_T) ys[i] = zmk(i == j ? 1.0 : 0.0, 0);
   __syncthreads();
-  for (int top = j; top > 0;) {
-    const int nb = min(BS_B, top), k0 = top - nb;
+  for (int kb = (j / BS_B) * BS_B; kb >= 0; kb -= BS_B) {
     if (t < 64) {
-      const bool own = lane < nb;
-      const zd* row = M + (long long)(k0 + (own ? lane : 0)) * n + k0;
+      const bool own = lane < BS_B && kb + lane < j;
+      const zd* row = M + (long long)(kb + (own ? lane : 0)) * n + kb;
       zd m[BS_B];
 #pragma unroll
-      for (int c = 0; c < BS_B; ++c) m[c] = (own && c < nb) ? row[c] : zmk(0, 0);
-      zd acc = own ? ys[k0 + lane] : zmk(0, 0);
+      for (int c = 0; c < BS_B; ++c) m[c] = (own && kb + c <= j) ? row[c] : zmk(0, 0);
+      zd acc = own ? ys[kb + lane] : zmk(0, 0);
       zd rd = zmk(1, 0);
       if (mode == 0 && own) {
         zd den = zsub(row[lane], mjj);
@@ -1200,36 +1226,26 @@ __global__ __launch_bounds__(BS_T) void k_upper_backsolve(const zd* M, zd* X, in
       }
 #pragma unroll
       for (int c = BS_B - 1; c >= 0; --c) {
-        if (c < nb) {
-          const zd xl = mode == 0 ? zmul(acc, rd) : acc;
-          const zd x = zmk(bcast(xl.x, c), bcast(xl.y, c));
+        if (kb + c <= j) {
+          zd x = zmk(1, 0);
+          if (kb + c < j) {
+            const zd xl = mode == 0 ? zmul(acc, rd) : acc;
+            x = zmk(bcast(xl.x, c), bcast(xl.y, c));
+          }
           if (lane < c) acc = zsub(acc, zmul(m[c], x));
           if (lane == c) acc = x;
         }
       }
-      if (own) ys[k0 + lane] = acc;
+      if (own) ys[kb + lane] = acc;
     }
     __syncthreads();
-    if (k0 > 0) {  // then nb == BS_B
-      zd xv[BS_B];
-#pragma unroll
-      for (int c = 0; c < BS_B; ++c) xv[c] = ys[k0 + c];
-      for (int i = t; i < k0; i += BS_T) {
-        const zd* row = M + (long long)i * n + k0;
-        double ar = ys[i].x, ai = ys[i].y;
-#pragma unroll
-        for (int c = 0; c < BS_B; ++c) {
-          const zd mv = row[c];
-          ar = fma(-mv.x, xv[c].x, ar);
-          ar = fma(mv.y, xv[c].y, ar);
-          ai = fma(-mv.x, xv[c].y, ai);
-          ai = fma(-mv.y, xv[c].x, ai);
-        }
-        ys[i] = zmk(ar, ai);
-      }
+    if (kb > 0) {
+      if (kb + BS_B > j)
+        backsolve_bulk<true>(M, ys, n, j, kb, t);
+      else
+        backsolve_bulk<false>(M, ys, n, j, kb, t);
       __syncthreads();
     }
-    top = k0;
   }
   for (int i = t; i < n; i += BS_T) X[(long long)i * n + j] = (i <= j) ? ys[i] : zmk(0, 0);
 }
@@ -1245,13 +1261,13 @@ static int backsolve_lds_attr(size_t lds) {
 int trevec(const zd* T, zd* Y, int n, hipStream_t st) {
   size_t lds = sizeof(zd) * (size_t)n;
   if (backsolve_lds_attr(lds)) return -1;
-  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(BS_T), lds, st, T, Y, n, 0);
+  hipLaunchKernelGGL(k_upper_backsolve, dim3(backsolve_grid(n)), dim3(BS_T), lds, st, T, Y, n, 0);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 int triinv_unit(const zd* Y, zd* Yinv, int n, hipStream_t st) {
   size_t lds = sizeof(zd) * (size_t)n;
   if (backsolve_lds_attr(lds)) return -1;
-  hipLaunchKernelGGL(k_upper_backsolve, dim3(n), dim3(BS_T), lds, st, Y, Yinv, n, 1);
+  hipLaunchKernelGGL(k_upper_backsolve, dim3(backsolve_grid(n)), dim3(BS_T), lds, st, Y, Yinv, n, 1);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 __global__ void k_diag(const zd* T, zd* s, int n) {

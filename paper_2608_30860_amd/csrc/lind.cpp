@@ -125,6 +125,7 @@ static int count_nonfinite(Ctx& c, const zd* x, long long len, int* flag_dev, bo
 static int power_norm(Ctx& c, const zd* M, zd* x, zd* y, int iters, double* out) {
   const int n = c.n;
   double nrm = 0;
+  if (iters < 1) return LIND_EINVAL;
   for (int it = 0; it < iters; ++it) {
     // y holds n entries of an n x n buffer; the rest is the scratch of the two-pass A^H x
     zd* scratch = gemv_scratch_elems(n) <= (long long)n * n - n ? y + n : nullptr;
@@ -132,9 +133,10 @@ static int power_norm(Ctx& c, const zd* M, zd* x, zd* y, int iters, double* out)
     TRY(gemv(M, n, OP_C, y, x, scratch, c.st));
     TRY(nrm2(x, n, (double*)c.dsc, c.dscr, c.st));
     TRY(scale_by_inv(x, n, (const double*)c.dsc, c.st));
-    TRY(c.fetch(c.dsc, sizeof(double)));
-    nrm = ((const double*)c.hsc)[0];
   }
+  // only the last iterate's norm is used: one read-back after the loop
+  TRY(c.fetch(c.dsc, sizeof(double)));
+  nrm = ((const double*)c.hsc)[0];
   *out = std::sqrt(nrm);
   return 0;
 }
