@@ -472,16 +472,22 @@ __global__ void k_gemv_c_part(const zd* A, int n, const zd* x, zd* part) {
   }
   part[(long long)blockIdx.y * n + j] = zmk(a, b);
 }
-__global__ void k_gemv_c_sum(const zd* part, int n, int chunks, zd* y) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// second pass: 4 waves per 64 columns, wave w adding chunks c = w (mod 4); the four partial
+// sums are then added in a fixed order (deterministic)
+__global__ __launch_bounds__(256) void k_gemv_c_sum(const zd* part, int n, int chunks, zd* y) {
+  __shared__ zd ps[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   double a = 0, b = 0;
-  for (int c = 0; c < chunks; ++c) {
-    const zd p = part[(long long)c * n + j];
-    a += p.x;
-    b += p.y;
-  }
-  y[j] = zmk(a, b);
+  if (j < n)
+    for (int c = w; c < chunks; c += 4) {
+      const zd p = part[(long long)c * n + j];
+      a += p.x;
+      b += p.y;
+    }
+  ps[w][lane] = zmk(a, b);
+  __syncthreads();
+  if (w == 0 && j < n) y[j] = zadd(zadd(ps[0][lane], ps[1][lane]), zadd(ps[2][lane], ps[3][lane]));
 }
 long long gemv_scratch_elems(int n) { return (long long)((n + GEMV_RC - 1) / GEMV_RC) * n; }
 int gemv(const zd* A, int n, int opA, const zd* x, zd* y, zd* scratch, hipStream_t st) {
@@ -490,7 +496,7 @@ int gemv(const zd* A, int n, int opA, const zd* x, zd* y, zd* scratch, hipStream
   } else if (scratch && n > 2 * GEMV_RC) {
     const int chunks = (n + GEMV_RC - 1) / GEMV_RC;
     hipLaunchKernelGGL(k_gemv_c_part, dim3((n + 63) / 64, chunks), dim3(64), 0, st, A, n, x, scratch);
-    hipLaunchKernelGGL(k_gemv_c_sum, dim3((n + 255) / 256), dim3(256), 0, st, (const zd*)scratch, n, chunks, y);
+    hipLaunchKernelGGL(k_gemv_c_sum, dim3((n + 63) / 64), dim3(256), 0, st, (const zd*)scratch, n, chunks, y);
   } else {
     hipLaunchKernelGGL(k_gemv_c, dim3((n + 63) / 64), dim3(64), 0, st, A, n, x, y);
   }

@@ -1164,31 +1164,33 @@ int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double*
 // mode 0 (eigenvectors of T): column j solves (T - T_jj I) y = 0 with y_j = 1.
 // mode 1 (inverse of a unit upper-triangular M): column j solves M x = e_j.
 // Both are back substitutions x_i = -(sum_{k=i+1..j} M_ik x_k) / d_i, d_i = M_ii - M_jj (tiny
-// values lifted to ulp |M_jj|) or 1.  One work-group per column; the right-hand sides of the rows
-// not yet solved live in LDS.  Rows go in blocks of BS_B aligned to multiples of BS_B (x_j = 1
-// enters through the first block like a solved value): the diagonal block sits in the registers
-// of wave 0 (lane r owns row kb + r, each solved value is broadcast with v_readlane), then the
-// block's contribution to every row above is one rank-BS_B update over the work-group, so no step
-// waits on a global load or a reduction.  Work-groups are dispatched to the 8 XCDs in turn; the
-// column map gives each XCD runs of BS_R neighbouring columns, longest first, which sweep the
-// same aligned row segments at about the same time and so share them in that XCD's L2.
+// values lifted to ulp |M_jj|) or 1.  The kernel reads Mt = M^T (plain transpose, upper triangle
+// of M only), so that lanes running down a column of M read consecutive addresses.  One
+// work-group per column; the right-hand sides of the rows not yet solved live in LDS.  Rows go in
+// blocks of BS_B aligned to multiples of BS_B (x_j = 1 enters through the first block like a
+// solved value): the diagonal block sits in the registers of wave 0 (lane r owns row kb + r, each
+// solved value is broadcast with v_readlane), then the block's contribution to every row above is
+// one rank-BS_B update over the work-group, so no step waits on a global load or a reduction.
+// Work-groups are dispatched to the 8 XCDs in turn; the column map gives each XCD runs of BS_R
+// neighbouring columns, longest first, which sweep the same row blocks at about the same time and
+// so share them in that XCD's L2.
 constexpr int BS_T = 256, BS_B = 16, BS_R = 16;
 static int backsolve_grid(int n) { return ((n + 8 * BS_R - 1) / (8 * BS_R)) * 8 * BS_R; }
+#define MT(i, k) Mt[(long long)(k) * n + (i)]  // M[i][k]
 
 // ys[i] -= sum_c M[i][kb + c] x[kb + c] for i < kb; FIRST: the block holding x_j = 1, whose
 // columns beyond j are not read.
 template <bool FIRST>
-__device__ inline void backsolve_bulk(const zd* M, zd* ys, int n, int j, int kb, int t) {
+__device__ inline void backsolve_bulk(const zd* Mt, zd* ys, int n, int j, int kb, int t) {
   zd xv[BS_B];
 #pragma unroll
   for (int c = 0; c < BS_B; ++c) xv[c] = (!FIRST || kb + c <= j) ? ys[kb + c] : zmk(0, 0);
   for (int i = t; i < kb; i += BS_T) {
-    const zd* row = M + (long long)i * n + kb;
     double ar = ys[i].x, ai = ys[i].y;
 #pragma unroll
     for (int c = 0; c < BS_B; ++c) {
       if (!FIRST || kb + c <= j) {
-        const zd mv = row[c];
+        const zd mv = MT(i, kb + c);
         ar = fma(-mv.x, xv[c].x, ar);
         ar = fma(mv.y, xv[c].y, ar);
         ai = fma(-mv.x, xv[c].y, ai);
@@ -1199,28 +1201,28 @@ __device__ inline void backsolve_bulk(const zd* M, zd* ys, int n, int j, int kb,
   }
 }
 
-__global__ __launch_bounds__(BS_T) void k_upper_backsolve(const zd* M, zd* X, int n, int mode) {
+__global__ __launch_bounds__(BS_T) void k_upper_backsolve(const zd* Mt, zd* X, int n, int mode) {
   extern __shared__ zd ys[];
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int j = n - 1 - ((slot / BS_R) * 8 * BS_R + xcd * BS_R + slot % BS_R);
   if (j < 0) return;  // padding of the grid to whole rounds (uniform over the work-group)
   const int t = threadIdx.x, lane = t & 63;
   const double ulp = 2.220446049250313e-16;
-  const zd mjj = M[(long long)j * n + j];
+  const zd mjj = MT(j, j);
   const double smin = fmax(ulp * cabs1(mjj), 1e-290);
   for (int i = t; i <= j; i += BS_T) ys[i] = zmk(i == j ? 1.0 : 0.0, 0);
   __syncthreads();
   for (int kb = (j / BS_B) * BS_B; kb >= 0; kb -= BS_B) {
     if (t < 64) {
       const bool own = lane < BS_B && kb + lane < j;
-      const zd* row = M + (long long)(kb + (own ? lane : 0)) * n + kb;
+      const int r = kb + (own ? lane : 0);
       zd m[BS_B];
 #pragma unroll
-      for (int c = 0; c < BS_B; ++c) m[c] = (own && kb + c <= j) ? row[c] : zmk(0, 0);
-      zd acc = own ? ys[kb + lane] : zmk(0, 0);
+      for (int c = 0; c < BS_B; ++c) m[c] = (own && kb + c <= j) ? MT(r, kb + c) : zmk(0, 0);
+      zd acc = own ? ys[r] : zmk(0, 0);
       zd rd = zmk(1, 0);
       if (mode == 0 && own) {
-        zd den = zsub(row[lane], mjj);
+        zd den = zsub(MT(r, r), mjj);
         if (cabs1(den) < smin) den = zmk(smin, 0);
         rd = zdiv(zmk(1, 0), den);
       }
@@ -1236,40 +1238,54 @@ __global__ __launch_bounds__(BS_T) void k_upper_backsolve(const zd* M, zd* X, in
           if (lane == c) acc = x;
         }
       }
-      if (own) ys[kb + lane] = acc;
+      if (own) ys[r] = acc;
     }
     __syncthreads();
     if (kb > 0) {
       if (kb + BS_B > j)
-        backsolve_bulk<true>(M, ys, n, j, kb, t);
+        backsolve_bulk<true>(Mt, ys, n, j, kb, t);
       else
-        backsolve_bulk<false>(M, ys, n, j, kb, t);
+        backsolve_bulk<false>(Mt, ys, n, j, kb, t);
       __syncthreads();
     }
   }
   for (int i = t; i < n; i += BS_T) X[(long long)i * n + j] = (i <= j) ? ys[i] : zmk(0, 0);
 }
+#undef MT
 
-static int backsolve_lds_attr(size_t lds) {
+// Y = X^T (plain transpose) on the tiles of an n x n matrix that meet its upper triangle, 32 x 32
+// tiles through LDS; tiles wholly below the diagonal are skipped (the back substitutions never
+// read them).
+__global__ __launch_bounds__(256) void k_transpose_upper(const zd* X, zd* Y, int n) {
+  __shared__ zd tile[32][33];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi * 32 + r, k = bj * 32 + tx;
+    if (i < n && k < n) tile[r][tx] = X[(long long)i * n + k];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int k = bj * 32 + r, i = bi * 32 + tx;
+    if (i < n && k < n) Y[(long long)k * n + i] = tile[tx][r];
+  }
+}
+
+static int backsolve(const zd* M, zd* Mt, zd* X, int n, int mode, hipStream_t st) {
+  const size_t lds = sizeof(zd) * (size_t)n;
   if (lds > 160 * 1024) return -1;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)k_upper_backsolve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
           hipSuccess)
     return -1;
-  return 0;
-}
-int trevec(const zd* T, zd* Y, int n, hipStream_t st) {
-  size_t lds = sizeof(zd) * (size_t)n;
-  if (backsolve_lds_attr(lds)) return -1;
-  hipLaunchKernelGGL(k_upper_backsolve, dim3(backsolve_grid(n)), dim3(BS_T), lds, st, T, Y, n, 0);
+  const int nt = (n + 31) / 32;
+  hipLaunchKernelGGL(k_transpose_upper, dim3(nt, nt), dim3(256), 0, st, M, Mt, n);
+  hipLaunchKernelGGL(k_upper_backsolve, dim3(backsolve_grid(n)), dim3(BS_T), lds, st, (const zd*)Mt, X, n, mode);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
-int triinv_unit(const zd* Y, zd* Yinv, int n, hipStream_t st) {
-  size_t lds = sizeof(zd) * (size_t)n;
-  if (backsolve_lds_attr(lds)) return -1;
-  hipLaunchKernelGGL(k_upper_backsolve, dim3(backsolve_grid(n)), dim3(BS_T), lds, st, Y, Yinv, n, 1);
-  return hipGetLastError() == hipSuccess ? 0 : -4;
-}
+int trevec(const zd* T, zd* ws, zd* Y, int n, hipStream_t st) { return backsolve(T, ws, Y, n, 0, st); }
+int triinv_unit(const zd* Y, zd* ws, zd* Yinv, int n, hipStream_t st) { return backsolve(Y, ws, Yinv, n, 1, st); }
 __global__ void k_diag(const zd* T, zd* s, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) s[i] = T[(long long)i * n + i];

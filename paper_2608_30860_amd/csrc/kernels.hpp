@@ -132,9 +132,10 @@ struct SchurWork;
 // on entry A holds G.  Returns 0 on success, -3 if the QR iteration failed to converge.
 int schur_factor(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr);
 int schur_factor_ex(zd* A, zd* Z, int n, hipStream_t st, double* t_hess, double* t_qr, int mode);
-// Y: eigenvectors of upper-triangular T (unit diagonal), Yinv = Y^{-1} (unit upper triangular)
-int trevec(const zd* T, zd* Y, int n, hipStream_t st);
-int triinv_unit(const zd* Y, zd* Yinv, int n, hipStream_t st);
+// Y: eigenvectors of upper-triangular T (unit diagonal), Yinv = Y^{-1} (unit upper triangular);
+// ws: n x n device workspace (receives the transposed input), overwritten
+int trevec(const zd* T, zd* ws, zd* Y, int n, hipStream_t st);
+int triinv_unit(const zd* Y, zd* ws, zd* Yinv, int n, hipStream_t st);
 // extract diagonal of T into s
 int diag_extract(const zd* T, zd* s, int n, hipStream_t st);
 

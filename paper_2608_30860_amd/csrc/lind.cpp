@@ -186,8 +186,9 @@ static int ctx_factor(lind_ctx* X) {
   if (!(minre > 1e-13 * std::max(c.gnorm, 1e-300)) || maxre >= 0)
     return c.fail(LIND_ESINGULAR, "spec(G) meets the imaginary axis: S is not invertible");
   // eigenvectors: Y (upper triangular), Y^{-1}; U = Z Y, V = Z Y^{-H}; unit columns of U
-  TRY(trevec(c.T, c.w2, n, c.st));
-  TRY(triinv_unit(c.w2, c.w3, n, c.st));
+  // (U and V serve as the solves' workspaces before they receive their values)
+  TRY(trevec(c.T, c.U, c.w2, n, c.st));
+  TRY(triinv_unit(c.w2, c.V, c.w3, n, c.st));
   TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_N, c.w2, n, OP_N, c.U, n, one, 0));
   TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_N, c.w3, n, OP_C, c.V, n, one, 0));
   double* cn = (double*)c.dscr;  // n doubles

@@ -52,15 +52,20 @@ extern "C" int lindx_small_eig(const void* A, int m, void* w, void* Y, void* str
   return h ? -3 : 0;
 }
 
+static int with_square_ws(int n, int (*f)(const zd*, zd*, zd*, int, hipStream_t), const void* in, void* out,
+                          void* stream) {
+  zd* ws = nullptr;
+  if (hipMalloc(&ws, sizeof(zd) * (size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1)) != hipSuccess) return -5;
+  int rc = f((const zd*)in, ws, (zd*)out, n, (hipStream_t)stream);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == 0) rc = -4;
+  hipFree(ws);
+  return rc;
+}
 extern "C" int lindx_trevec(const void* T, void* Y, int n, void* stream) {
-  int rc = trevec((const zd*)T, (zd*)Y, n, (hipStream_t)stream);
-  if (rc) return rc;
-  return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -4;
+  return with_square_ws(n, trevec, T, Y, stream);
 }
 extern "C" int lindx_triinv(const void* Y, void* Yinv, int n, void* stream) {
-  int rc = triinv_unit((const zd*)Y, (zd*)Yinv, n, (hipStream_t)stream);
-  if (rc) return rc;
-  return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -4;
+  return with_square_ws(n, triinv_unit, Y, Yinv, stream);
 }
 extern "C" int lindx_trisylv(const void* T, void* X, int n, double sr, double si, void* stream) {
   zd* ws = nullptr;
