@@ -46,56 +46,57 @@ struct WinList {
 
 // ------------------------------------------------------------------ Hessenberg reduction -----
 // Reflector for column k: P = I - gam u u^H with u = x + ph*||x|| e_{k+1}, P x = -ph*||x|| e_{k+1}.
-__global__ __launch_bounds__(256) void k_hh_vec(zd* A, int n, int k, zd* u, double* gam, zd* vb, int c,
-                                                double* gb) {
+// Each column costs two launches.  Column k of A is kept contiguously in `col` (written by the
+// update of column k - 1; column 0 by k_hh_col0), and every workgroup of pass 1 derives the
+// reflector's scalars from it in the same order, so all obtain the same bits without a launch of
+// their own.
+struct HHScal {
+  zd x0, ph;
+  double nrm, ax0;
+  bool skip;
+};
+// Called by all 256 threads of a workgroup.  The part below x0 is summed on its own: ||x||^2 -
+// |x0|^2 cancels to zero when that part is small against x0, and the column would be left
+// unreduced.
+__device__ inline HHScal hh_scalars(const zd* col, int n, int k) {
   __shared__ double sh[4];
-  __shared__ double tot;
-  // the part below x0 is summed on its own: ||x||^2 - |x0|^2 cancels to zero when that part is
-  // small against x0, and the column would be left unreduced
   double s = 0;
-  for (int i = k + 2 + threadIdx.x; i < n; i += 256) s += zabs2(A[(long long)i * n + k]);
+  for (int i = k + 2 + threadIdx.x; i < n; i += 256) s += zabs2(col[i]);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) tot = sh[0] + sh[1] + sh[2] + sh[3];
-  __syncthreads();
-  const double tail = tot;
-  zd x0 = A[(long long)(k + 1) * n + k];
-  double nrm2 = zabs2(x0) + tail;
-  double nrm = sqrt(nrm2);
-  double ax0 = sqrt(zabs2(x0));
-  zd ph = ax0 > 0 ? zscale(x0, 1.0 / ax0) : zmk(1, 0);
-  bool skip = !(tail > 0.0);
-  for (int i = threadIdx.x; i < n; i += 256) {
-    zd v = zmk(0, 0);
-    if (!skip && i > k) v = A[(long long)i * n + k];
-    if (!skip && i == k + 1) v = zadd(x0, zscale(ph, nrm));
-    u[i] = v;
-    vb[(long long)i * WYB + c] = v;  // column c of the block of reflectors applied to Z later
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // u^H u = 2 ||x|| (||x|| + |x0|)
-    gam[0] = skip ? 0.0 : 1.0 / (nrm * (nrm + ax0));
-    gb[c] = gam[0];
-  }
-  if (!skip) {
-    for (int i = k + 1 + threadIdx.x; i < n; i += 256)
-      A[(long long)i * n + k] = (i == k + 1) ? zscale(ph, -nrm) : zmk(0, 0);
-  }
+  const double tail = sh[0] + sh[1] + sh[2] + sh[3];
+  HHScal r;
+  r.x0 = col[k + 1];
+  r.nrm = sqrt(zabs2(r.x0) + tail);
+  r.ax0 = sqrt(zabs2(r.x0));
+  r.ph = r.ax0 > 0 ? zscale(r.x0, 1.0 / r.ax0) : zmk(1, 0);
+  r.skip = !(tail > 0.0);
+  return r;
+}
+__device__ inline zd hh_u(const zd* col, const HHScal& r, int k, int i) {
+  if (r.skip || i <= k) return zmk(0, 0);
+  return i == k + 1 ? zadd(r.x0, zscale(r.ph, r.nrm)) : col[i];
+}
+__global__ void k_hh_col0(const zd* A, int n, zd* col) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) col[i] = A[(long long)i * n];
 }
 
 // The two one-sided updates of column k are applied in one pass.  With w = gam u^H A (left) and
 // A' = A - u w, the right update needs A' u = A u - u (w u), so A u can be formed from the matrix
 // before the left update, together with u^H A:
-//   A <- A - u w - y u^H,  y = gam (A u - u (w u));   Z <- Z - gam (Z u) u^H.
+//   A <- A - u w - y u^H,  y = gam (A u - u (w u)),  w u = gam u^H (A u);   Z <- Z - gam (Z u) u^H.
 // Z is updated by blocks of reflectors (k_wy_t and three products, see hessenberg()).
 // Pass 1 (k_hh_pass1): workgroups [0, ncb * nrc) form partial sums of u^H A over row chunks
 // (rows > k; workgroup (cb, rc) = (b % ncb, b / ncb), 64 columns each); the others form the raw
-// row sums (A u)_i, one row per wave.
-__global__ __launch_bounds__(256) void k_hh_pass1(const zd* A, int n, int k, const zd* u, int rchunk, int ncb,
-                                                  int nrc, zd* part, zd* y) {
+// row sums (A u)_i, one row per wave, and store, for their rows, u, column c of the reflector
+// block and the reduced column k of A (which no workgroup of this pass reads).
+__global__ __launch_bounds__(256) void k_hh_pass1(zd* A, int n, int k, const zd* col, int rchunk, int ncb, int nrc,
+                                                  zd* part, zd* y, zd* u, double* gam, zd* vb, int c,
+                                                  double* gb) {
   __shared__ zd ss[4][64];
+  const HHScal r = hh_scalars(col, n, k);
   const int nlp = ncb * nrc;
   if ((int)blockIdx.x < nlp) {
     const int cb = blockIdx.x % ncb, rc = blockIdx.x / ncb;
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_hh_pass1(const zd* A, int n, int k, con
     const int r1 = r0 + rchunk < n ? r0 + rchunk : n;
     zd s = zmk(0, 0);
     if (j < n)
-      for (int i = r0 + rg; i < r1; i += 4) s = zadd(s, zcmul(u[i], A[(long long)i * n + j]));
+      for (int i = r0 + rg; i < r1; i += 4) s = zadd(s, zcmul(hh_u(col, r, k, i), A[(long long)i * n + j]));
     ss[rg][threadIdx.x & 63] = s;
     __syncthreads();
     if (rg == 0 && j < n) {
@@ -114,63 +115,72 @@ __global__ __launch_bounds__(256) void k_hh_pass1(const zd* A, int n, int k, con
     }
     return;
   }
+  if ((int)blockIdx.x == nlp && threadIdx.x == 0) {
+    const double g = r.skip ? 0.0 : 1.0 / (r.nrm * (r.nrm + r.ax0));  // u^H u = 2 ||x|| (||x|| + |x0|)
+    gam[0] = g;
+    gb[c] = g;
+  }
   const int row = (blockIdx.x - nlp) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   zd s = zmk(0, 0);
-  for (int j = k + 1 + lane; j < n; j += 64) s = zadd(s, zmul(A[(long long)row * n + j], u[j]));
+  for (int j = k + 1 + lane; j < n; j += 64) s = zadd(s, zmul(A[(long long)row * n + j], hh_u(col, r, k, j)));
   double a = s.x, b = s.y;
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_down(a, o, 64);
     b += __shfl_down(b, o, 64);
   }
-  if (lane == 0) y[row] = zmk(a, b);
-}
-// w_j = gam sum_rc part[rc][j] (j > k), and the partial sums of w u of this workgroup's columns
-__global__ __launch_bounds__(256) void k_hh_wreduce(const zd* part, int nrc, int n, int k, const double* gam,
-                                                    const zd* u, zd* w, zd* wup) {
-  __shared__ zd red[4];
-  const int j = k + 1 + blockIdx.x * 256 + threadIdx.x;
-  zd wu = zmk(0, 0);
-  if (j < n) {
-    zd s = zmk(0, 0);
-    for (int r = 0; r < nrc; ++r) s = zadd(s, part[(long long)r * n + j]);
-    s = zscale(s, gam[0]);
-    w[j] = s;
-    wu = zmul(s, u[j]);
+  if (lane == 0) {
+    y[row] = zmk(a, b);
+    const zd ur = hh_u(col, r, k, row);
+    u[row] = ur;
+    vb[(long long)row * WYB + c] = ur;
+    if (!r.skip && row > k) A[(long long)row * n + k] = (row == k + 1) ? zscale(r.ph, -r.nrm) : zmk(0, 0);
   }
-  double a = wu.x, b = wu.y;
+}
+// A <- A - u w - y u^H on a tile of 64 columns (> k) and HU_R rows.  Each workgroup forms w_j for
+// its columns from the row-chunk partial sums, and w u = gam sum_i conj(u_i) (A u)_i from the row
+// sums (the same bits in every workgroup); the new column k + 1 also goes to `col`.
+constexpr int HU_R = 128;
+__global__ __launch_bounds__(256) void k_hh_update(zd* A, int n, int k, const zd* u, const double* gam,
+                                                   const zd* y, const zd* part, int nrc, zd* col) {
+  __shared__ double sh[2][4];
+  __shared__ zd ws[64];
+  const int t = threadIdx.x, lane = t & 63, rg = t >> 6;
+  const double g = gam[0];
+  double a = 0, b = 0;
+  for (int i = k + 1 + t; i < n; i += 256) {
+    const zd p = zcmul(u[i], y[i]);
+    a += p.x;
+    b += p.y;
+  }
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_down(a, o, 64);
     b += __shfl_down(b, o, 64);
   }
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = zmk(a, b);
-  __syncthreads();
-  if (threadIdx.x == 0) wup[blockIdx.x] = zadd(zadd(red[0], red[1]), zadd(red[2], red[3]));
-}
-// A <- A - u w - y u^H (all rows, columns > k), one pass
-__global__ __launch_bounds__(256) void k_hh_update(zd* A, int n, int k, const zd* u, const zd* w, const zd* y,
-                                                   const zd* wup, int nwb, const double* gam) {
-  __shared__ zd s_wu;
-  if (threadIdx.x == 0) {
-    zd t = zmk(0, 0);
-    for (int b = 0; b < nwb; ++b) t = zadd(t, wup[b]);
-    s_wu = t;
+  if (lane == 0) {
+    sh[0][rg] = a;
+    sh[1][rg] = b;
+  }
+  const int j = k + 1 + blockIdx.x * 64 + lane;
+  if (rg == 0) {
+    zd s = zmk(0, 0);
+    if (j < n)
+      for (int q = 0; q < nrc; ++q) s = zadd(s, part[(long long)q * n + j]);
+    ws[lane] = zscale(s, g);
   }
   __syncthreads();
-  const zd wu = s_wu;
-  const double g = gam[0];
-  const long long cols = n - k - 1;
-  const long long tot = (long long)n * cols;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-    const long long row = t / cols;
-    const int j = k + 1 + (int)(t % cols);
-    const zd cu = zconj(u[j]);
-    const zd ui = u[row];
-    const zd yi = zscale(zsub(y[row], zmul(ui, wu)), g);
-    const long long e = row * n + j;
-    A[e] = zsub(zsub(A[e], zmul(ui, w[j])), zmul(yi, cu));
+  const zd wu = zscale(zmk(sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]), g);
+  if (j >= n) return;
+  const zd wj = ws[lane], cu = zconj(u[j]);
+  const int i0 = blockIdx.y * HU_R, i1 = i0 + HU_R < n ? i0 + HU_R : n;
+  for (int i = i0 + rg; i < i1; i += 4) {
+    const zd ui = u[i];
+    const zd yi = zscale(zsub(y[i], zmul(ui, wu)), g);
+    const long long e = (long long)i * n + j;
+    const zd v = zsub(zsub(A[e], zmul(ui, wj)), zmul(yi, cu));
+    A[e] = v;
+    if (j == k + 1) col[i] = v;
   }
 }
 
@@ -207,8 +217,7 @@ static int gridN(long long len) {
   return (int)(nb < 1 ? 1 : nb);
 }
 
-// y holds the n row sums and, after 2 n entries, the partial sums of w u (one per workgroup of
-// k_hh_wreduce).  The reflectors reach Z in blocks of WYB: with V (n x nb, row stride WYB; rows
+// y holds the n row sums.  The reflectors reach Z in blocks of WYB: with V (n x nb, row stride WYB; rows
 // <= k0 are zero) and T from k_wy_t, Z <- Z - ((Z V) T) V^H.  The products over the rows of V are
 // split into NBK row chunks (batches summed through the workspace) so that they fill the chip.
 struct WyBufs {
@@ -264,21 +273,19 @@ static int wy_flush(zd* Z, int n, int k0, int nb, const WyBufs& wy, hipStream_t 
   return gemm(PREC_F64, z, st) ? -4 : 0;
 }
 
-static int hessenberg(zd* A, zd* Z, int n, zd* u, double* gam, zd* part, zd* w, zd* y, const WyBufs& wy,
+static int hessenberg(zd* A, zd* Z, int n, zd* u, double* gam, zd* part, zd* col, zd* y, const WyBufs& wy,
                       hipStream_t st) {
   const int nrc = 16;
   int k0 = 0;
+  hipLaunchKernelGGL(k_hh_col0, dim3((n + 255) / 256), dim3(256), 0, st, (const zd*)A, n, col);
   for (int k = 0; k + 2 < n; ++k) {
     const int rows = n - k - 1;
     const int rchunk = (rows + nrc - 1) / nrc;
     const int ncb = (rows + 63) / 64;
-    const int nwb = (rows + 255) / 256;
-    hipLaunchKernelGGL(k_hh_vec, dim3(1), dim3(256), 0, st, A, n, k, u, gam, wy.vb, k - k0, wy.gb);
-    hipLaunchKernelGGL(k_hh_pass1, dim3(ncb * nrc + (n + 3) / 4), dim3(256), 0, st, A, n, k, u, rchunk, ncb, nrc,
-                       part, y);
-    hipLaunchKernelGGL(k_hh_wreduce, dim3(nwb), dim3(256), 0, st, part, nrc, n, k, gam, u, w, y + 2 * n);
-    hipLaunchKernelGGL(k_hh_update, dim3(gridN((long long)n * rows)), dim3(256), 0, st, A, n, k, u, w, y, y + 2 * n,
-                       nwb, gam);
+    hipLaunchKernelGGL(k_hh_pass1, dim3(ncb * nrc + (n + 3) / 4), dim3(256), 0, st, A, n, k, (const zd*)col, rchunk,
+                       ncb, nrc, part, y, u, gam, wy.vb, k - k0, wy.gb);
+    hipLaunchKernelGGL(k_hh_update, dim3(ncb, (n + HU_R - 1) / HU_R), dim3(256), 0, st, A, n, k, (const zd*)u,
+                       (const double*)gam, (const zd*)y, (const zd*)part, nrc, col);
     if (k - k0 + 1 == WYB || k + 3 >= n) {
       if (wy_flush(Z, n, k0, k - k0 + 1, wy, st)) return -4;
       k0 = k + 1;
@@ -732,7 +739,7 @@ __global__ __launch_bounds__(64) void k_aed(zd* A, int n, int kw, int ihi, zd* U
     // independent accumulators to shorten their dependency chains.
     for (int k = 0; k + 2 < nu; ++k) {
       __syncthreads();
-      // the part below x0 on its own (see k_hh_vec)
+      // the part below x0 on its own (see hh_scalars)
       double tail = (t > k + 1 && t < nu) ? zabs2(Hs[t * LDM + k]) : 0.0;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) tail += __shfl_xor(tail, o, 64);
