@@ -30,7 +30,11 @@ int lindx_schur(void* A, void* Z, int n, int mode, void* stream);
    m x m matrix A (m <= 64), one workgroup */
 int lindx_small_eig(const void* A, int m, void* w, void* Y, void* stream);
 
-/* eigenvectors Y of upper-triangular T (unit diagonal) and the inverse of a unit upper-triangular Y */
+/* eigenvectors Y of upper-triangular T (unit diagonal) and the inverse of a unit upper-triangular Y
+   (n x n; only the upper triangle of the input is read, the output's lower triangle is zero).
+   Each call allocates an n x n workspace for the transposed input and frees it before returning
+   (synchronous).  n = 0 does nothing; n < 0 or n > 10240 (the column's right-hand sides must fit
+   in 160 KB of LDS) returns -1, -5 if the workspace cannot be allocated. */
 int lindx_trevec(const void* T, void* Y, int n, void* stream);
 int lindx_triinv(const void* Y, void* Yinv, int n, void* stream);
 

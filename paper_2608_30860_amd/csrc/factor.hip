@@ -1280,6 +1280,7 @@ __global__ __launch_bounds__(256) void k_transpose_upper(const zd* X, zd* Y, int
 }
 
 static int backsolve(const zd* M, zd* Mt, zd* X, int n, int mode, hipStream_t st) {
+  if (n < 1) return n == 0 ? 0 : -1;
   const size_t lds = sizeof(zd) * (size_t)n;
   if (lds > 160 * 1024) return -1;
   if (lds > 64 * 1024 &&

@@ -54,8 +54,10 @@ extern "C" int lindx_small_eig(const void* A, int m, void* w, void* Y, void* str
 
 static int with_square_ws(int n, int (*f)(const zd*, zd*, zd*, int, hipStream_t), const void* in, void* out,
                           void* stream) {
+  if (n == 0) return 0;
+  if (n < 0 || n > 10240) return -1;
   zd* ws = nullptr;
-  if (hipMalloc(&ws, sizeof(zd) * (size_t)(n > 0 ? n : 1) * (size_t)(n > 0 ? n : 1)) != hipSuccess) return -5;
+  if (hipMalloc(&ws, sizeof(zd) * (size_t)n * (size_t)n) != hipSuccess) return -5;
   int rc = f((const zd*)in, ws, (zd*)out, n, (hipStream_t)stream);
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == 0) rc = -4;
   hipFree(ws);

@@ -75,3 +75,14 @@ def test_create_rejects_bad_arguments_without_touching_a_device(lib):
     assert lib.lind_create(None, ctypes.c_void_p(16), None, 4, 0, None) == -1
     lib.lind_last_error.restype = ctypes.c_char_p
     assert b"invalid" in lib.lind_last_error(None) or b"NULL" in lib.lind_last_error(None)
+
+
+def test_triangular_solves_check_sizes_without_touching_a_device(lib):
+    """n = 0 is an empty solve; a negative n, or one whose column does not fit in LDS, is refused
+    before any workspace is allocated or kernel launched."""
+    for name in ("lindx_trevec", "lindx_triinv"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+        assert f(None, None, 0, None) == 0
+        assert f(None, None, -3, None) == -1
+        assert f(None, None, 10241, None) == -1
