@@ -34,6 +34,10 @@ extern "C" {
 
 typedef struct lind_ctx lind_ctx;
 
+/* largest n accepted by lind_create (the triangular eigenvector solves hold one column's
+   right-hand sides, n complex128 values, in a workgroup's 160 KB of LDS) */
+#define LIND_NMAX 10240
+
 enum {
   LIND_OK = 0,
   LIND_EINVAL = -1,     /* invalid argument (NULL pointer, n < 1, d < 0, non-finite input, ...) */
@@ -95,8 +99,8 @@ void lind_default_opts(lind_opts* opts);
    Householder Hessenberg reduction, multishift QR to the Schur form G = Z T Z^+, and for the
    eigenbasis route the eigenvectors U = Z Y with V = U^{-+} = Z Y^{-+} (Algorithm "No-jump
    resolvent via eigendecomposition").  opts may be NULL (defaults).
-   Errors: EINVAL (NULL pointers, n < 1, d < 0, d > 64), ESINGULAR (min |Re s_i| too small:
-   Theorem 1, first case), ENOMEM, EDEVICE. */
+   Errors: EINVAL (NULL pointers, n < 1, n > LIND_NMAX, d < 0, d > 64), ESINGULAR (min |Re s_i|
+   too small: Theorem 1, first case), ENOMEM, EDEVICE. */
 int lind_create(lind_ctx** out, const void* H, const void* L_stacked, int n, int d, const lind_opts* opts);
 
 /* Release every device buffer of the context.  NULL is a no-op. */

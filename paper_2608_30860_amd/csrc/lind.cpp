@@ -237,6 +237,10 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
     g_create_err = "invalid arguments (need H, n >= 1, 0 <= d <= 64, L when d > 0)";
     return LIND_EINVAL;
   }
+  if (n > LIND_NMAX) {
+    g_create_err = "n > 10240: the eigenvector solves keep one column's right-hand sides in 160 KB of LDS";
+    return LIND_EINVAL;
+  }
   lind_opts o;
   lind_default_opts(&o);
   if (opts) o = *opts;

@@ -75,6 +75,8 @@ def test_create_rejects_bad_arguments_without_touching_a_device(lib):
     assert lib.lind_create(None, ctypes.c_void_p(16), None, 4, 0, None) == -1
     lib.lind_last_error.restype = ctypes.c_char_p
     assert b"invalid" in lib.lind_last_error(None) or b"NULL" in lib.lind_last_error(None)
+    assert lib.lind_create(ctypes.byref(h), ctypes.c_void_p(16), None, 10241, 0, None) == -1  # n > LIND_NMAX
+    assert b"10240" in lib.lind_last_error(None)
 
 
 def test_triangular_solves_check_sizes_without_touching_a_device(lib):
