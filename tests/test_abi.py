@@ -88,3 +88,16 @@ def test_triangular_solves_check_sizes_without_touching_a_device(lib):
         assert f(None, None, 0, None) == 0
         assert f(None, None, -3, None) == -1
         assert f(None, None, 10241, None) == -1
+
+
+def test_binding_rejects_host_tensors_and_wrong_dtypes():
+    """The Python binding hands the library device pointers only: host tensors and other dtypes
+    are refused before lind_create is called (so no device is touched)."""
+    torch = pytest.importorskip("torch")
+    from paper_2608_30860_amd import Lindblad
+    H = torch.zeros((4, 4), dtype=torch.complex128)
+    Ls = torch.zeros((1, 4, 4), dtype=torch.complex128)
+    with pytest.raises(TypeError, match="CUDA"):
+        Lindblad(H, Ls)
+    with pytest.raises(TypeError, match="complex128"):
+        Lindblad(H.to(torch.complex64), Ls)
