@@ -170,27 +170,43 @@ def main():
 
     xi = torch.eye(n, dtype=torch.complex128, device=dev) / n
 
+    def exact_trace_norm(m_, rho_):
+        # ||L rho||_1 = sum |eig| of the Hermitian residual (torch's eigvalsh on the device: a
+        # diagnostic beside the library's column-norm bound, not part of the solve)
+        r_ = m_.apply(rho_)
+        return float(torch.linalg.eigvalsh(0.5 * (r_ + r_.conj().T)).abs().sum())
+
+    def trace_dist(a, b):
+        diff = a - b
+        return float(0.5 * torch.linalg.eigvalsh(0.5 * (diff + diff.conj().T)).abs().sum())
+
     # ---------------------------------------------------------------- timed steps (mixed) ----
     for w in range(args.warmup):
         r = model.steady_state(args.tol)
         log(f"[bench] warmup {w}: {r.info}")
+    # event timing of the named kernels on the context's stream; the library reads the events
+    # back at the end of every solve, so only one solve's events are ever in flight
     lib.lindx_profile(model.h, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    infos, step_s = [], []
     for s in range(args.steps):
+        ts = time.perf_counter()
         r = model.steady_state(args.tol)
+        step_s.append(time.perf_counter() - ts)
         infos.append(r.info)
     torch.cuda.synchronize()
     t_timed = time.perf_counter() - t0
     for s, inf in enumerate(infos):
-        log(f"[bench] step {s}: {inf}")
+        log(f"[bench] step {s}: {1000 * step_s[s]:.1f} ms {inf}")
     n_phi = sum(i["n_phi"] for i in infos)
     prof = {k: prof_read(model, k) for k in range(4)}
     lib.lindx_profile(model.h, 0)
     rho_mixed = r.rho
     value = n_phi / t_timed
     ms_per_step = 1000.0 * t_timed / args.steps
+    step_ms = sorted(1000.0 * x for x in step_s)
+    step_stats = {"median": step_ms[len(step_ms) // 2], "min": step_ms[0], "max": step_ms[-1]}
 
     # dominant kernel: the stacked jump product [Lt_1; ..; Lt_d] Xh (M = d n, N = K = n)
     cnt, ms = prof[0]
@@ -217,60 +233,93 @@ def main():
                 roof["traffic"] = tj["bytes_per_launch"]
         except Exception:
             pass
+    # the other timed kinds, each with the work it actually executes: the jump reduction of the
+    # steady-state iteration forms a Hermitian result from the tiles on and above the diagonal
+    # (T (T + 1) / 2 of T^2 tiles, T = ceil(n / 128)), the basis change is two n^3 products
+    tiles = (n + 127) // 128
+    herm_frac = tiles * (tiles + 1) / 2 / tiles ** 2
     other = {}
-    for k, name in [(1, "jump_reduce"), (2, "basis_in"), (3, "phi")]:
-        c, t = prof[k]
-        if c:
-            other[name] = {"launches": c, "avg_ms": t / c}
-            if name == "jump_reduce":
-                other[name]["achieved_tflops"] = flops / (t / c / 1000) / 1e12
+    for k, name, fl in [(1, "jump_reduce", 8.0 * d * n ** 3 * herm_frac),
+                        (2, "basis_in", 8.0 * n ** 3 * (1 + herm_frac)), (3, "phi", None)]:
+        c_, t_ = prof[k]
+        if c_:
+            other[name] = {"launches": c_, "avg_ms": t_ / c_}
+            if fl is not None:
+                tf = fl / (t_ / c_ / 1000) / 1e12
+                other[name].update({"executed_flops_per_launch": fl, "achieved_tflops": tf, "frac": tf / peak})
+    if "phi" in other:
+        # whole map: 8 (2 + 2d) n^3 algorithmic flops with the fused operands Lt_j = L_j U
+        tf = 8.0 * (2 + 2 * d) * n ** 3 / (other["phi"]["avg_ms"] / 1000) / 1e12
+        other["phi"].update({"algorithmic_tflops": tf, "frac": tf / peak})
 
-    # ---------------------------------------------------------------- comparisons ------------
+    def solve_stats(m_, reps):
+        m_.steady_state(args.tol)  # warm
+        torch.cuda.synchronize()
+        ts_, last = [], None
+        for _ in range(reps):
+            t0_ = time.perf_counter()
+            last = m_.steady_state(args.tol)
+            torch.cuda.synchronize()
+            ts_.append(time.perf_counter() - t0_)
+        ts_.sort()
+        return ts_[len(ts_) // 2], last
+
+    # ------------------------------------------- time-to-tolerance over seeds 0, 1, 2 ---------
+    # per seed: one context per precision, the median of 3 solves; reported: each seed and the
+    # median over the seeds (factorisation and iteration phases separate)
+    seeds = []
+    if not args.no_compare:
+        for sd in [0, 1, 2]:
+            if sd == args.seed:
+                Hs, Ls_ = Ht, Lt
+            else:
+                Hn, Lsn = li.random_dense(n, d, sd)
+                Hs, Ls_ = torch.from_numpy(Hn).to(dev), torch.from_numpy(np.stack(Lsn)).to(dev)
+            row = {"seed": sd}
+            states = {}
+            for p in [args.prec, "fp64"]:
+                if p == args.prec and sd == args.seed:
+                    mp = model
+                else:
+                    mp = Lindblad(Hs, Ls_, prec=p)
+                t_it, rp = solve_stats(mp, 3)
+                row[p] = {"iteration_s": t_it, "t_factor_s": rp.info["t_factor_s"],
+                          "total_s": t_it + rp.info["t_factor_s"], "n_phi": rp.info["n_phi"],
+                          "n_refine": rp.info["n_refine"], "resid_trace_bound": rp.info["resid_trace"],
+                          "resid_trace_exact": exact_trace_norm(mp, rp.rho), "resid_max": rp.info["resid_max"]}
+                states[p] = rp.rho
+                if mp is not model:
+                    mp.close()
+            row["trace_distance_mixed_fp64"] = trace_dist(states[args.prec], states["fp64"])
+            row["speedup_iteration"] = row["fp64"]["iteration_s"] / row[args.prec]["iteration_s"]
+            row["speedup_total"] = row["fp64"]["total_s"] / row[args.prec]["total_s"]
+            seeds.append(row)
+            log(f"[bench] seed {sd}: {row}")
+
     compare = {}
     if not args.no_compare:
-        for p in ["fp64", "fp32"]:
-            if p == args.prec:
-                continue
-            log(f"[bench] comparison: factorising for {p}")
-            t0 = time.perf_counter()
-            mp = Lindblad(Ht, Lt, prec=p)
-            tc = time.perf_counter() - t0
-            mp.steady_state(args.tol)  # warm
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rp = mp.steady_state(args.tol)
-            torch.cuda.synchronize()
-            ts = time.perf_counter() - t0
-            # pure Phi loop rate
+        if args.prec != "fp32":
+            mp = Lindblad(Ht, Lt, prec="fp32")
+            t_it, rp = solve_stats(mp, 3)
+            compare["fp32"] = {"time_to_tol_iteration_s": t_it, "t_factor_s": rp.info["t_factor_s"],
+                               "n_phi": rp.info["n_phi"], "resid_trace_bound": rp.info["resid_trace"],
+                               "trace_distance_to_mixed": trace_dist(rp.rho, rho_mixed)}
             x = xi.clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(args.phi_loop):
                 x = mp.phi(x)
             torch.cuda.synchronize()
-            rate = args.phi_loop / (time.perf_counter() - t0)
-            diff = (rp.rho - rho_mixed)
-            ev = torch.linalg.eigvalsh(0.5 * (diff + diff.conj().T))
-            compare[p] = {"time_to_tol_iteration_s": ts, "create_s": tc, "t_factor_s": rp.info["t_factor_s"],
-                          "n_phi": rp.info["n_phi"], "n_refine": rp.info["n_refine"],
-                          "resid_trace_bound": rp.info["resid_trace"], "phi_loop_rate": rate,
-                          "trace_distance_to_mixed": float(0.5 * ev.abs().sum())}
-            log(f"[bench] {p}: {compare[p]}")
+            compare["fp32"]["phi_loop_rate"] = args.phi_loop / (time.perf_counter() - t0)
+            log(f"[bench] fp32: {compare['fp32']}")
             mp.close()
         # the same steady state by preconditioned GMRES (method option), same precision
         log("[bench] comparison: steady state by preconditioned GMRES")
         mg = Lindblad(Ht, Lt, prec=args.prec, method="gmres")
-        mg.steady_state(args.tol)  # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rg = mg.steady_state(args.tol)
-        torch.cuda.synchronize()
-        tg = time.perf_counter() - t0
-        diff = (rg.rho - rho_mixed)
-        ev = torch.linalg.eigvalsh(0.5 * (diff + diff.conj().T))
+        tg, rg = solve_stats(mg, 3)
         compare["gmres_method"] = {"time_to_tol_iteration_s": tg, "gmres_steps": rg.info["n_inner"],
                                    "resid_trace_bound": rg.info["resid_trace"],
-                                   "trace_distance_to_mixed": float(0.5 * ev.abs().sum())}
+                                   "trace_distance_to_mixed": trace_dist(rg.rho, rho_mixed)}
         log(f"[bench] gmres method: {compare['gmres_method']}")
         mg.close()
     # pure Phi loop of the benchmarked precision
@@ -283,24 +332,27 @@ def main():
     loop_rate = args.phi_loop / (time.perf_counter() - t0)
 
     it_mixed = ms_per_step / 1000.0
-    t_to_tol = {"mixed": {"prec": args.prec, "iteration_s": it_mixed, "t_factor_s": infos[-1]["t_factor_s"],
-                          "total_s": it_mixed + infos[-1]["t_factor_s"], "n_phi": infos[-1]["n_phi"],
-                          "n_refine": infos[-1]["n_refine"], "resid_trace_bound": infos[-1]["resid_trace"],
-                          "resid_max": infos[-1]["resid_max"], "phi_loop_rate": loop_rate}}
-    if "fp64" in compare:
-        f = compare["fp64"]
-        t_to_tol["fp64"] = {"iteration_s": f["time_to_tol_iteration_s"], "t_factor_s": f["t_factor_s"],
-                            "total_s": f["time_to_tol_iteration_s"] + f["t_factor_s"], "n_phi": f["n_phi"],
-                            "resid_trace_bound": f["resid_trace_bound"], "phi_loop_rate": f["phi_loop_rate"],
-                            "trace_distance_to_mixed": f["trace_distance_to_mixed"]}
-        t_to_tol["speedup_iteration_fp64_over_mixed"] = f["time_to_tol_iteration_s"] / it_mixed
-        t_to_tol["speedup_total_fp64_over_mixed"] = t_to_tol["fp64"]["total_s"] / t_to_tol["mixed"]["total_s"]
-    if "gmres_method" in compare:
-        t_to_tol["gmres_method"] = compare["gmres_method"]
-    if "fp32" in compare:
-        t_to_tol["fp32"] = {k: compare["fp32"][k] for k in ["time_to_tol_iteration_s", "t_factor_s", "n_phi",
-                                                             "resid_trace_bound", "phi_loop_rate",
-                                                             "trace_distance_to_mixed"]}
+    t_to_tol = {"mixed_timed_steps": {"prec": args.prec, "iteration_s": it_mixed, "median_step_s": step_stats["median"] / 1000,
+                                      "t_factor_s": infos[-1]["t_factor_s"], "n_phi": infos[-1]["n_phi"],
+                                      "n_refine": infos[-1]["n_refine"], "resid_trace_bound": infos[-1]["resid_trace"],
+                                      "resid_trace_exact": exact_trace_norm(model, rho_mixed),
+                                      "resid_max": infos[-1]["resid_max"], "phi_loop_rate": loop_rate}}
+    if seeds:
+        def med(vals):
+            vals = sorted(vals)
+            return vals[len(vals) // 2]
+        t_to_tol["seeds"] = seeds
+        t_to_tol["median_over_seeds"] = {
+            "mixed_iteration_s": med([r_[args.prec]["iteration_s"] for r_ in seeds]),
+            "fp64_iteration_s": med([r_["fp64"]["iteration_s"] for r_ in seeds]),
+            "mixed_total_s": med([r_[args.prec]["total_s"] for r_ in seeds]),
+            "fp64_total_s": med([r_["fp64"]["total_s"] for r_ in seeds]),
+            "t_factor_s": med([r_["fp64"]["t_factor_s"] for r_ in seeds]),
+            "speedup_iteration_fp64_over_mixed": med([r_["speedup_iteration"] for r_ in seeds]),
+            "speedup_total_fp64_over_mixed": med([r_["speedup_total"] for r_ in seeds])}
+    for k_ in ["gmres_method", "fp32"]:
+        if k_ in compare:
+            t_to_tol[k_] = compare[k_]
 
     # resolvent benchmark of the paper (after the timed region): (lambda - L) X = I/n at
     # lambda = lambda_max * 10^{0,-1,-2}, lambda_max the spectral radius of L by power iteration
@@ -373,6 +425,7 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "Phi-apps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+           "step_ms": step_stats,
            "config": {"workload": f"random dense Lindbladian n={n} d={d} seed={args.seed}: steady state to "
                                   f"||L rho||_1 bound <= {args.tol:g}", "n": n, "d": d, "tol": args.tol,
                       "step": "one steady-state solve (Arnoldi on Phi + FP64 refinement); factorisation once, "

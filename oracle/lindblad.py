@@ -311,9 +311,3 @@ def lyap_integral(G, Y, t_max=60.0, steps=6000):
         acc = acc + w * (P @ Y @ dag(P))
         P = E @ P
     return -(h / 3.0) * acc
-
-
-def residual_norms(H, Ls, rho):
-    """(trace norm, max norm) of L(rho)."""
-    r = lindblad_apply(H, Ls, rho)
-    return trace_norm(r), max_norm(r)

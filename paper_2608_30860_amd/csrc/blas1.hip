@@ -190,9 +190,15 @@ int axpby(zd a, const zd* x, zd b, zd* y, long long len, hipStream_t st) {
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(len)), dim3(RB), 0, st, a, x, b, y, len);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
+__global__ void k_copy(const zd* __restrict__ x, zd* __restrict__ y, long long len) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) y[i] = x[i];
+}
+// device-to-device copies of the solvers: a plain streaming kernel on the context's stream
 int copy(const zd* x, zd* y, long long len, hipStream_t st) {
   if (len <= 0) return 0;
-  return hipMemcpyAsync(y, x, (size_t)len * sizeof(zd), hipMemcpyDeviceToDevice, st) == hipSuccess ? 0 : -4;
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(len)), dim3(RB), 0, st, x, y, len);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 __global__ void k_zero(unsigned int* p, long long nwords) {
   long long stride = (long long)gridDim.x * blockDim.x;

@@ -137,6 +137,8 @@ struct GmresResult {
   double resid0 = 0.0;
   bool converged = false;
   bool stagnated = false;  // restarts stopped reducing the true residual
+  bool est_hit = false;    // the last cycle's recurrence reached the target (the true residual may
+                           // still miss it: a reduced-precision operator is linear only up to rounding)
 };
 int gmres(Ctx& c, const std::function<int(const zd*, zd*)>& A, const std::function<int(const zd*, zd*)>* P,
           const zd* b, zd* x, bool x_zero, int m, int max_cycles, double rtol, double atol, GmresResult& res,

@@ -342,6 +342,7 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
     res.cycles = cyc + 1;
     res.resid = est;
     prev_est_hit = est <= target;
+    res.est_hit = prev_est_hit;
 
     // ---- recycle update: harmonic Ritz vectors over span(W^) ----
     // Without a preconditioner W^ and V^ live in one space and F = V^^H W^ is formed exactly.  In

@@ -434,7 +434,8 @@ extern "C" int lind_phi(lind_ctx* ctx, const void* xi, void* out) {
   if (!ctx || !xi || !out || xi == out) return LIND_EINVAL;
   Ctx& c = ctx->c;
   TRY(op_phi(c, (const zd*)xi, (zd*)out, c.prec));
-  return c.sync();
+  TRY(c.sync());
+  return c.prof_collect();
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -511,7 +512,9 @@ int lindx::finish_state(lind_ctx* X, zd* rho, double* colsum, double* mx, double
 
 extern "C" int lind_steady_state(lind_ctx* ctx, double tol, const void* rho0, void* rho_out, lind_info* info) {
   if (!ctx || !rho_out || !(tol > 0) || !std::isfinite(tol)) return LIND_EINVAL;
-  return steady_state_impl(ctx, tol, (const zd*)rho0, (zd*)rho_out, info);
+  const int rc = steady_state_impl(ctx, tol, (const zd*)rho0, (zd*)rho_out, info);
+  const int prc = ctx->c.prof_collect();
+  return rc ? rc : prc;
 }
 
 int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_out, lind_info* info) {
@@ -694,7 +697,10 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
           return grc;
         }
         inf.n_inner += gr.iters;
-        if (!gr.converged && !gr.stagnated && !long_mode) {
+        // a long cycle only when the recurrence itself missed the target (a strongly non-normal
+        // map); a recurrence that met it with the true residual short of it has reached the
+        // rounding floor of the reduced-precision map, which more steps do not lower
+        if (!gr.converged && !gr.stagnated && !gr.est_hit && !long_mode) {
           long_mode = true;
           m_ref = long_cycle_len(c, 256, false);
         }

@@ -20,7 +20,10 @@ Ctx::~Ctx() {
 }
 
 int Ctx::prof_begin(int kind) {
-  if (!prof || pending.size() >= 200000) return -1;
+  // the pending slots are read back at the end of every entry point that synchronises; the cap
+  // bounds the events in flight (thousands of outstanding timing events slow the runtime's own
+  // synchronisation) and launches past it go untimed
+  if (!prof || pending.size() >= 1024) return -1;
   ProfSlot sl;
   sl.kind = kind;
   for (hipEvent_t* e : {&sl.a, &sl.b}) {

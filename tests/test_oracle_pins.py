@@ -103,13 +103,36 @@ def test_thermal_state_is_geometric():
 
 
 def test_thermal_low_spectrum():
-    """Damped oscillator spectrum lambda = -i omega l - kappa (m + |l|/2): at small nbar and a
-    large enough truncation the lowest modes agree with it (to the truncation effect)."""
-    H, Ls = li.thermal_oscillator(14, omega=1.0, kappa=1.0, nbar=0.1)
-    ev = ol.low_spectrum_dense(H, Ls, 6)
-    expected = np.array([-0.5 - 1j, -0.5 + 1j, -1.0, -1.5 - 1j, -1.5 + 1j, -1 - 2j])
+    """Damped oscillator spectrum lambda = -i omega l - kappa (m + |l|/2), m >= 0, independent of
+    nbar.  With omega = kappa = 1 the eight smallest nonzero moduli are -1, -1/2 +- i, -3/2 +- i,
+    -2, -1 +- 2i; at n = 20 and nbar = 0.1 the truncation moves them by far less than 1e-10.
+    Both multisets must match (nothing missing, nothing extra)."""
+    H, Ls = li.thermal_oscillator(20, omega=1.0, kappa=1.0, nbar=0.1)
+    ev = ol.low_spectrum_dense(H, Ls, 8)
+    expected = np.array([-1.0, -0.5 - 1j, -0.5 + 1j, -1.5 - 1j, -1.5 + 1j, -2.0, -1 - 2j, -1 + 2j])
     for e in expected:
-        assert np.min(np.abs(ev - e)) < 1e-6 or abs(e) > np.max(np.abs(ev))
+        assert np.min(np.abs(ev - e)) < 1e-10, e
+    for e in ev:
+        assert np.min(np.abs(expected - e)) < 1e-10, e
+    # sorted by modulus, ties (the conjugate pairs) by Im ascending
+    assert np.allclose(ev, expected, atol=1e-10)
+
+
+def test_thermal_low_eigenpairs():
+    """low_eigenpairs_dense: the same eigenvalues as low_spectrum_dense; every eigenvector is a unit
+    matrix with L(v) = lambda v checked through the term-by-term L (not the Kronecker matrix that
+    produced it); the mode -i omega l - kappa (m + |l|/2) is supported on the entries |k><k'| with
+    k - k' = l (the phase-covariant oscillator conserves k - k'; -i[omega N, .] multiplies them by
+    -i omega (k - k'))."""
+    H, Ls = li.thermal_oscillator(20, omega=1.0, kappa=1.0, nbar=0.1)
+    ev, vecs = ol.low_eigenpairs_dense(H, Ls, 8)
+    assert np.allclose(ev, ol.low_spectrum_dense(H, Ls, 8), atol=1e-12)
+    for lam, v in zip(ev, vecs):
+        assert abs(np.linalg.norm(v) - 1) < 1e-12
+        assert ol.max_norm(ol.lindblad_apply(H, Ls, v) - lam * v) < 1e-10
+        ell = int(round(-lam.imag))  # omega = 1
+        k, kp = np.nonzero(np.abs(v) > 1e-8)
+        assert np.all(k - kp == ell), (lam, set(k - kp))
 
 
 def test_three_level_cyclic_golden():
