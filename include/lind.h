@@ -176,6 +176,27 @@ int lind_resolve(lind_ctx* ctx, double lambda_re, double lambda_im, const void* 
    was hit; rho_out holds the last completed state). */
 int lind_ie(lind_ctx* ctx, double dt, int steps, const void* rho0, void* rho_out, double tol, lind_info* info);
 
+/* Size of the fixed device array behind lind_apply_noalloc (64 MiB, one copy per GPU the library
+   runs on, held until the process ends). */
+#define LIND_NOALLOC_SCRATCH_BYTES (64LL << 20)
+
+/* For callers that cannot allocate device memory while they run (code under stream capture,
+   tight serving loops, harnesses that forbid hipMalloc): out = L(rho) exactly as lind_apply
+   computes it (same kernels, FP64), but every intermediate -- the stacked products L_j rho and the
+   split-K partials of the sum over j -- lives in a fixed device array of
+   LIND_NOALLOC_SCRATCH_BYTES instead of the context's workspaces.  The call makes no hipMalloc,
+   hipFree or other allocating call; the context (created beforehand by lind_create) and the
+   device buffers rho, out (n x n complex128, may not alias) are the caller's.
+   Limit: lind_apply_noalloc_bytes(n, d) <= LIND_NOALLOC_SCRATCH_BYTES (about d n^2 16 bytes plus
+   the partials; e.g. n = 512 with d <= 8, n = 1024 with d <= 3), else LIND_EINVAL with a message.  The context's device
+   must be the current device.  The array is shared by every call on that GPU and keeps the last
+   call's contents (each call overwrites what it reads); calls that overlap on one GPU (other
+   threads, other streams) race on it.  Synchronises the context's stream before returning. */
+int lind_apply_noalloc(lind_ctx* ctx, const void* rho, void* out);
+/* Scratch bytes lind_apply_noalloc needs for an n x n system with d jump operators (-1 if n < 1
+   or d < 0). */
+long long lind_apply_noalloc_bytes(int n, int d);
+
 /* Factorisation data (device pointers owned by the context, valid until lind_destroy):
    which: 0 = G, 1 = T (Schur factor), 2 = Z (Schur vectors), 3 = U (unit-column eigenvectors),
    4 = V = U^{-+}, 5 = s (n eigenvalues of G).  Returns NULL if not available. */

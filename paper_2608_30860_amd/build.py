@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblindx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["zgemm.hip", "zgemm_p4.hip", "blas1.hip", "small_eig.hip", "factor.hip", "trisylv.hip",
-           "ops.cpp", "gcrodr.cpp", "lind.cpp", "eigs.cpp", "resolve.cpp", "testing.cpp"]
+           "ops.cpp", "gcrodr.cpp", "lind.cpp", "eigs.cpp", "resolve.cpp", "testing.cpp", "noalloc.cpp"]
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

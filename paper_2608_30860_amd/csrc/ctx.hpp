@@ -32,6 +32,7 @@ struct Recycle {
 
 struct Ctx {
   int n = 0, d = 0;
+  int dev = 0;  // HIP device the context was created on
   long long n2 = 0;
   lind_opts opts;
   hipStream_t st = nullptr;
@@ -145,6 +146,16 @@ int gmres(Ctx& c, const std::function<int(const zd*, zd*)>& A, const std::functi
           double t_deadline);
 
 double now_s();
+
+// device address of the fixed scratch array of lind_apply_noalloc on device dev (resolved once
+// per device; lind_create calls it with the device current)
+int noalloc_setup(int dev);
+
+#define TRY_RC(x)                                        \
+  do {                                                   \
+    int rc__ = (x);                                      \
+    if (rc__) return rc__ < 0 ? rc__ : LIND_EDEVICE;     \
+  } while (0)
 
 }  // namespace lindx
 

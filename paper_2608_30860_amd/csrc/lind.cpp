@@ -256,8 +256,12 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
     g_create_err = "no gfx950 (MI355X) device available";
     return LIND_EDEVICE;
   }
+  // the fixed scratch of lind_apply_noalloc is resolved here, once per device (failure only
+  // disables that entry point)
+  noalloc_setup(dev);
   lind_ctx* X = new lind_ctx();
   Ctx& c = X->c;
+  c.dev = dev;
   c.n = n;
   c.d = d;
   c.n2 = (long long)n * n;

@@ -23,7 +23,7 @@ METHOD = {"phi_arnoldi": 0, "gmres": 1}
 ROUTE = {"auto": 0, "eig": 1, "schur": 2}
 SYMBOLS = ["lind_default_opts", "lind_create", "lind_destroy", "lind_apply", "lind_apply_adjoint", "lind_sinv",
            "lind_phi", "lind_steady_state", "lind_eigs", "lind_steady_grad", "lind_resolve", "lind_ie",
-           "lind_factor_ptr", "lind_last_error"]
+           "lind_factor_ptr", "lind_last_error", "lind_apply_noalloc", "lind_apply_noalloc_bytes"]
 
 
 class LindOpts(ctypes.Structure):
@@ -71,6 +71,10 @@ def load_library(path: str = LIB_PATH):
         f = getattr(lib, name)
         f.argtypes = [vp, vp, vp]
         f.restype = ci
+    lib.lind_apply_noalloc.argtypes = [vp, vp, vp]
+    lib.lind_apply_noalloc.restype = ci
+    lib.lind_apply_noalloc_bytes.argtypes = [ci, ci]
+    lib.lind_apply_noalloc_bytes.restype = ctypes.c_longlong
     lib.lind_sinv.argtypes = [vp, vp, vp, cd, cd]
     lib.lind_sinv.restype = ci
     lib.lind_steady_state.argtypes = [vp, cd, vp, vp, ctypes.POINTER(LindInfo)]
@@ -174,6 +178,16 @@ class Lindblad:
         _check_mat(rho, self.n, "rho")
         out = self._new()
         rc = self.lib.lind_apply(self.h, _ptr(rho), _ptr(out))
+        if rc:
+            self._err(rc)
+        return out
+
+    def apply_noalloc(self, rho, out):
+        """out = L(rho) through lind_apply_noalloc (intermediates in the library's fixed device
+        array; the output buffer is the caller's)."""
+        _check_mat(rho, self.n, "rho")
+        _check_mat(out, self.n, "out")
+        rc = self.lib.lind_apply_noalloc(self.h, _ptr(rho), _ptr(out))
         if rc:
             self._err(rc)
         return out
