@@ -68,7 +68,8 @@ typedef struct {
   int max_restarts;     /* Arnoldi / GMRES restarts                       default 200         */
   int refine_max;       /* FP64 refinement steps                          default 8           */
   double eta;           /* deflation constant (eq. steady_state_linear_problem), default 1.0 */
-  double time_limit_s;  /* wall-clock cap per solver call, <= 0: none     default 0           */
+  double time_limit_s;  /* wall-clock cap per solver call, <= 0: none     default 0; checked
+                           between Krylov steps (lind_eigs: between thick restarts)             */
   void* stream;         /* hipStream_t, NULL = default stream                                 */
   int method;           /* LIND_METHOD_* for lind_steady_state (and the state of steady_grad), default PHI_ARNOLDI */
   const double* gauge;  /* HOST, NULL or 2d doubles (re, im) of c_j: the split uses L_j + c_j I and

@@ -64,6 +64,14 @@ int lindx_profile_read(lind_ctx* ctx, int kind, long long* count, double* total_
 int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch, int opA, int opB, int out_mode,
                   const void* dr, const void* dc, void* C, void* stream);
 
+/* One classical Gram-Schmidt step with re-orthogonalisation, as in the Arnoldi and GMRES drivers:
+   h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, nrm = ||w||_2 (FP64).  V: k basis vectors of len
+   complex128 entries at stride ld (>= len); h: 2k complex128 (h1, then h2); nrm: one double (all
+   device).  reps > 1 repeats the step on the updated w (timing).  Synchronous; allocates a
+   partial-sum workspace.  Returns 0, -1 for invalid arguments, -4, -5. */
+int lindx_cgs2(const void* V, long long ld, int k, void* w, long long len, void* h, void* nrm, int reps,
+               void* stream);
+
 /* dst = src (nbytes, a multiple of 16) with a plain vector copy kernel; used to calibrate the
    HBM byte counters of the profiler.  Asynchronous on stream. */
 int lindx_copy(void* dst, const void* src, long long nbytes, void* stream);

@@ -11,7 +11,7 @@ Three independent routes:
   L~_eta drho = -(dL) rho_inf with Tr drho = 0, dJ = Re Tr(O drho).  It never uses the
   adjoint formula, so it checks it (Remark "Differentiating the steady state").
 * ``grad_adjoint``        -- the adjoint route of that remark: solve L* mu = O - <O> I
-  (through the deflated adjoint operator), then
+  (through the deflated adjoint operator; densely, or matrix-free by ``adjoint_state_gmres``), then
   g_H = i [rho, mu],  g_Lj = L_j {rho, mu} - 2 mu L_j rho.
 * ``grad_fd``             -- central finite differences of J along given directions.
 """
@@ -83,6 +83,31 @@ def adjoint_state_dense(H, Ls, O, rho, eta=1.0):
     A = M + eta * np.outer(vI, vI.conj())
     rhs = O - expectation(O, rho) * np.eye(n)
     mu = unvec(np.linalg.solve(dag(A), vec(rhs)), n)
+    return hermitize(mu)
+
+
+def adjoint_state_gmres(H, Ls, O, rho, eta=1.0, rtol=1e-13, m=40, max_cycles=60):
+    """Matrix-free form of ``adjoint_state_dense`` for sizes where the superoperator does not fit:
+    the deflated adjoint system (L~_eta)*(mu) = L*(mu) + eta Tr(mu) I = O - <O> I (the adjoint of
+    eq. steady_state_linear_problem's operator) solved by the oracle's right-preconditioned GMRES
+    with the adjoint no-jump inverse S*^{-1}, S*(X) = G^+ X + X G, as preconditioner (the Remark
+    "Differentiating the steady state" preconditions the adjoint solve with the adjoint Lyapunov
+    operator).  S*^{-1} is the eigendecomposition solve of eq. lyapu_eig_solution applied to G^+
+    (its Lyapunov equation G^+ X + X (G^+)^+ = Y is S*(X) = Y).  Returned hermitised.
+    Pinned against ``adjoint_state_dense`` at small n in the oracle's tests."""
+    from .krylov import gmres
+    from .lindblad import EigResolvent, no_jump_generator
+
+    n = H.shape[0]
+    G = no_jump_generator(H, Ls)
+    Radj = EigResolvent(dag(G))
+    I = np.eye(n, dtype=np.complex128)
+    rhs = O - expectation(O, rho) * I
+
+    def A(X):
+        return lindblad_adjoint_apply(H, Ls, X) + eta * np.trace(X) * I
+
+    mu = gmres(A, rhs, apply_P=Radj.sinv, m=m, max_cycles=max_cycles, atol=rtol * np.linalg.norm(rhs))
     return hermitize(mu)
 
 

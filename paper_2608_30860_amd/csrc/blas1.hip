@@ -44,37 +44,70 @@ static int nparts(long long len) {
 }
 
 // ---------------------------------------------------------------- multi-dot (Gram-Schmidt) ----
-// stage 1: block b handles a contiguous chunk; groups of 8 basis vectors share one read of w.
+// stage 1 on a 2-D grid: block (x, y) takes row chunk x of every vector and the 8 basis vectors of
+// group y, so a launch has (row chunks) x (k / 8) independent blocks; w's chunk is read once per
+// group (it stays in L2 across the groups).  The 16 partial sums of a thread are reduced in one
+// pass at the end (wave shuffles, one LDS exchange between the 4 waves).
+static constexpr int MDG = 8;  // basis vectors per block
+static int mdot_parts(long long len) {
+  long long p = (len + 2047) / 2048;  // >= 8 rows per thread and vector
+  if (p > NPART) p = NPART;
+  if (p < 1) p = 1;
+  return (int)p;
+}
 __global__ __launch_bounds__(RB) void k_mdot1(const zd* __restrict__ V, long long ld, int k,
                                               const zd* __restrict__ w, long long len,
                                               zd* __restrict__ part, int np) {
-  __shared__ double sh[4];
-  long long chunk = (len + np - 1) / np;
-  long long i0 = (long long)blockIdx.x * chunk;
-  long long i1 = i0 + chunk < len ? i0 + chunk : len;
-  for (int j0 = 0; j0 < k; j0 += 8) {
-    double sr[8], si[8];
+  __shared__ double sh[RB / 64][2 * MDG];
+  const long long chunk = (len + np - 1) / np;
+  const long long i0 = (long long)blockIdx.x * chunk;
+  const long long i1 = i0 + chunk < len ? i0 + chunk : len;
+  const int j0 = blockIdx.y * MDG;
+  const int nv = k - j0 < MDG ? k - j0 : MDG;
+  double sr[MDG], si[MDG];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) { sr[t] = 0; si[t] = 0; }
+  for (int t = 0; t < MDG; ++t) { sr[t] = 0; si[t] = 0; }
+  const zd* Vb = V + (long long)j0 * ld;
+  if (nv == MDG) {
     for (long long i = i0 + threadIdx.x; i < i1; i += RB) {
-      zd x = w[i];
+      const zd x = w[i];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        if (j0 + t < k) {
-          zd v = V[(long long)(j0 + t) * ld + i];
+      for (int t = 0; t < MDG; ++t) {
+        const zd v = Vb[(long long)t * ld + i];
+        sr[t] += v.x * x.x + v.y * x.y;
+        si[t] += v.x * x.y - v.y * x.x;
+      }
+    }
+  } else {
+    for (long long i = i0 + threadIdx.x; i < i1; i += RB) {
+      const zd x = w[i];
+#pragma unroll
+      for (int t = 0; t < MDG; ++t) {
+        if (t < nv) {
+          const zd v = Vb[(long long)t * ld + i];
           sr[t] += v.x * x.x + v.y * x.y;
           si[t] += v.x * x.y - v.y * x.x;
         }
       }
     }
+  }
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      if (j0 + t < k) {
-        double a = block_sum(sr[t], sh);
-        double b = block_sum(si[t], sh);
-        if (threadIdx.x == 0) part[(long long)(j0 + t) * np + blockIdx.x] = zmk(a, b);
-      }
-    }
+  for (int t = 0; t < MDG; ++t) {
+    sr[t] = warp_sum(sr[t]);
+    si[t] = warp_sum(si[t]);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int t = 0; t < MDG; ++t) { sh[wv][2 * t] = sr[t]; sh[wv][2 * t + 1] = si[t]; }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    const int t = threadIdx.x;
+    double a = 0, b = 0;
+#pragma unroll
+    for (int q = 0; q < RB / 64; ++q) { a += sh[q][2 * t]; b += sh[q][2 * t + 1]; }
+    part[(long long)(j0 + t) * np + blockIdx.x] = zmk(a, b);
   }
 }
 __global__ __launch_bounds__(RB) void k_mdot2(const zd* __restrict__ part, int np, zd* __restrict__ h) {
@@ -94,8 +127,8 @@ __global__ __launch_bounds__(RB) void k_mdot2(const zd* __restrict__ part, int n
 int multi_dot(const zd* V, long long ld, int k, const zd* w, long long len, zd* h, zd* scratch,
               hipStream_t st) {
   if (k <= 0) return 0;
-  int np = nparts(len);
-  hipLaunchKernelGGL(k_mdot1, dim3(np), dim3(RB), 0, st, V, ld, k, w, len, scratch, np);
+  const int np = mdot_parts(len);
+  hipLaunchKernelGGL(k_mdot1, dim3(np, (k + MDG - 1) / MDG), dim3(RB), 0, st, V, ld, k, w, len, scratch, np);
   hipLaunchKernelGGL(k_mdot2, dim3(k), dim3(RB), 0, st, scratch, np, h);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }

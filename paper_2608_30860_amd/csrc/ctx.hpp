@@ -15,7 +15,8 @@ typedef std::complex<double> cplx;
 enum { PROF_JUMP_STACK = 0, PROF_JUMP_REDUCE = 1, PROF_BASIS_IN = 2, PROF_PHI = 3, PROF_RESID = 4, PROF_CGS = 5 };
 
 struct Ctx;
-constexpr int kMaxLong = 1024;  // longest GMRES cycle (basis vectors kept in HBM)
+constexpr int kMaxLong = 6144;  // longest GMRES cycle (basis vectors kept in HBM)
+constexpr int kHostScalars = 2 * kMaxLong + 4096;  // complex128 slots of the pinned host buffer
 // recycled subspace of the GCRO-DR solver: (A P) U = C with orthonormal C, k vectors of n*n
 struct Recycle {
   int k = 0, cap = 0;

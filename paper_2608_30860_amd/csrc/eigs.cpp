@@ -189,7 +189,7 @@ extern "C" int lind_eigs(lind_ctx* ctx, int k, double mu_re, double mu_im, doubl
         Hk[(size_t)i * m + j] += cplx(c.hsc[8 + i].x + c.hsc[80 + i].x, c.hsc[8 + i].y + c.hsc[80 + i].y);
       Hk[(size_t)(j + 1) * m + j] = hn;
       if (hn > 0) TRY(scale_by_inv(wv, n2, (const double*)(c.dsc + 4), c.st));
-      if (deadline > 0 && now_s() > deadline) break;
+      // (the time limit is checked between restarts: a thick restart needs the whole m-step basis)
     }
     // Ritz pairs of the m x m projected matrix
     int rc = small_eig_host(X, Hk, m, m, w, Y);
@@ -387,7 +387,7 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
     return apply_precond(c, P, in, out, c.prec);
   };
   // recycled GMRES(40) first; if it has not converged after a dozen cycles the preconditioned adjoint
-  // is strongly non-normal (long chains of levels), and one long cycle (up to 1024 steps, basis in
+  // is strongly non-normal (long chains of levels), and one long cycle (up to kMaxLong steps, basis in
   // HBM) continues from the current iterate
   const double rtol_adj = std::min(1e-9, std::max(1e-13, 0.01 * tol));
   GmresResult gr;
@@ -398,16 +398,46 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
   if (!gr.converged && !gr.stagnated) {
     const double r0 = gr.resid0;
     GmresResult g2;
-    const int ml = long_cycle_len(c, kMaxLong, true);
-    int rc2 = gmres_rec(X, Aop, &Pop, rhs, wadj, false, ml, 0, 4, rtol_adj, 0.0, c.rec, g2, 0.0);
+    int rc2 = 0;
+    if (c.prec == PREC_F64) {
+      // FP64 preconditioner (linear to rounding): plain right preconditioning keeps one basis, half
+      // the memory of the flexible form, so the cycle can be twice as long.  Solve (A P) y = r with
+      // r = rhs - A w from the current iterate, then w += P y.  A truncated Fock ladder needs a
+      // Krylov space of a few times n (about 4n for the dephased Kerr cavity at n = 128): one
+      // cycle, restarted only to confirm the true residual.
+      const int ml = long_cycle_len(c, kMaxLong, false);
+      zd* r = X->zetaB;
+      zd* y = X->rhoB;
+      zd* t = X->delB;
+      TRY(Aop(wadj, r));
+      TRY(axpby(zmk(1, 0), rhs, zmk(-1, 0), r, n2, c.st));
+      std::function<int(const zd*, zd*)> APop = [&](const zd* in, zd* out) -> int {
+        int e = Pop(in, t);
+        return e ? e : Aop(t, out);
+      };
+      rc2 = gmres_rec(X, APop, nullptr, r, y, true, ml, 0, 3, 0.0, rtol_adj * r0, c.rec, g2, 0.0);
+      if (!rc2) rc2 = Pop(y, t);
+      if (!rc2) rc2 = axpby(zmk(1, 0), t, zmk(1, 0), wadj, n2, c.st) ? LIND_EDEVICE : 0;
+    } else {
+      const int ml = long_cycle_len(c, kMaxLong, true);
+      rc2 = gmres_rec(X, Aop, &Pop, rhs, wadj, false, ml, 0, 4, rtol_adj, 0.0, c.rec, g2, 0.0);
+    }
     release_long_basis(c);
     TRY(rc2);
     inf.n_inner += g2.iters;
     g2.resid0 = r0;  // relative to ||rhs||, as for the first attempt
     gr = g2;
   }
-  // hermitise w (exact adjoint state is Hermitian for Hermitian O)
+  // hermitise w (exact adjoint state is Hermitian for Hermitian O), then its true relative residual
   TRY(hermitize(wadj, n, 0, nullptr, c.dscr, c.st));
+  double adj_rel = 0.0;
+  {
+    TRY(Aop(wadj, X->zetaB));
+    TRY(axpby(zmk(1, 0), rhs, zmk(-1, 0), X->zetaB, n2, c.st));
+    double rn = 0;
+    TRY(op_nrm(c, X->zetaB, &rn));
+    adj_rel = rn / std::max(gr.resid0, 1e-300);
+  }
   // g_H = i (rho w - w rho); M = rho w + w rho
   if (grad_H) {
     TRY(op_gemm(c, PREC_F64, n, n, n, rho, n, OP_N, wadj, n, OP_N, grad_H, n, cplx(0, 1), 0));
@@ -434,17 +464,18 @@ extern "C" int lind_steady_grad(lind_ctx* ctx, const void* O, double tol, double
       if (*it == (void*)p) { c.allocs.erase(it); break; }
     hipFree(p);
   }
-  inf.err_est = gr.resid / std::max(gr.resid0, 1e-300);
+  inf.err_est = adj_rel;
   inf.t_solve_s = now_s() - t0;
   if (info) *info = inf;
   if (status) return c.fail(status, "steady state for the gradient did not reach the tolerance");
-  // a solve stopped at its rounding floor (restarts no longer reduce the true residual) is accepted
-  // when that floor is far below what the gradient needs
-  const bool adj_ok = gr.converged || (gr.stagnated && gr.resid <= 1e-10 * std::max(gr.resid0, 1e-300));
+  // a solve that stops at its rounding floor short of rtol_adj is accepted when the true relative
+  // residual is far below what the gradient needs (1e-10; the FP64 floor of the long chains of a
+  // truncated Fock ladder sits near 1e-13)
+  const bool adj_ok = adj_rel <= std::max(10.0 * rtol_adj, 1e-10);
   if (!adj_ok) {
     char msg[160];
     std::snprintf(msg, sizeof msg, "adjoint GMRES did not converge (relative residual %.2e after %d iterations)",
-                  gr.resid / std::max(gr.resid0, 1e-300), gr.iters);
+                  adj_rel, inf.n_inner);
     return c.fail(LIND_ENOCONV, msg);
   }
   return LIND_OK;

@@ -95,7 +95,7 @@ int maxpy(Ctx& c, const zd* V, int k, const zd* h, zd* w, int accumulate, double
 
 int upload(Ctx& c, const std::vector<cplx>& v, zd* dst) {
   const size_t cnt = v.size();
-  if (cnt > 8000) return LIND_EINVAL;
+  if (cnt > (size_t)kHostScalars) return LIND_EINVAL;
   for (size_t i = 0; i < cnt; ++i) c.hsc[i] = zmk(v[i].real(), v[i].imag());
   if (hipMemcpyAsync(dst, c.hsc, sizeof(zd) * cnt, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
   return c.sync();  // the pinned staging buffer is reused right after
@@ -259,7 +259,11 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
     }
     TRY(scale_by_inv(r, n2, (const double*)c.dsc, c.st));  // dsc[0] holds beta
     const int mm = m - kc;
-    std::vector<cplx> Hraw((size_t)(mm + 1) * mm, 0.0), Hg((size_t)(mm + 1) * mm, 0.0);
+    // Hraw (the unrotated Hessenberg) is kept only for the recycle update; without recycling (the
+    // long cycles, up to kMaxLong steps) the columns go straight into Hg
+    std::vector<cplx> Hg((size_t)(mm + 1) * mm, 0.0);
+    std::vector<cplx> Hraw(kdef > 0 ? (size_t)(mm + 1) * mm : 0, 0.0);
+    std::vector<cplx>& HR = kdef > 0 ? Hraw : Hg;
     std::vector<cplx> Bh((size_t)std::max(kc, 1) * mm, 0.0);
     std::vector<cplx> cs(mm), sn(mm), g(mm + 1, 0.0);
     g[0] = beta;
@@ -288,11 +292,12 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
       for (int i = 0; i < nb; ++i) {
         const cplx h = cplx(c.hsc[1 + i].x, c.hsc[1 + i].y) + cplx(c.hsc[1 + nb + i].x, c.hsc[1 + nb + i].y);
         if (i < kc) Bh[(size_t)i * mm + j] = h;
-        else Hraw[(size_t)(i - kc) * mm + j] = h;
+        else HR[(size_t)(i - kc) * mm + j] = h;
       }
-      Hraw[(size_t)(j + 1) * mm + j] = hn;
+      HR[(size_t)(j + 1) * mm + j] = hn;
       if (hn > 0) TRY(scale_by_inv(w, n2, (const double*)nrmdev, c.st));
-      for (int i = 0; i <= j + 1; ++i) Hg[(size_t)i * mm + j] = Hraw[(size_t)i * mm + j];
+      if (kdef > 0)
+        for (int i = 0; i <= j + 1; ++i) Hg[(size_t)i * mm + j] = Hraw[(size_t)i * mm + j];
       for (int i = 0; i < j; ++i) {
         const cplx a = Hg[(size_t)i * mm + j], bb = Hg[(size_t)(i + 1) * mm + j];
         Hg[(size_t)i * mm + j] = cs[i] * a + sn[i] * bb;

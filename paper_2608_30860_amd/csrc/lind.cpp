@@ -291,7 +291,7 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
     if (wsb > 0) rc |= c.alloc((char**)&c.gws, (size_t)wsb);
     c.gws_bytes = wsb;
   }
-  if (rc == 0 && hipHostMalloc((void**)&c.hsc, sizeof(zd) * 8192) != hipSuccess) rc = LIND_ENOMEM;
+  if (rc == 0 && hipHostMalloc((void**)&c.hsc, sizeof(zd) * kHostScalars) != hipSuccess) rc = LIND_ENOMEM;
   if (rc) {
     delete X;
     g_create_err = "out of device memory";
@@ -594,7 +594,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     for (int rs = 0; restarts_left > 0 && !converged; ++rs) {
       --restarts_left;
       std::fill(Hh.begin(), Hh.end(), cplx(0));
-      int k = 0, sel = 0;
+      int k = 0, sel = 0, k_ritz = 0;  // k_ritz: the Krylov dimension the Ritz pair (w, Y) belongs to
       double est = 1e300;
       for (int j = 0; j < m; ++j) {
         zd* vj = K + (long long)j * n2;
@@ -619,6 +619,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
         if (check) {
           int rc = small_eig_host(X, Hh, m, k, w, Y);
           if (rc && rc != LIND_ENOCONV) return rc;
+          k_ritz = k;
           sel = pick_nearest_one(w);
           cplx th = w[sel];
           cplx ylast = Y[(size_t)(k - 1) * k + sel];
@@ -626,6 +627,12 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
           if (c_scale * est <= std::max(0.25 * tol, eps_floor) || hn == 0.0) break;
         }
         if (deadline > 0 && now_s() > deadline) break;
+      }
+      // the cycle may end (time limit) at a step without a Ritz evaluation: evaluate it for this k
+      if (k_ritz != k) {
+        int rc = small_eig_host(X, Hh, m, k, w, Y);
+        if (rc && rc != LIND_ENOCONV) return rc;
+        sel = pick_nearest_one(w);
       }
       // Ritz vector xi = V_k y
       std::vector<cplx> ysel(k);

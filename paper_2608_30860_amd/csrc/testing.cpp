@@ -151,3 +151,32 @@ extern "C" int lindx_p4_test(const void* A, const void* B, int M, int N, int K, 
   return rc;
 }
 
+
+// One Gram-Schmidt step of the Arnoldi and GMRES drivers (classical, twice): h1 = V^H w,
+// w -= V h1, h2 = V^H w, w -= V h2, nrm = ||w||, with the basis taken in chunks as the drivers do
+// (64 vectors per dot launch, 128 per update launch).  h: device, 2k complex128 (h1 then h2).
+extern "C" int lindx_cgs2(const void* V, long long ld, int k, void* w, long long len, void* h, void* nrm,
+                          int reps, void* stream) {
+  if (!V || !w || !h || !nrm || k < 1 || len < 1 || ld < len || reps < 1) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  void* scr = nullptr;
+  const size_t scr_bytes = sizeof(zd) * (size_t)64 * 1024 + 4096;
+  if (hipMalloc(&scr, scr_bytes) != hipSuccess) return -5;
+  const zd* Vz = (const zd*)V;
+  zd* wz = (zd*)w;
+  zd* hz = (zd*)h;
+  int rc = 0;
+  for (int r = 0; r < reps && !rc; ++r) {
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
+      zd* hp = hz + (long long)pass * k;
+      for (int c0 = 0; c0 < k && !rc; c0 += 64)
+        rc = multi_dot(Vz + (long long)c0 * ld, ld, std::min(64, k - c0), wz, len, hp + c0, (zd*)scr, st);
+      for (int c0 = 0; c0 < k && !rc; c0 += 128)
+        rc = multi_axpy(Vz + (long long)c0 * ld, ld, std::min(128, k - c0), hp + c0, wz, len, 1, -1.0, st);
+    }
+    if (!rc) rc = nrm2(wz, len, (double*)nrm, (double*)scr, st);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = -4;
+  hipFree(scr);
+  return rc;
+}

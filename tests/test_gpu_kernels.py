@@ -20,6 +20,7 @@ def lib():
     L.lindx_triinv.argtypes = [vp, vp, ci, vp]
     L.lindx_trisylv.argtypes = [vp, vp, ci, cd, cd, vp]
     L.lindx_p4_test.argtypes = [vp, vp, ci, ci, ci, ci, ci, ci, ci, vp, vp, vp, vp]
+    L.lindx_cgs2.argtypes = [vp, ll, ci, vp, ll, vp, vp, ci, vp]
     return L
 
 
@@ -238,3 +239,35 @@ def test_trisylv(n, shift):
     Xn = X.cpu().numpy()
     res = Tm @ Xn + Xn @ Tm.conj().T + shift * Xn - C
     assert np.max(np.abs(res)) < 1e-12 * np.abs(C).max() * n
+
+
+@pytest.mark.parametrize("k,length,pad", [(1, 1, 0), (9, 5000, 3), (64, 4096, 0), (65, 3001, 7), (200, 20000, 16),
+                                          (31, 2048 * 2048, 0)])
+def test_cgs2_step(k, length, pad):
+    """One classical Gram-Schmidt step with re-orthogonalisation (the Arnoldi/GMRES kernels: 2-D dot
+    kernel, multi-vector update, norm) against NumPy on an orthonormal random basis: both coefficient
+    passes, the updated vector and its norm (FP64).  Ragged lengths, padded strides, chunked k."""
+    rng = np.random.default_rng(k + length)
+    ld = length + pad
+    Vh = crand(rng, k, length)
+    if k <= length:
+        Q, _ = np.linalg.qr(Vh.T)  # orthonormal columns
+        Vh = Q.T.copy()
+    Vst = np.zeros((k, ld), dtype=np.complex128)
+    Vst[:, :length] = Vh
+    w0 = crand(rng, length)
+    V_d, w_d = T(Vst), T(w0)
+    h_d = torch.zeros(2 * k, dtype=torch.complex128, device="cuda:0")
+    nrm_d = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    rc = lib().lindx_cgs2(P(V_d), ld, k, P(w_d), length, P(h_d), P(nrm_d), 1, None)
+    assert rc == 0
+    h1 = Vh.conj() @ w0
+    w1 = w0 - Vh.T @ h1
+    h2 = Vh.conj() @ w1
+    w2 = w1 - Vh.T @ h2
+    h = h_d.cpu().numpy()
+    scale = np.linalg.norm(w0)
+    assert np.max(np.abs(h[:k] - h1)) <= 1e-13 * scale
+    assert np.max(np.abs(h[k:] - h2)) <= 1e-13 * scale
+    assert np.max(np.abs(w_d.cpu().numpy() - w2)) <= 1e-13 * scale
+    assert abs(float(nrm_d.cpu()[0]) - np.linalg.norm(w2)) <= 1e-12 * scale
