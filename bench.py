@@ -91,7 +91,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the resolvent / implicit Euler measurement")
     ap.add_argument("--no-configs", action="store_true", help="skip the Phi rates of the other workloads")
     ap.add_argument("--phi-loop", type=int, default=10, help="Phi applications per precision in the pure loop")
-    ap.add_argument("--kernel-only", default=None, help="profiling mode: only run Phi loops in this precision")
+    ap.add_argument("--kernel-only", default=None,
+                    help="profiling mode: fp64 | fp32 | bf16x3 (the stacked jump product alone) or hbm "
+                         "(the bandwidth-bound kernels)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -124,6 +126,34 @@ def main():
     Lt = torch.from_numpy(np.stack(Ls)).to(dev)
     torch.cuda.synchronize()
 
+    if args.kernel_only == "hbm":
+        # counter runs of the bandwidth-bound kernels at the benchmarked size: three Gram-Schmidt
+        # steps against 31 basis vectors (the longest step of an Arnoldi cycle of 30), then two mixed
+        # steady-state solves (vector splits into bf16 planes, hermitise/trace, residual norms), then
+        # one plain copy of 512 MiB for calibration
+        lib.lindx_cgs2.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_longlong, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+        lib.lindx_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_longlong, ctypes.c_void_p]
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        kq, ln = 31, n * n
+        V = torch.randn(kq, ln, dtype=torch.complex128, device=dev)
+        w = torch.randn(ln, dtype=torch.complex128, device=dev)
+        hh = torch.zeros(2 * kq, dtype=torch.complex128, device=dev)
+        nr = torch.zeros(1, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            assert lib.lindx_cgs2(ctypes.c_void_p(V.data_ptr()), ln, kq, ctypes.c_void_p(w.data_ptr()), ln,
+                                  ctypes.c_void_p(hh.data_ptr()), ctypes.c_void_p(nr.data_ptr()), 1, stream) == 0
+        del V
+        mh = Lindblad(Ht, Lt, prec="bf16x3")
+        for _ in range(2):
+            mh.steady_state(args.tol)
+        mh.close()
+        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        assert lib.lindx_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), src.numel(), stream) == 0
+        torch.cuda.synchronize()
+        log("[bench] kernel-only hbm: 3 Gram-Schmidt steps (k = 31), 2 mixed solves, one 512 MiB copy")
+        return
     if args.kernel_only:
         # counter runs: the stacked jump product alone at the benchmarked shape (random operands
         # of the same size and type), then one plain copy of 512 MiB for calibration
@@ -354,6 +384,36 @@ def main():
         if k_ in compare:
             t_to_tol[k_] = compare[k_]
 
+    # the bandwidth-bound Arnoldi orthogonalisation at this size: one classical Gram-Schmidt step
+    # with re-orthogonalisation against 31 basis vectors (the longest step of an Arnoldi cycle of
+    # 30), timed over 5 repetitions; algorithmic bytes = two passes of (dot: k + 1 vectors read;
+    # update: k + 1 read, 1 written) plus the norm's read, 16 n^2 bytes per vector
+    hbm = None
+    try:
+        lib.lindx_cgs2.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_longlong, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+        kq, ln = 31, n * n
+        V = torch.randn(kq, ln, dtype=torch.complex128, device=dev)
+        w = torch.randn(ln, dtype=torch.complex128, device=dev)
+        hh = torch.zeros(2 * kq, dtype=torch.complex128, device=dev)
+        nr = torch.zeros(1, dtype=torch.float64, device=dev)
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        args_ = (ctypes.c_void_p(V.data_ptr()), ln, kq, ctypes.c_void_p(w.data_ptr()), ln,
+                 ctypes.c_void_p(hh.data_ptr()), ctypes.c_void_p(nr.data_ptr()))
+        assert lib.lindx_cgs2(*args_, 1, stream) == 0
+        reps = 5
+        t0 = time.perf_counter()
+        assert lib.lindx_cgs2(*args_, reps, stream) == 0
+        dt = (time.perf_counter() - t0) / reps
+        byts = 16.0 * ln * (2 * ((kq + 1) + (kq + 2)) + 1)
+        hbm = {"kernel": "Gram-Schmidt step (k_mdot1/k_mdot2, k_maxpy, twice; k_sumsq1): k = 31 vectors of n^2",
+               "bound": "hbm", "ms_per_step": 1e3 * dt, "algorithmic_bytes": byts,
+               "achieved": byts / dt / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": byts / dt / 1e9 / PEAK_HBM_GBS}
+        del V, w
+        log(f"[bench] Gram-Schmidt {hbm}")
+    except Exception as e:  # a measurement, not part of the timed result
+        log(f"[bench] Gram-Schmidt timing skipped: {e}")
+
     # resolvent benchmark of the paper (after the timed region): (lambda - L) X = I/n at
     # lambda = lambda_max * 10^{0,-1,-2}, lambda_max the spectral radius of L by power iteration
     # (off the clock), plus implicit Euler steps at dt = 1/lambda_max * 100
@@ -430,7 +490,7 @@ def main():
                                   f"||L rho||_1 bound <= {args.tol:g}", "n": n, "d": d, "tol": args.tol,
                       "step": "one steady-state solve (Arnoldi on Phi + FP64 refinement); factorisation once, "
                               "reported in time_to_tol", "parallelism": "single GPU"},
-           "time_to_tol": t_to_tol, "roofline": roof, "kernels": other, "cpu_baseline": cpu,
+           "time_to_tol": t_to_tol, "roofline": roof, "kernels": other, "hbm_kernels": hbm, "cpu_baseline": cpu,
            "create_s": t_create, "resolvent": extras, "phi_rates": per_config}
     model.close()
     print(json.dumps(out), flush=True)

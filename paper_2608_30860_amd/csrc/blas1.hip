@@ -263,20 +263,34 @@ int to_c128(const zf* x, zd* y, long long len, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- matrix helpers ------------
-__global__ void k_hermitize(zd* X, int n) {
-  long long tot = (long long)n * n;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-    int i = (int)(t / n), j = (int)(t - (long long)i * n);
-    if (j < i) continue;
-    if (i == j) {
-      X[t].y = 0.0;
-    } else {
-      zd a = X[(long long)i * n + j], b = X[(long long)j * n + i];
-      zd m = zmk(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-      X[(long long)i * n + j] = m;
-      X[(long long)j * n + i] = zconj(m);
-    }
+// X <- (X + X^H)/2 in place, in pairs of 32 x 32 tiles (bm <= bn): both tiles are read and
+// written row by row, the transposed one through LDS
+__global__ __launch_bounds__(RB) void k_hermitize(zd* X, int n) {
+  __shared__ zd a[32][33], b[32][33];
+  const int tn = (n + 31) / 32;
+  int t = blockIdx.x, bm = 0;
+  while (t >= tn - bm) { t -= tn - bm; ++bm; }
+  const int bn = bm + t;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int r1 = bm * 32 + yy, c1 = bn * 32 + tx;  // upper tile
+    const int r2 = bn * 32 + yy, c2 = bm * 32 + tx;  // lower tile
+    a[yy][tx] = (r1 < n && c1 < n) ? X[(long long)r1 * n + c1] : zmk(0, 0);
+    b[yy][tx] = (r2 < n && c2 < n) ? X[(long long)r2 * n + c2] : zmk(0, 0);
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    // upper entry (r1, c1): (a[yy][tx] + conj(b[tx][yy])) / 2; its mirror is (c1, r1)
+    const int r1 = bm * 32 + yy, c1 = bn * 32 + tx;
+    const zd u = a[yy][tx], v = b[tx][yy];
+    zd m = zmk(0.5 * (u.x + v.x), 0.5 * (u.y - v.y));
+    if (r1 == c1) m.y = 0.0;
+    if (r1 < n && c1 < n && (bm < bn || r1 <= c1)) X[(long long)r1 * n + c1] = m;
+    // lower entry (r2, c2) = conj of upper entry (c2, r2) = (a[tx][yy] + conj(b[yy][tx])) / 2
+    const int r2 = bn * 32 + yy, c2 = bm * 32 + tx;
+    const zd u2 = a[tx][yy], v2 = b[yy][tx];
+    const zd m2 = zmk(0.5 * (u2.x + v2.x), -0.5 * (u2.y - v2.y));
+    if (r2 < n && c2 < n && (bm < bn || r2 > c2)) X[(long long)r2 * n + c2] = m2;
   }
 }
 __global__ __launch_bounds__(RB) void k_trace(const zd* X, int n, zd* out) {
@@ -302,7 +316,10 @@ __global__ void k_scale_by_trace(zd* X, long long len, const zd* tr) {
 int hermitize(zd* X, int n, int normalize_trace, zd* trace_out, double* scratch, hipStream_t st) {
   (void)scratch;
   long long len = (long long)n * n;
-  hipLaunchKernelGGL(k_hermitize, dim3(grid_for(len)), dim3(RB), 0, st, X, n);
+  {
+    const long long tn = (n + 31) / 32;
+    hipLaunchKernelGGL(k_hermitize, dim3((int)(tn * (tn + 1) / 2)), dim3(RB), 0, st, X, n);
+  }
   if (trace_out) hipLaunchKernelGGL(k_trace, dim3(1), dim3(RB), 0, st, X, n, trace_out);
   if (normalize_trace && trace_out)
     hipLaunchKernelGGL(k_scale_by_trace, dim3(grid_for(len)), dim3(RB), 0, st, X, len, trace_out);
@@ -349,20 +366,43 @@ __global__ __launch_bounds__(RB) void k_colnorm1(const zd* X, int n, int rchunk,
     if (rg == 0) pdiag[c] = fabs(v.y);
   }
 }
+// per-column totals over the row chunks (one thread per column, contiguous across threads), then
+// per-block partials of (sum |x|^2, sum of column 2-norms, max |x|^2, max |Im x_cc|)
 __global__ __launch_bounds__(RB) void k_colnorm2(int n, int nrc, const double* psum, const double* pmax,
-                                                 const double* pdiag, double* out) {
+                                                 const double* pdiag, double* part) {
   __shared__ double sh[4];
   double fro = 0, mx = 0, colsum = 0, dmx = 0;
-  for (int c = threadIdx.x; c < n; c += RB) {
+  const int c = blockIdx.x * RB + threadIdx.x;
+  if (c < n) {
     double s = 0, m = 0;
     for (int r = 0; r < nrc; ++r) {
       s += psum[(long long)r * n + c];
       m = fmax(m, pmax[(long long)r * n + c]);
     }
-    fro += s;
-    mx = fmax(mx, m);
-    colsum += sqrt(s);
-    dmx = fmax(dmx, pdiag[c]);
+    fro = s;
+    mx = m;
+    colsum = sqrt(s);
+    dmx = pdiag[c];
+  }
+  fro = block_sum(fro, sh);
+  colsum = block_sum(colsum, sh);
+  mx = block_max(mx, sh);
+  dmx = block_max(dmx, sh);
+  if (threadIdx.x == 0) {
+    part[4 * blockIdx.x] = fro;
+    part[4 * blockIdx.x + 1] = colsum;
+    part[4 * blockIdx.x + 2] = mx;
+    part[4 * blockIdx.x + 3] = dmx;
+  }
+}
+__global__ __launch_bounds__(RB) void k_colnorm3(int nb, const double* part, double* out) {
+  __shared__ double sh[4];
+  double fro = 0, mx = 0, colsum = 0, dmx = 0;
+  for (int b = threadIdx.x; b < nb; b += RB) {
+    fro += part[4 * b];
+    colsum += part[4 * b + 1];
+    mx = fmax(mx, part[4 * b + 2]);
+    dmx = fmax(dmx, part[4 * b + 3]);
   }
   fro = block_sum(fro, sh);
   colsum = block_sum(colsum, sh);
@@ -382,8 +422,11 @@ int mat_norms(const zd* X, int n, double* out, double* scratch, hipStream_t st) 
   double* psum = scratch;
   double* pmax = scratch + (long long)nrc * n;
   double* pdiag = scratch + 2LL * nrc * n;
+  double* part = pdiag + n;
+  const int nb = (n + RB - 1) / RB;
   hipLaunchKernelGGL(k_colnorm1, dim3((n + 63) / 64, nrc), dim3(RB), 0, st, X, n, rchunk, psum, pmax, pdiag);
-  hipLaunchKernelGGL(k_colnorm2, dim3(1), dim3(RB), 0, st, n, nrc, psum, pmax, pdiag, out);
+  hipLaunchKernelGGL(k_colnorm2, dim3(nb), dim3(RB), 0, st, n, nrc, psum, pmax, pdiag, part);
+  hipLaunchKernelGGL(k_colnorm3, dim3(1), dim3(RB), 0, st, nb, part, out);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
@@ -393,6 +436,16 @@ __global__ void k_add_identity(zd* X, int n, zd c) {
 }
 int add_identity(zd* X, int n, zd c, hipStream_t st) {
   hipLaunchKernelGGL(k_add_identity, dim3((n + RB - 1) / RB), dim3(RB), 0, st, X, n, c);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+__global__ void k_add_identity_dev(zd* X, int n, const zd* t, zd c) {
+  const zd a = zmul(c, t[0]);
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X[(long long)i * n + i] = zadd(X[(long long)i * n + i], a);
+}
+int add_identity_trace(zd* X, int n, const zd* Y, zd c, zd* scratch_tr, hipStream_t st) {
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(RB), 0, st, Y, n, scratch_tr);
+  hipLaunchKernelGGL(k_add_identity_dev, dim3((n + RB - 1) / RB), dim3(RB), 0, st, X, n, (const zd*)scratch_tr, c);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

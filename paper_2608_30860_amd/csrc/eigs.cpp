@@ -36,10 +36,8 @@ int apply_shifted_deflated(Ctx& c, const zd* x, zd* out, cplx mu, double eta, bo
   else TRY(op_apply(c, x, out, false));
   cplx m = adjoint ? std::conj(mu) : mu;
   TRY(axpby(zmk(m.real(), m.imag()), x, zmk(-1, 0), out, c.n2, c.st));
-  cplx tr;
-  TRY(op_trace(c, x, &tr));
-  tr *= -eta;
-  TRY(add_identity(out, c.n, zmk(tr.real(), tr.imag()), c.st));
+  // - eta Tr(x) I with the trace kept on the device (no host round trip per Krylov step)
+  TRY(add_identity_trace(out, c.n, x, zmk(-eta, 0), c.dsc + 980, c.st));
   return 0;
 }
 
@@ -55,10 +53,8 @@ struct Precond {
 int apply_precond(Ctx& c, const Precond& P, const zd* x, zd* out, int prec) {
   TRY(op_sinv(c, x, out, P.mu, prec, P.adjoint));
   TRY(axpby(zmk(0, 0), out, zmk(-1, 0), out, c.n2, c.st));
-  cplx trZ;
-  TRY(op_trace(c, out, &trZ));
-  cplx coef = P.eta * trZ / (1.0 - P.eta * P.trW);
-  TRY(axpby(zmk(coef.real(), coef.imag()), P.W, zmk(1, 0), out, c.n2, c.st));
+  // Z + eta Tr(Z) / (1 - eta Tr W) W with Tr(Z) and the coefficient on the device
+  TRY(sherman_morrison(out, P.W, c.n, zmk(P.eta, 0), zmk(P.trW.real(), P.trW.imag()), c.dsc + 984, c.dscr, c.st));
   return 0;
 }
 

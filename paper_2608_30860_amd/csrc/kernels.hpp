@@ -104,6 +104,8 @@ int mat_norms(const zd* X, int n, double* out, double* scratch, hipStream_t st);
 // X += c * I
 int add_identity(zd* X, int n, zd c, hipStream_t st);
 // Sherman-Morrison step: Z += coef * W where coef = c*Tr(Z)/(1 - c*trW) computed on device
+// X += c Tr(Y) I with the trace taken on the device (scratch_tr: one device complex128)
+int add_identity_trace(zd* X, int n, const zd* Y, zd c, zd* scratch_tr, hipStream_t st);
 int sherman_morrison(zd* Z, const zd* W, int n, zd c, zd trW, zd* scratch_tr, double* scratch,
                      hipStream_t st);
 // D = G X (n x n) elementwise helpers for the generator: G = -iH - 1/2 W

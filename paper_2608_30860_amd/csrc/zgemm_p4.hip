@@ -281,24 +281,53 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
     }
 }
 
-// sum of the FP32 split-K partials, scaled by alpha, into complex128 (row-major, ldo)
+// sum of the FP32 split-K partials, scaled by alpha, into complex128 (row-major, ldo), in 32 x 32
+// tiles: every partial row is read once, contiguously.  Hermitian result (tri): only the tiles on
+// and above the diagonal are summed; each is written in place and, through an LDS transpose (so
+// the stores stay contiguous too), as the conjugate of the tile below the diagonal.
 __global__ __launch_bounds__(256) void k_p4_reduce(const float2* __restrict__ ws, int nsplit, int M, int N,
                                                    double alpha, zd* __restrict__ out, long long ldo, int tri) {
+  __shared__ zd sh[32][33];
   const long long tot = (long long)M * N;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-    const int row = (int)(t / N), col = (int)(t - (long long)row * N);
-    // Hermitian result: entries below the diagonal are the conjugates of those above it
-    const bool low = tri && row > col;
-    const long long src = low ? (long long)col * N + row : t;
-    double re = 0, im = 0;
-    for (int s = 0; s < nsplit; ++s) {
-      const float2 v = ws[(long long)s * tot + src];
-      re += v.x;
-      im += v.y;
+  const int tn = (N + 31) / 32;
+  int bm, bn;
+  if (tri) {
+    int t = blockIdx.x, r = 0;
+    while (t >= tn - r) { t -= tn - r; ++r; }
+    bm = r;
+    bn = r + t;
+  } else {
+    bm = blockIdx.x / tn;
+    bn = blockIdx.x - bm * tn;
+  }
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int row = bm * 32 + yy, col = bn * 32 + tx;
+    zd v = zmk(0, 0);
+    if (row < M && col < N) {
+      const long long o = (long long)row * N + col;
+      double re = 0, im = 0;
+      for (int sp = 0; sp < nsplit; ++sp) {
+        const float2 p = ws[(long long)sp * tot + o];
+        re += p.x;
+        im += p.y;
+      }
+      v = zmk(alpha * re, alpha * im);
+      if (tri && row == col) v.y = 0.0;
+      // on a diagonal tile the entries below the diagonal come from the mirror below
+      if (!tri || bm < bn || row <= col) out[(long long)row * ldo + col] = v;
     }
-    if (tri) im = (row == col) ? 0.0 : (low ? -im : im);
-    out[(long long)row * ldo + col] = zmk(alpha * re, alpha * im);
+    sh[yy][tx] = v;
+  }
+  if (!tri) return;
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    // entry (bn*32 + yy, bm*32 + tx) of the lower tile is the conjugate of (bm*32 + tx, bn*32 + yy)
+    const int row = bn * 32 + yy, col = bm * 32 + tx;
+    if (row < M && col < N && (bm < bn || row > col)) {
+      const zd v = sh[tx][yy];
+      out[(long long)row * ldo + col] = zmk(v.x, -v.y);
+    }
   }
 }
 
@@ -454,9 +483,8 @@ int p4_gemm(const P4Desc& g0, hipStream_t st) {
     if (!g.ws) return -1;
     int rc = launch_p4_out<true, P4OUT_WS>(g, blocks, st);
     if (rc) return rc;
-    long long tot = (long long)g.M * g.N;
-    long long nbk = (tot + 255) / 256;
-    if (nbk > 16384) nbk = 16384;
+    const long long t32m = (g.M + 31) / 32, t32n = (g.N + 31) / 32;
+    const long long nbk = g.tri ? t32n * (t32n + 1) / 2 : t32m * t32n;
     hipLaunchKernelGGL(k_p4_reduce, dim3((int)nbk), dim3(256), 0, st, (const float2*)g.ws, g.nsplit, g.M, g.N,
                        g.alpha, (zd*)g.out64, g.ldo, g.tri);
     return hipGetLastError() == hipSuccess ? 0 : -4;
