@@ -91,6 +91,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the resolvent / implicit Euler measurement")
     ap.add_argument("--no-configs", action="store_true", help="skip the Phi rates of the other workloads")
     ap.add_argument("--phi-loop", type=int, default=10, help="Phi applications per precision in the pure loop")
+    ap.add_argument("--eigs", action="store_true",
+                    help="also measure the low spectrum at this size (16 eigenvalues nearest --eigs-mu to 1e-8; "
+                         "about 15 minutes at n = 2048)")
+    ap.add_argument("--eigs-mu", type=float, default=-0.7408,
+                    help="shift of the spectrum measurement (0.03 right of the edge of the n = 2048, d = 8 workload)")
     ap.add_argument("--kernel-only", default=None,
                     help="profiling mode: fp64 | fp32 | bf16x3 (the stacked jump product alone) or hbm "
                          "(the bandwidth-bound kernels)")
@@ -447,6 +452,29 @@ def main():
                                      "gmres_steps": iinfo["n_inner"], "worst_rel_residual": iinfo["err_est"]}}
         log(f"[bench] extras {extras}")
 
+    # low spectrum (opt-in): Krylov-Schur shift-invert, BF16x3 inner solves refined on the FP64
+    # residual; the eigen-residuals are recomputed with the FP64 Lindbladian (lind_apply)
+    spectrum = None
+    if args.eigs:
+        me = Lindblad(Ht, Lt, prec=args.prec, m=48, time_limit_s=1500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vals, vecs, einfo = me.eigs(16, mu=args.eigs_mu, tol=1e-8, vectors=True, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t0
+        res = []
+        for t in range(16):
+            r_ = me.apply(vecs[t].contiguous()) - complex(vals[t]) * vecs[t]
+            res.append(float(r_.abs().max()))
+        order = np.argsort(np.abs(vals))
+        spectrum = {"k": 16, "mu": args.eigs_mu, "tol": 1e-8, "time_s": te, "status": einfo["status"],
+                    "restarts": einfo["n_restarts"], "inner_steps": einfo["n_inner"],
+                    "lowest10": [{"re": float(vals[i].real), "im": float(vals[i].imag), "abs": float(abs(vals[i])),
+                                  "resid_max": res[i]} for i in order[:10]],
+                    "worst_resid_max": max(res)}
+        me.close()
+        log(f"[bench] spectrum {spectrum}")
+
     # Phi-applications per second on the other workloads (after the timed region): plain loops of
     # Phi on a seeded Hermitian state, per precision mode the workload is specified with
     per_config = None
@@ -491,6 +519,7 @@ def main():
                       "step": "one steady-state solve (Arnoldi on Phi + FP64 refinement); factorisation once, "
                               "reported in time_to_tol", "parallelism": "single GPU"},
            "time_to_tol": t_to_tol, "roofline": roof, "kernels": other, "hbm_kernels": hbm, "cpu_baseline": cpu,
+           "low_spectrum": spectrum,
            "create_s": t_create, "resolvent": extras, "phi_rates": per_config}
     model.close()
     print(json.dumps(out), flush=True)

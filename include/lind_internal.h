@@ -72,6 +72,12 @@ int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch,
 int lindx_cgs2(const void* V, long long ld, int k, void* w, long long len, void* h, void* nrm, int reps,
                void* stream);
 
+/* out = L(X) for the context's Lindbladian with BF16x3 products on pre-split planes (the operator
+   of the inner shift-invert solves of lind_eigs in BF16x3 contexts); X, out: device n x n
+   complex128, may not alias.  The planes of G and the L_j are split on the first call (eigenbasis
+   route, d >= 1; LIND_EINVAL otherwise).  Synchronous. */
+int lindx_apply_bf16(lind_ctx* ctx, const void* X, void* out);
+
 /* dst = src (nbytes, a multiple of 16) with a plain vector copy kernel; used to calibrate the
    HBM byte counters of the profiler.  Asynchronous on stream. */
 int lindx_copy(void* dst, const void* src, long long nbytes, void* stream);

@@ -67,6 +67,14 @@ struct Ctx {
   P4 p4_VH, p4_VT, p4_Lt, p4_xiT, p4_C1, p4_XhT, p4_Y;
   float2* p4_ws = nullptr;
   int p4_nsplit = 1;
+  // BF16x3 Lindbladian (inner solves of lind_eigs, allocated on first use): the batched operands of
+  //   L(X) = sum_j Y_j L_j^H + G X + X G^H,  Y = [L_1; ..; L_d] X,
+  // A rows [Y_1 .. Y_d | G | X], B rows [L_1 .. L_d | conj(X^T) | G] (each block n rows, read with
+  // B conjugated), and X^T for the stacked product
+  bool p4L_ready = false;
+  P4 p4L_A, p4L_B, p4L_xT;
+  float2* p4L_ws = nullptr;
+  int p4L_nsplit = 1;
   zd* dsc = nullptr;      // device scalars
   double* dscr = nullptr; // reduction scratch
   long long dscr_len = 0;
@@ -126,6 +134,9 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian = false);
 int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in);
 // out = L*(X) (FP64)
 int op_apply_adj(Ctx& c, const zd* X, zd* out);
+// out = L(X) with BF16x3 products (FP32 accumulation, complex128 result); sets up its constant
+// operand planes on the first call (eigen route only: returns LIND_EINVAL when unavailable)
+int op_apply_p4(Ctx& c, const zd* X, zd* out);
 // norms of an n x n matrix to host: fro, max, colsum, max|Im diag|
 int op_norms(Ctx& c, const zd* X, double out[4]);
 int op_trace(Ctx& c, const zd* X, cplx* tr);
@@ -147,6 +158,8 @@ int gmres(Ctx& c, const std::function<int(const zd*, zd*)>& A, const std::functi
           double t_deadline);
 
 double now_s();
+// progress lines on stderr requested by the environment (LINDX_LOG)
+bool log_on();
 
 // device address of the fixed scratch array of lind_apply_noalloc on device dev (resolved once
 // per device; lind_create calls it with the device current)

@@ -140,10 +140,52 @@ extern "C" int lind_eigs(lind_ctx* ctx, int k, double mu_re, double mu_im, doubl
   // the outer one (the eigen-residual of a Ritz pair is about |lambda| times the inner residual)
   const double rtol_in = std::min(1e-8, std::max(1e-12, 0.1 * tol));
   c.rec.reset();
+  // reduced-precision contexts (eigen route): each solve is iterative refinement on the FP64
+  // residual, the corrections from recycled GMRES on the operator with BF16x3 products and the
+  // context's preconditioner, a consistent low-precision pair; the FP64 operator is applied once per
+  // refinement step instead of once per Krylov step
+  // The low-precision operator must be accurate on the scale of the shifted spectrum: a truncated
+  // Fock ladder with ||L|| ~ n^2 and wanted eigenvalues near 1e-3 is not (BF16x3 errors of
+  // ~1e-5 ||L|| exceed |mu - lambda|).  A first refinement step that does not halve the residual
+  // switches the call back to the FP64 operator in every Krylov step.
+  bool mixed = c.prec != PREC_F64 && c.route == LIND_ROUTE_EIG && c.d > 0;
+  std::function<int(const zd*, zd*)> Alow = [&](const zd* in, zd* out) -> int {
+    TRY(op_apply_p4(c, in, out));
+    TRY(axpby(zmk(mu.real(), mu.imag()), in, zmk(-1, 0), out, c.n2, c.st));
+    TRY(add_identity_trace(out, c.n, in, zmk(-eta, 0), c.dsc + 980, c.st));
+    return 0;
+  };
   auto OP = [&](const zd* b, zd* x) -> int {
     GmresResult gr;
-    TRY(gmres_rec(X, Aop, &Pop, b, x, true, kInnerM, kInnerK, 60, rtol_in, 0.0, c.rec, gr, deadline));
-    inf.n_inner += gr.iters;
+    if (!mixed) {
+      TRY(gmres_rec(X, Aop, &Pop, b, x, true, kInnerM, kInnerK, 60, rtol_in, 0.0, c.rec, gr, deadline));
+      inf.n_inner += gr.iters;
+      return 0;
+    }
+    double bn = 0;
+    TRY(op_nrm(c, b, &bn));
+    TRY(fill_zero(x, c.n2 * (long long)sizeof(zd), c.st));
+    TRY(copy(b, X->resB, c.n2, c.st));  // r = b - A x with x = 0
+    double rn = bn, prev = 1e300;
+    for (int it = 0; it < 8 && rn > rtol_in * bn; ++it) {
+      // correction to 1e-3 of the current residual (the BF16x3 operator is accurate to ~1e-5)
+      TRY(gmres_rec(X, Alow, &Pop, X->resB, X->delB, true, kInnerM, kInnerK, 60, 1e-3, 0.0, c.rec, gr, deadline));
+      inf.n_inner += gr.iters;
+      TRY(axpby(zmk(1, 0), X->delB, zmk(1, 0), x, c.n2, c.st));
+      TRY(Aop(x, X->resB));
+      TRY(axpby(zmk(1, 0), b, zmk(-1, 0), X->resB, c.n2, c.st));
+      TRY(op_nrm(c, X->resB, &rn));
+      if (it == 0 && !(rn <= 0.5 * bn)) {
+        // the low-precision operator is too coarse for this shift: FP64 operator from here on
+        mixed = false;
+        c.rec.reset();  // the recycle space belonged to the low-precision operator
+        TRY(gmres_rec(X, Aop, &Pop, b, x, true, kInnerM, kInnerK, 60, rtol_in, 0.0, c.rec, gr, deadline));
+        inf.n_inner += gr.iters;
+        return 0;
+      }
+      if (rn > 0.5 * prev) break;  // refinement no longer converging: keep the best so far
+      prev = rn;
+    }
     return 0;
   };
 
@@ -219,6 +261,9 @@ extern "C" int lind_eigs(lind_ctx* ctx, int k, double mu_re, double mu_im, doubl
       lam_out.push_back(lam);
       idx_out.push_back(i);
     }
+    if (log_on())
+      std::fprintf(stderr, "[lindx] eigs restart %d: %d of %d pairs converged, worst %.2e, %d inner steps, %.1f s\n",
+                   inf.n_restarts, nconv, k, worst, inf.n_inner, now_s() - t0);
     if (nconv == k) { converged = true; break; }
     if (deadline > 0 && now_s() > deadline) break;
     if (rs + 1 >= c.opts.max_restarts) break;

@@ -24,6 +24,7 @@
 // of Fock levels needs about as many Krylov steps as it has levels, and restarts lose them).  The
 // basis then lives in HBM (m + 3 vectors of n*n complex128).
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <numeric>
 #include "ctx.hpp"
@@ -348,6 +349,9 @@ int gmres_rec(lind_ctx* X, const std::function<int(const zd*, zd*)>& A, const st
     res.resid = est;
     prev_est_hit = est <= target;
     res.est_hit = prev_est_hit;
+    if (log_on() && m > 64)
+      std::fprintf(stderr, "[lindx] long GMRES cycle %d: %d steps, residual estimate %.2e of %.2e\n", cyc, jd, est,
+                   bnorm);
 
     // ---- recycle update: harmonic Ritz vectors over span(W^) ----
     // Without a preconditioner W^ and V^ live in one space and F = V^^H W^ is formed exactly.  In

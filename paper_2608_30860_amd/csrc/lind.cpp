@@ -3,6 +3,7 @@
 // FP64 iterative refinement).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <random>
 #include "ctx.hpp"
@@ -402,6 +403,15 @@ extern "C" int lind_apply(lind_ctx* ctx, const void* rho, void* out) {
   return c.sync();
 }
 
+// out = L(X) with BF16x3 products (include/lind_internal.h; the operator of the inner solves of
+// lind_eigs in BF16x3 contexts)
+extern "C" int lindx_apply_bf16(lind_ctx* ctx, const void* X, void* out) {
+  if (!ctx || !X || !out || X == out) return LIND_EINVAL;
+  Ctx& c = ctx->c;
+  TRY(op_apply_p4(c, (const zd*)X, (zd*)out));
+  return c.sync();
+}
+
 extern "C" int lind_apply_adjoint(lind_ctx* ctx, const void* X, void* out) {
   if (!ctx || !X || !out || X == out) return LIND_EINVAL;
   Ctx& c = ctx->c;
@@ -646,6 +656,9 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
       cplx trb;
       TRY(finish_state(X, X->rhoB, &colsum, &mx, &fro, &trb));
       ++inf.n_restarts;
+      if (log_on())
+        std::fprintf(stderr, "[lindx] steady state restart %d: residual bound %.3e after %d Phi\n", inf.n_restarts,
+                     colsum, inf.n_phi);
       double xn = 0;
       TRY(op_nrm(c, X->xiB, &xn));
       if (std::abs(trb) > 0) c_scale = std::sqrt((double)n) * xn / std::abs(trb);

@@ -4,12 +4,22 @@
 // problem on the host.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include "ctx.hpp"
 
 namespace lindx {
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// progress lines on stderr when the environment sets LINDX_LOG (to a value other than 0)
+bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("LINDX_LOG");
+    return v && v[0] && !(v[0] == '0' && v[1] == 0);
+  }();
+  return on;
 }
 
 Ctx::~Ctx() {
@@ -331,6 +341,66 @@ int op_apply(Ctx& c, const zd* rho, zd* out, bool hermitian_in) {
     g.C = out; g.ldc = n; g.beta = 1;
     TRY(gemm(PREC_F64, g, c.st));
   }
+  return 0;
+}
+
+// BF16x3 Lindbladian.  One stacked product Y = [L_1; ..; L_d] X (planes out), then one batched
+// reduction over d + 2 pairs with split-K partials:
+//   sum_{j<d} Y_j L_j^H  +  G (conj(X^T))^H  +  X G^H  =  L(X)   (eq. lindblad_decomposition)
+// The constant planes (L_j, G in both operand arrays) are split once; X is split three ways per call.
+static P4 p4_rows_view(const P4& P, long long row0) {
+  P4 v = P;
+  v.p = P.p + row0 * P.ld;
+  v.rows = P.rows - row0;
+  return v;
+}
+static int setup_p4L(Ctx& c) {
+  const int n = c.n, d = c.d;
+  const long long rows = (long long)(d + 2) * n;
+  for (P4* b : {&c.p4L_A, &c.p4L_B}) {
+    if (p4_alloc(*b, rows, n)) return c.fail(LIND_ENOMEM, "out of device memory (bf16 Lindbladian planes)");
+    c.allocs.push_back(b->p);
+  }
+  if (p4_alloc(c.p4L_xT, n, n)) return c.fail(LIND_ENOMEM, "out of device memory (bf16 Lindbladian planes)");
+  c.allocs.push_back(c.p4L_xT.p);
+  // the Lindbladian is the same for every gauge: the (possibly shifted) pair the context holds
+  for (int j = 0; j < d; ++j)
+    if (p4_split(c.L + (long long)j * c.n2, 1, n, n, n, 0, 0, p4_rows_view(c.p4L_B, (long long)j * n), c.st))
+      return LIND_EDEVICE;
+  if (p4_split(c.G, 1, n, n, n, 0, 0, p4_rows_view(c.p4L_B, (long long)(d + 1) * n), c.st)) return LIND_EDEVICE;
+  if (p4_split(c.G, 1, n, n, n, 0, 0, p4_rows_view(c.p4L_A, (long long)d * n), c.st)) return LIND_EDEVICE;
+  // split-K over the d + 2 pairs: the largest divisor of d + 2 that keeps the grid within 4 waves
+  // of 256 workgroups
+  const long long tm = (n + 127) / 128;
+  int s = 1;
+  for (int q = 2; q <= d + 2; ++q)
+    if ((d + 2) % q == 0 && tm * tm * q <= 1024) s = q;
+  c.p4L_nsplit = s;
+  if (c.alloc(&c.p4L_ws, (size_t)s * c.n2)) return c.fail(LIND_ENOMEM, "out of device memory (split-K)");
+  c.p4L_ready = true;
+  return 0;
+}
+
+int op_apply_p4(Ctx& c, const zd* X, zd* out) {
+  const int n = c.n, d = c.d;
+  if (c.route != LIND_ROUTE_EIG || d < 1) return LIND_EINVAL;
+  if (!c.p4L_ready) TRY(setup_p4L(c));
+  TRY(p4_split(X, 1, n, n, n, 0, 0, p4_rows_view(c.p4L_A, (long long)(d + 1) * n), c.st));  // X
+  TRY(p4_split(X, 1, n, n, n, 1, 1, p4_rows_view(c.p4L_B, (long long)d * n), c.st));        // conj(X^T)
+  TRY(p4_split(X, 1, n, n, n, 1, 0, c.p4L_xT, c.st));                                        // X^T
+  P4Desc y;
+  y.M = d * n; y.N = n; y.K = n;
+  y.A = c.p4L_B.p; y.lda = c.p4L_B.ld; y.pA = c.p4L_B.pstride;
+  y.B = c.p4L_xT.p; y.ldb = c.p4L_xT.ld; y.pB = c.p4L_xT.pstride;
+  y.out = P4OUT_PLANES; y.C = c.p4L_A.p; y.ldc = c.p4L_A.ld; y.pC = c.p4L_A.pstride;
+  TRY(p4_gemm(y, c.st));
+  P4Desc r;
+  r.M = n; r.N = n; r.K = n; r.nbatch = d + 2; r.nsplit = c.p4L_nsplit;
+  r.A = c.p4L_A.p; r.lda = c.p4L_A.ld; r.pA = c.p4L_A.pstride; r.sA = (long long)n * c.p4L_A.ld;
+  r.B = c.p4L_B.p; r.ldb = c.p4L_B.ld; r.pB = c.p4L_B.pstride; r.sB = (long long)n * c.p4L_B.ld;
+  r.conjB = 1;
+  r.out = P4OUT_WS; r.ws = c.p4L_ws; r.out64 = out; r.ldo = n; r.alpha = 1.0;
+  TRY(p4_gemm(r, c.st));
   return 0;
 }
 

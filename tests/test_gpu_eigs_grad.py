@@ -33,12 +33,15 @@ def match_multiset(got, ref, tol):
         got.pop(j)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 @pytest.mark.parametrize("n,d,seed", [(7, 3, 2), (10, 2, 4)])
-def test_eigs_random_vs_dense(n, d, seed):
-    print(f"[case] eigs random n={n} d={d}", flush=True)
+def test_eigs_random_vs_dense(n, d, seed, prec):
+    """Shift-invert spectrum against dense eig; in BF16x3 the inner solves are refinement on the
+    FP64 residual with BF16x3 products (the returned pairs are still FP64-accurate)."""
+    print(f"[case] eigs random n={n} d={d} {prec}", flush=True)
     H, Ls = li.random_dense(n, d, seed)
     k = 4
-    m = make(H, Ls, m=24)
+    m = make(H, Ls, m=24, prec=prec)
     vals, vecs, info = m.eigs(k, tol=1e-10, vectors=True)
     print("eigs", vals, info)
     ref = ol.low_spectrum_dense(H, Ls, k + 2)

@@ -271,3 +271,26 @@ def test_cgs2_step(k, length, pad):
     assert np.max(np.abs(h[k:] - h2)) <= 1e-13 * scale
     assert np.max(np.abs(w_d.cpu().numpy() - w2)) <= 1e-13 * scale
     assert abs(float(nrm_d.cpu()[0]) - np.linalg.norm(w2)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,d", [(200, 3), (256, 2), (1024, 4)])
+def test_lindbladian_bf16x3(n, d):
+    """L(X) with BF16x3 products (one stacked product, one batched reduction that also carries
+    G X and X G^H) against the oracle's term-by-term FP64 L on a random non-Hermitian X, to the
+    accuracy of the two-term BF16 split with FP32 accumulation (relative to the largest entry)."""
+    import lind_inputs as li
+    from oracle import lindblad as ol
+    from paper_2608_30860_amd import Lindblad
+    H, Ls = li.random_dense(n, d, 4)
+    m = Lindblad(T(H), T(np.stack(Ls)), prec="bf16x3", route="eig")
+    X = li.random_state(n, seed=9, hermitian=False)
+    out = torch.empty((n, n), dtype=torch.complex128, device="cuda:0")
+    L = lib()
+    L.lindx_apply_bf16.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    Xd = T(X)
+    assert L.lindx_apply_bf16(m.h, P(Xd), P(out)) == 0
+    ref = ol.lindblad_apply(H, Ls, X)
+    err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    print("bf16x3 L rel err", err)
+    assert err < 1e-4
+    m.close()
