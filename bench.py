@@ -76,6 +76,25 @@ def cpu_baseline(n, d, seed, budget_s=25.0):
             "eig_s": t_eig, "phi_s": t / cnt}
 
 
+def cpu_alg4(n, d, seed, tol):
+    """The oracle's own Algorithm "Steady state as the fixed point of Phi" (restarted Arnoldi on Phi
+    with the eigendecomposition no-jump resolvent, NumPy FP64) to ||L rho||_1 <= tol on the host:
+    its time-to-tolerance, including its eigendecomposition of G (about two minutes at n = 2048)."""
+    from threadpoolctl import threadpool_info
+
+    import lind_inputs as li
+    from oracle import krylov as ok
+
+    H, Ls = li.random_dense(n, d, seed)
+    t0 = time.perf_counter()
+    rho, info = ok.steady_state_phi(H, Ls, tol=tol, return_info=True)
+    t = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"time_to_tol_s": t, "tol": tol, "norm": "trace", "cores": threads, "resid_trace": info["resid"],
+            "n_phi": info["n_phi"], "restarts": info["restarts"], "kind": "oracle",
+            "sample": f"one full solve at n={n}, d={d}, seed={seed} (includes eig(G) and the condition estimate)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +107,9 @@ def main():
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-alg4", action="store_true",
+                    help="also time the oracle's own Algorithm 4 to the tolerance on the host (about two minutes "
+                         "at n = 2048 on 16 threads)")
     ap.add_argument("--no-extras", action="store_true", help="skip the resolvent / implicit Euler measurement")
     ap.add_argument("--no-configs", action="store_true", help="skip the Phi rates of the other workloads")
     ap.add_argument("--phi-loop", type=int, default=10, help="Phi applications per precision in the pure loop")
@@ -508,6 +530,8 @@ def main():
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         cpu = cpu_baseline(n, d, args.seed)
+        if args.cpu_alg4:
+            cpu["alg4"] = cpu_alg4(n, d, args.seed, args.tol)
         log(f"[bench] cpu {cpu}")
 
     out = {"metric": METRIC, "value": value, "unit": "Phi-apps/s", "n_gpus": 1, "steps": args.steps,
