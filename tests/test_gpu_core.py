@@ -103,8 +103,13 @@ def test_sinv_matches_lyapunov(kind, n, d, mu):
 
 
 @pytest.mark.parametrize("kind,n,d", CASES)
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 3e-5), ("bf16x3", 3e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 3e-5), ("bf16x3", 3e-4)])
 def test_phi_matches_oracle(kind, n, d, prec, tol):
+    """Phi against the oracle's -K(S^{-1} xi), relative to the largest entry.  Tolerances from the
+    arithmetic: FP64 rounding through four products (1e-11); FP32 (2^-24 per operation, K up to 200
+    terms and the basis change with kappa_2(U) up to ~40 here: 3e-5); BF16x3 (each operand held to
+    ~2^-17 by the two-term split, the dropped lo*lo term ~2^-16 of each product, FP32 accumulation,
+    four chained products and the divide: ~1e-4; measured 1.2e-5 to 8.4e-5 on these cases: 3e-4)."""
     print(f"[case] phi {kind} n={n} d={d} {prec}", flush=True)
     H, Ls = system(kind, n, d)
     m = make(H, Ls, prec=prec)
