@@ -45,6 +45,11 @@ __device__ inline v4f_p mfma16(v8bf_p a, v8bf_p b, v4f_p c) {
 // against the unswizzled and other XOR placements, which all conflict).
 __device__ inline int slot_of(int r, int q) { return q ^ ((r >> 1) & 3); }
 
+// s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8) that
+// wait until at most 4 (0) LDS operations are outstanding and leave the other counters alone
+constexpr int kLgkm4 = 0xC000 | 0x000F | 0x0070 | (4 << 8);
+constexpr int kLgkm0 = 0xC000 | 0x000F | 0x0070;
+
 // XCD-aware tile order: consecutive workgroup ids go to different XCDs (round robin over 8), so
 // ids congruent mod 8 get a contiguous run of tiles.  When that run is whole tile rows, it is
 // walked in column-major groups of 4 tile rows: the 32 workgroups an XCD runs at once then cover
@@ -147,59 +152,113 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
     }
 
   const int kq = lane >> 4;
-  // operand fragments of one stage: A rows wm0 + 16 i, B rows wn0 + 16 j, all four planes
-  auto frags = [&](int buf, v8bf_p (&a)[4][4], v8bf_p (&bb)[TNW][4]) {
+  // operand fragments: A rows wm0 + 16 i (one 16-row block, all four planes), B rows wn0 + 16 j
+  auto readA = [&](int buf, int i, v8bf_p (&ai)[4]) {
+    const int r = wm0 + i * 16 + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = wm0 + i * 16 + (lane & 15);
-#pragma unroll
-      for (int p = 0; p < 4; ++p) a[i][p] = *(const v8bf_p*)&S[buf][0][p][r][slot_of(r, kq) * 8];
-      if (CONJ_A) { a[i][2] = neg8(a[i][2]); a[i][3] = neg8(a[i][3]); }
-    }
+    for (int p = 0; p < 4; ++p) ai[p] = *(const v8bf_p*)&S[buf][0][p][r][slot_of(r, kq) * 8];
+  };
+  auto readB = [&](int buf, v8bf_p (&bb)[TNW][4]) {
 #pragma unroll
     for (int j = 0; j < TNW; ++j) {
       const int r = wn0 + j * 16 + (lane & 15);
 #pragma unroll
       for (int p = 0; p < 4; ++p) bb[j][p] = *(const v8bf_p*)&S[buf][1][p][r][slot_of(r, kq) * 8];
-      if (CONJ_B) { bb[j][2] = neg8(bb[j][2]); bb[j][3] = neg8(bb[j][3]); }
     }
   };
-  // re += Ar Br - Ai Bi, im += Ar Bi + Ai Br; each group issues 4 TNW independent MFMAs.
-  // SWAP computes the transposed tile (B fragment as the MFMA row operand), so that a lane's
-  // four accumulator entries run along n instead of m.
-  auto compute = [&](v8bf_p (&a)[4][4], v8bf_p (&bb)[TNW][4]) {
-#define P4_GROUP(ACC, AF, BP)                                                          \
-  _Pragma("unroll") for (int i = 0; i < 4; ++i)                                        \
-    _Pragma("unroll") for (int j = 0; j < TNW; ++j) ACC[i][j] =                        \
-        SWAP ? mfma16(bb[j][BP], AF, ACC[i][j]) : mfma16(AF, bb[j][BP], ACC[i][j]);
-    P4_GROUP(cr, a[i][0], 0)
-    P4_GROUP(ci, a[i][0], 2)
-    P4_GROUP(cr, a[i][0], 1)
-    P4_GROUP(ci, a[i][0], 3)
-    P4_GROUP(cr, a[i][1], 0)
-    P4_GROUP(ci, a[i][1], 2)
-    P4_GROUP(ci, a[i][2], 0)
-    P4_GROUP(ci, a[i][2], 1)
-    P4_GROUP(ci, a[i][3], 0)
-    // the fragments die with this stage: negate Ai in place for the real part
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { a[i][2] = neg8(a[i][2]); a[i][3] = neg8(a[i][3]); }
-    P4_GROUP(cr, a[i][2], 2)
-    P4_GROUP(cr, a[i][2], 3)
-    P4_GROUP(cr, a[i][3], 2)
+  // row block i of the wave tile, 12 TNW MFMAs: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br.  The
+  // conjugations change signs only: with conj(A) re += Ar Br + Ai Bi, im += Ar Bi - Ai Br; with
+  // conj(B) the same pattern gives -im; with both, the plain pattern gives -im.  So the Ai planes
+  // go with the plain signs into one accumulator and, negated in place (the fragment dies with
+  // the block), into the other (XA picks which), and conj(B) negates im in the epilogue: no
+  // operand is negated when it is read.  SWAP computes the transposed tile (B fragment as the MFMA
+  // row operand), so that a lane's four accumulator entries run along n instead of m.
+  constexpr bool XA = CONJ_A != CONJ_B;
+  auto block = [&](int i, v8bf_p (&ai)[4], v8bf_p (&bb)[TNW][4]) {
+#define P4_GROUP(ACC, AP, BP)                                                                  \
+  _Pragma("unroll") for (int j = 0; j < TNW; ++j) ACC[i][j] =                                  \
+      SWAP ? mfma16(bb[j][BP], ai[AP], ACC[i][j]) : mfma16(ai[AP], bb[j][BP], ACC[i][j]);
+    P4_GROUP(cr, 0, 0)
+    P4_GROUP(ci, 0, 2)
+    P4_GROUP(cr, 0, 1)
+    P4_GROUP(ci, 0, 3)
+    P4_GROUP(cr, 1, 0)
+    P4_GROUP(ci, 1, 2)
+    if (XA) {
+      P4_GROUP(cr, 2, 2)
+      P4_GROUP(cr, 2, 3)
+      P4_GROUP(cr, 3, 2)
+    } else {
+      P4_GROUP(ci, 2, 0)
+      P4_GROUP(ci, 2, 1)
+      P4_GROUP(ci, 3, 0)
+    }
+    ai[2] = neg8(ai[2]);
+    ai[3] = neg8(ai[3]);
+    if (XA) {
+      P4_GROUP(ci, 2, 0)
+      P4_GROUP(ci, 2, 1)
+      P4_GROUP(ci, 3, 0)
+    } else {
+      P4_GROUP(cr, 2, 2)
+      P4_GROUP(cr, 2, 3)
+      P4_GROUP(cr, 3, 2)
+    }
 #undef P4_GROUP
   };
-  if (total > 0) issue(0, 0);
-  for (int it = 0; it < total; ++it) {
-    const int buf = it & 1;
-    // the loads of this stage have landed (the barrier waits for every outstanding load), and
-    // every wave is done with the other buffer, which the next stage may now overwrite
+  // One stage s, with its B fragments and A blocks 0-2 already in registers.  The only barrier
+  // comes after row block 0: by then every wave has read all of stage s (block 3 is read first)
+  // and the DMA of stage s + 1 has landed, so stage s + 2 goes into this stage's buffer and the
+  // fragments of stage s + 1 are read while blocks 1-3 keep the matrix cores busy.  All 24
+  // fragment reads of a stage thus overlap MFMA work instead of stalling every wave at once.
+  // The scheduling fences keep each read group where it stands: left alone, the compiler sinks the
+  // reads next to their first use and waits for them there.
+  auto step = [&](int s, v8bf_p (&A)[4][4], v8bf_p (&Bc)[TNW][4], v8bf_p (&An)[4][4], v8bf_p (&Bn)[TNW][4]) {
+    const int buf = s & 1, nbuf = buf ^ 1;
+    readA(buf, 3, A[3]);
+    __builtin_amdgcn_sched_barrier(0);
+    block(0, A[0], Bc);
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    // fragment reads first, so the LDS works while the wave issues the next stage's DMA
-    v8bf_p a[4][4], bb[TNW][4];
-    frags(buf, a, bb);
-    if (it + 1 < total) issue(it + 1, buf ^ 1);
-    compute(a, bb);
+    if (s + 2 < total) issue(s + 2, buf);
+    // on the last stage these read a buffer no DMA wrote: the values are never used
+    readB(nbuf, Bn);
+    readA(nbuf, 0, An[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    block(1, A[1], Bc);
+    __builtin_amdgcn_sched_barrier(0);
+    readA(nbuf, 1, An[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    block(2, A[2], Bc);
+    __builtin_amdgcn_sched_barrier(0);
+    // the 12 reads issued after the barrier have had two blocks to land.  Waiting for them here
+    // (at most the 4 of block 1 still pending) keeps the LDS counter below its 4-bit limit: with
+    // more reads in flight the compiler can only wait for all of them before the next block.
+    __builtin_amdgcn_s_waitcnt(kLgkm4);
+    readA(nbuf, 2, An[2]);
+    __builtin_amdgcn_sched_barrier(0);
+    block(3, A[3], Bc);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  if (total > 0) {
+    v8bf_p A0[4][4], A1[4][4], B0[TNW][4], B1[TNW][4];
+    issue(0, 0);
+    __syncthreads();
+    if (total > 1) issue(1, 1);
+    readB(0, B0);
+    readA(0, 0, A0[0]);
+    readA(0, 1, A0[1]);
+    readA(0, 2, A0[2]);
+    // nothing pending on entry to the loop, so that its first block waits for no more than the
+    // loop's own back edge requires
+    __builtin_amdgcn_s_waitcnt(kLgkm0);
+    // unrolled by two so that the register sets alternate without copies
+    int s = 0;
+    for (; s + 1 < total; s += 2) {
+      step(s, A0, B0, A1, B1);
+      step(s + 1, A1, B1, A0, B0);
+    }
+    if (s < total) step(s, A0, B0, A1, B1);
   }
 
   // epilogue.  Normal: lane holds rows m = ..+4*(lane>>4)+r at column n = ..+(lane&15).
@@ -220,7 +279,7 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
         nn[r] = SWAP ? n_l + r : n_l;
         ok[r] = mm[r] < g.M && nn[r] < g.N;
         re[r] = cr[i][j][r];
-        im[r] = ci[i][j][r];
+        im[r] = CONJ_B ? -ci[i][j][r] : ci[i][j][r];
       }
       if (OUT == P4OUT_WS) {
 #pragma unroll
