@@ -48,6 +48,8 @@ struct P4 {
 };
 enum { P4OUT_PLANES = 0, P4OUT_PLANES_T = 1, P4OUT_WS = 2 };
 struct P4Desc {
+  // P4OUT_WS: the nbatch * ceil(K / 32) (batch, k-chunk) steps of each output tile are cut into
+  // nsplit contiguous, nearly equal runs (1 <= nsplit <= that count), one workgroup per run
   int M = 0, N = 0, K = 0, nbatch = 1, nsplit = 1;
   // op(A) row m, k at A[pl * pA + b * sA + m * lda + k]; op(B) column n, k at B[pl * pB + b * sB + n * ldb + k]
   const __bf16* A = nullptr; long long lda = 0, pA = 0, sA = 0;
@@ -70,6 +72,11 @@ int p4_alloc(P4& p, long long rows, long long k);
 int p4_split(const void* X, int is64, long long ldx, int rows, int cols, int trans, int conj, const P4& out,
              hipStream_t st);
 int p4_gemm(const P4Desc& g, hipStream_t st);
+// split-K count for a P4OUT_WS product of `tiles` output tiles and nbatch * k_len reduction
+// length, on a device with `cus` compute units (one workgroup per unit at a time)
+int p4_pick_split(long long tiles, int nbatch, int k_len, int cus);
+// compute units of device dev (256 on MI355X if the query fails: only a tuning input)
+int device_cus(int dev);
 // complex128 X (rows x cols) from planes, reading P[r][c] (or P[c][r] when trans)
 int p4_join(const P4& P, int rows, int cols, int trans, zd* X, long long ldx, hipStream_t st);
 

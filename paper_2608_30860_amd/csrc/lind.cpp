@@ -34,12 +34,10 @@ static int setup_p4(Ctx& c) {
   if (p4_split(c.V, 1, n, n, n, 1, 1, c.p4_VH, c.st)) return LIND_EDEVICE;
   if (p4_split(c.V, 1, n, n, n, 1, 0, c.p4_VT, c.st)) return LIND_EDEVICE;
   if (p4_split(c.Lt, 1, n, d * n, n, 0, 0, c.p4_Lt, c.st)) return LIND_EDEVICE;
-  // split-K over the d jump operators: enough workgroups to cover the chip four times
-  // (the Hermitian reduction of the steady-state iteration runs on the upper half of the tiles)
+  // split-K of the jump reduction (d n-long products summed; only the tiles on and above the
+  // diagonal of its Hermitian result are computed) in runs that fill whole rounds of the chip
   const long long tm = (n + 127) / 128;
-  const long long tiles = tm * (tm + 1) / 2;
-  int s = 1;
-  while (s * 2 <= d && d % (s * 2) == 0 && tiles * s < 1024) s *= 2;
+  const int s = p4_pick_split(tm * (tm + 1) / 2, d, n, device_cus(c.dev));
   c.p4_nsplit = s;
   if (!c.p4_ws && c.alloc(&c.p4_ws, (size_t)s * c.n2)) return c.fail(LIND_ENOMEM, "out of device memory (split-K)");
   c.p4_ready = true;

@@ -369,12 +369,9 @@ static int setup_p4L(Ctx& c) {
       return LIND_EDEVICE;
   if (p4_split(c.G, 1, n, n, n, 0, 0, p4_rows_view(c.p4L_B, (long long)(d + 1) * n), c.st)) return LIND_EDEVICE;
   if (p4_split(c.G, 1, n, n, n, 0, 0, p4_rows_view(c.p4L_A, (long long)d * n), c.st)) return LIND_EDEVICE;
-  // split-K over the d + 2 pairs: the largest divisor of d + 2 that keeps the grid within 4 waves
-  // of 256 workgroups
+  // split-K over the d + 2 products summed, in runs that fill whole rounds of the chip
   const long long tm = (n + 127) / 128;
-  int s = 1;
-  for (int q = 2; q <= d + 2; ++q)
-    if ((d + 2) % q == 0 && tm * tm * q <= 1024) s = q;
+  const int s = p4_pick_split(tm * tm, d + 2, n, device_cus(c.dev));
   c.p4L_nsplit = s;
   if (c.alloc(&c.p4L_ws, (size_t)s * c.n2)) return c.fail(LIND_ENOMEM, "out of device memory (split-K)");
   c.p4L_ready = true;

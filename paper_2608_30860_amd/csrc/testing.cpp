@@ -113,7 +113,10 @@ extern "C" int lindx_p4_test(const void* A, const void* B, int M, int N, int K, 
   float2* ws = nullptr;
   int nsplit = 1;
   if (!rc && out_mode == 2) {
-    while (nsplit * 2 <= nbatch && nbatch % (nsplit * 2) == 0) nsplit *= 2;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) rc = -4;
+    const long long tm = (M + 127) / 128, tn = (N + 127) / 128;
+    nsplit = p4_pick_split(tri ? tm * (tm + 1) / 2 : tm * tn, nbatch, K, device_cus(dev));
     if (hipMalloc((void**)&ws, sizeof(float2) * (size_t)nsplit * M * N) != hipSuccess) rc = -5;
   }
   const zd* Ad = (const zd*)A;

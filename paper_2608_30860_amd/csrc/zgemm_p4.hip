@@ -112,9 +112,10 @@ __global__ __launch_bounds__(64 * NW) void k_p4_gemm(P4Desc g) {
   else tile_xcd(blockIdx.x - split * tiles, tm, tn, bm, bn);
   const int m0 = bm * TB, n0 = bn * TB;
   const int ktiles = (g.K + KS - 1) / KS;
-  const int bps = g.nbatch / g.nsplit;
-  const int it_begin = split * bps * ktiles;
-  const int total = bps * ktiles;
+  // this workgroup's run of the (batch, k-chunk) steps
+  const long long nit = (long long)g.nbatch * ktiles;
+  const int it_begin = (int)(split * nit / g.nsplit);
+  const int total = (int)((split + 1) * nit / g.nsplit) - it_begin;
 
   // stage loader: 64 wave-loads of 1 KB (operand, plane, 16-row group), LPW per wave: the first
   // half of the waves stage A, the second half B.  Lane l of a wave-load writes LDS
@@ -523,10 +524,37 @@ int p4_join(const P4& P, int rows, int cols, int trans, zd* X, long long ldx, hi
 
 long long p4_ws_elems(int M, int N, int nsplit) { return (long long)nsplit * M * N; }
 
+int device_cus(int dev) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  return cus;
+}
+
+// One workgroup per compute unit at a time (the double-buffered stages take 128 KB of LDS), so a
+// grid of B workgroups runs in ceil(B / cus) rounds, each as long as the longest run of k-chunk
+// steps.  Each split also writes, and the reduction reads, one more FP32 partial per tile (256 KB):
+// at the few TB/s those passes reach, about a 64th of a k-chunk step's time per tile, the weight
+// it gets below.  Smallest modelled time; ties go to fewer splits.
+int p4_pick_split(long long tiles, int nbatch, int k_len, int cus) {
+  const long long nit = (long long)nbatch * ((k_len + KS - 1) / KS);
+  if (tiles < 1 || nit < 1 || cus < 1) return 1;
+  long long best = -1;
+  int best_s = 1;
+  for (long long s = 1; s <= nit && s <= 64; ++s) {
+    const long long rounds = (tiles * s + cus - 1) / cus;
+    const long long steps = (nit + s - 1) / s;
+    const long long cost = 64 * rounds * steps + s * tiles;
+    if (best < 0 || cost < best) { best = cost; best_s = (int)s; }
+  }
+  return best_s;
+}
+
 int p4_gemm(const P4Desc& g0, hipStream_t st) {
   P4Desc g = g0;
   if (g.M <= 0 || g.N <= 0) return 0;
-  if (g.K <= 0 || g.nbatch <= 0 || g.nsplit <= 0 || g.nbatch % g.nsplit) return -1;
+  if (g.K <= 0 || g.nbatch <= 0 || g.nsplit <= 0) return -1;
+  if ((long long)g.nsplit > (long long)g.nbatch * ((g.K + KS - 1) / KS)) return -1;
+  if (g.nsplit > 1 && g.out != P4OUT_WS) return -1;
   // every stage reads whole 128-row tiles and 32-wide k chunks: the planes must hold them
   const long long kpad = p4_ld(g.K);
   if (g.lda < kpad || g.ldb < kpad) return -1;
