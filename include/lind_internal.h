@@ -41,6 +41,16 @@ int lindx_triinv(const void* Y, void* Yinv, int n, void* stream);
 /* T X + X T^H + shift X = C in place (X holds C on entry), T upper triangular */
 int lindx_trisylv(const void* T, void* X, int n, double shift_re, double shift_im, void* stream);
 
+/* The same solve (synchronous) as the low-precision maps of the Schur route run it: the 32 x 32
+   diagonal blocks of T are diagonalised by their unit upper triangular eigenvector matrices Y_I,
+   and a block pair (I, J) with kappa_inf(Y_I) and kappa_inf(Y_J) both <= thr is solved as
+   Y_I [(Y_I^{-1} C Y_J^{-H}) / (t_a + conj t_b + shift)] Y_J^H, the others by the sweep.
+   kap: host array of ceil(n / 32) doubles receiving the condition numbers (may be NULL;
+   infinite where two diagonal entries of a block coincide).  0, -1 on bad arguments, -5 when a
+   workspace cannot be allocated, -4 on a device error. */
+int lindx_trisylv_blk(const void* T, void* X, int n, double shift_re, double shift_im, double thr, double* kap,
+                      void* stream);
+
 /* Event timing of the kernels inside a context, recorded on the context's stream.
    lindx_profile(ctx, 1) resets the counters and starts recording, (ctx, 0) stops.
    lindx_profile_read returns the number of timed launches and their summed duration for a kind:

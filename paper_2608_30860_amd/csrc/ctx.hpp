@@ -15,7 +15,11 @@ typedef std::complex<double> cplx;
 enum { PROF_JUMP_STACK = 0, PROF_JUMP_REDUCE = 1, PROF_BASIS_IN = 2, PROF_PHI = 3, PROF_RESID = 4, PROF_CGS = 5 };
 
 struct Ctx;
-constexpr int kMaxLong = 6144;  // longest GMRES cycle (basis vectors kept in HBM)
+constexpr int kMaxLong = 6144;
+// Largest condition number (infinity norm) of a diagonal block's eigenvector matrix for which the
+// low-precision maps solve a block pair through block eigenbases: the FP64 rounding error of that
+// solve grows like kappa_I kappa_J u <= 1e8 * 1.1e-16, two orders below FP32 rounding.
+constexpr double kBlkKappaMax = 1e4;  // longest GMRES cycle (basis vectors kept in HBM)
 constexpr int kHostScalars = 2 * kMaxLong + 4096;  // complex128 slots of the pinned host buffer
 // recycled subspace of the GCRO-DR solver: (A P) U = C with orthonormal C, k vectors of n*n
 struct Recycle {
@@ -56,6 +60,8 @@ struct Ctx {
   std::vector<cplx> s_host;
   // low-precision operands (complex64)
   zf *U32 = nullptr, *V32 = nullptr, *Z32 = nullptr, *Lt32 = nullptr;
+  // Schur route, low-precision modes: eigenbases of the diagonal blocks of T and of T_adj
+  TsBlk tsb, tsb_adj;
   // work
   zd *w1 = nullptr, *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *Ys = nullptr;
   zf *a32 = nullptr, *b32 = nullptr, *Y32 = nullptr;

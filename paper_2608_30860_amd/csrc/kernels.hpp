@@ -158,7 +158,18 @@ int small_eig(const zd* A, int lda, int m, zd* w, zd* Y, int* info, hipStream_t 
 // ---------------------------------------------------------------------------
 // T X + X T^H + shift X = C (T upper triangular, X overwrites C); ws holds trisylv_ws_elems(n)
 // complex entries of scratch
-int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st);
+// Block eigenbases of T's 32 x 32 diagonal blocks (trisylv_blk_setup): Y, Y^{-1} (each
+// trisylv_blk_elems(n) entries, block after block) and kap (one per block).  A block pair whose
+// two condition numbers are <= thr is solved through them; null kap: every pair is swept.
+struct TsBlk {
+  const zd* Y = nullptr;
+  const zd* Yi = nullptr;
+  const double* kap = nullptr;
+  double thr = 0.0;
+};
+int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st, const TsBlk* blk = nullptr);
 long long trisylv_ws_elems(int n);
+long long trisylv_blk_elems(int n);
+int trisylv_blk_setup(const zd* T, int n, zd* Y, zd* Yi, double* kap, hipStream_t st);
 
 }  // namespace lindx

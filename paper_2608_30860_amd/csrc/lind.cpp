@@ -216,6 +216,19 @@ static int ctx_factor(lind_ctx* X) {
   const zd* B = (route == LIND_ROUTE_EIG) ? c.U : c.Z;
   if (d > 0) TRY(op_gemm(c, PREC_F64, d * n, n, n, c.L, n, OP_N, B, n, OP_N, c.Lt, n, one, 0));
   if (route == LIND_ROUTE_SCHUR) TRY(flip_conj_transpose(c.T, c.Tadj, n, c.st));
+  if (route == LIND_ROUTE_SCHUR && c.prec != PREC_F64 && !c.tsb.kap) {
+    // the low-precision maps solve well-conditioned diagonal block pairs through block eigenbases
+    const long long be = trisylv_blk_elems(n), nbk = (n + 31) / 32;
+    zd *y, *yi, *ya, *yia;
+    double *k, *ka;
+    if (c.alloc(&y, be) || c.alloc(&yi, be) || c.alloc(&ya, be) || c.alloc(&yia, be) ||
+        c.alloc(&k, nbk) || c.alloc(&ka, nbk))
+      return c.fail(LIND_ENOMEM, "out of device memory (block eigenbases)");
+    TRY(trisylv_blk_setup(c.T, n, y, yi, k, c.st));
+    TRY(trisylv_blk_setup(c.Tadj, n, ya, yia, ka, c.st));
+    c.tsb.Y = y; c.tsb.Yi = yi; c.tsb.kap = k; c.tsb.thr = kBlkKappaMax;
+    c.tsb_adj.Y = ya; c.tsb_adj.Yi = yia; c.tsb_adj.kap = ka; c.tsb_adj.thr = kBlkKappaMax;
+  }
   if (c.prec != PREC_F64) {
     TRY(to_c64(c.U, c.U32, n2, c.st));
     TRY(to_c64(c.V, c.V32, n2, c.st));

@@ -105,6 +105,16 @@ int op_gemm(Ctx& c, int prec, int M, int N, int K, const void* A, long long lda,
     if (rc__) return rc__ < 0 ? rc__ : LIND_EDEVICE; \
   } while (0)
 
+// C (complex128, n x n) = A op(B) with complex64 operands in the working precision
+static int basis_to64(Ctx& c, int prec, const zf* A, int opA, const zf* B, int opB, zd* C) {
+  GemmDesc g;
+  g.M = c.n; g.N = c.n; g.K = c.n;
+  g.A = A; g.lda = c.n; g.opA = opA;
+  g.B = B; g.ldb = c.n; g.opB = opB;
+  g.C = C; g.ldc = c.n; g.out64 = 1;
+  return gemm(prec, g, c.st) ? LIND_EDEVICE : 0;
+}
+
 // ---------------------------------------------------------------------------------------------
 // (S - mu)^{-1}.  Eigenbasis route (eq. lyapu_eig_solution):
 //   X = U [ (V^H Y V)_ij / (s_i + conj(s_j) - mu) ] U^H            (V = U^{-H})
@@ -161,17 +171,31 @@ int op_sinv(Ctx& c, const zd* Y, zd* X, cplx mu, int prec, bool adjoint) {
     TRY(gemm(prec, h, c.st));
     return 0;
   }
-  // Schur route: always FP64 for the triangular solve; basis changes in FP64.
-  TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_C, Y, n, OP_N, c.w1, n, one, 0));
-  TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, c.Z, n, OP_N, c.w2, n, one, 0));
+  // Schur route: the triangular solve always in FP64; the basis changes in the working precision
+  // (FP64, or FP32 / BF16x3 products of the FP32 copy of Z with FP32 accumulation)
+  const bool lowp = prec != PREC_F64 && c.Z32;
+  if (lowp) {
+    TRY(to_c64(Y, c.a32, n2, c.st));
+    TRY(op_gemm(c, prec, n, n, n, c.Z32, n, OP_C, c.a32, n, OP_N, c.b32, n, one, 0));
+    TRY(basis_to64(c, prec, c.b32, OP_N, c.Z32, OP_N, c.w2));
+  } else {
+    TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_C, Y, n, OP_N, c.w1, n, one, 0));
+    TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, c.Z, n, OP_N, c.w2, n, one, 0));
+  }
   if (!adjoint) {
-    TRY(trisylv(c.T, c.w2, n, zmk(-mu.real(), -mu.imag()), c.tsws, c.st));
+    TRY(trisylv(c.T, c.w2, n, zmk(-mu.real(), -mu.imag()), c.tsws, c.st, lowp ? &c.tsb : nullptr));
   } else {
     // T^H Xt + Xt T - conj(mu) Xt = Yt  <=>  T' X' + X' T'^H - conj(mu) X' = Y'  with
     // T' = J T^H J (upper triangular, precomputed), X' = J Xt J, Y' = J Yt J (J = exchange)
     TRY(flip_rev(c.w2, c.w1, n, c.st));
-    TRY(trisylv(c.Tadj, c.w1, n, zmk(-mu.real(), mu.imag()), c.tsws, c.st));
+    TRY(trisylv(c.Tadj, c.w1, n, zmk(-mu.real(), mu.imag()), c.tsws, c.st, lowp ? &c.tsb_adj : nullptr));
     TRY(flip_rev(c.w1, c.w2, n, c.st));
+  }
+  if (lowp) {
+    TRY(to_c64(c.w2, c.a32, n2, c.st));
+    TRY(op_gemm(c, prec, n, n, n, c.Z32, n, OP_N, c.a32, n, OP_N, c.b32, n, one, 0));
+    TRY(basis_to64(c, prec, c.b32, OP_N, c.Z32, OP_C, X));
+    return 0;
   }
   TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_N, c.w2, n, OP_N, c.w1, n, one, 0));
   TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, c.Z, n, OP_C, X, n, one, 0));
@@ -190,9 +214,17 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian) {
   const cplx one(1, 0), mone(-1, 0);
   if (d == 0) return fill_zero(out, n2 * (long long)sizeof(zd), c.st) ? LIND_EDEVICE : 0;
   if (c.route == LIND_ROUTE_SCHUR) {
-    TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_C, xi, n, OP_N, c.w1, n, one, 0));
-    TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, c.Z, n, OP_N, c.w2, n, one, 0));
-    TRY(trisylv(c.T, c.w2, n, zmk(0, 0), c.tsws, c.st));
+    // FP64 triangular solve between basis changes and jump products in the working precision
+    const bool lowp = prec != PREC_F64 && c.Z32;
+    if (lowp) {
+      TRY(to_c64(xi, c.a32, n2, c.st));
+      TRY(op_gemm(c, prec, n, n, n, c.Z32, n, OP_C, c.a32, n, OP_N, c.b32, n, one, 0));
+      TRY(basis_to64(c, prec, c.b32, OP_N, c.Z32, OP_N, c.w2));
+    } else {
+      TRY(op_gemm(c, PREC_F64, n, n, n, c.Z, n, OP_C, xi, n, OP_N, c.w1, n, one, 0));
+      TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, c.Z, n, OP_N, c.w2, n, one, 0));
+    }
+    TRY(trisylv(c.T, c.w2, n, zmk(0, 0), c.tsws, c.st, lowp ? &c.tsb : nullptr));
     if (prec == PREC_F64) {
       TRY(op_gemm(c, PREC_F64, d * n, n, n, c.Lt, n, OP_N, c.w2, n, OP_N, c.Ys, n, one, 0));
       GemmDesc g;

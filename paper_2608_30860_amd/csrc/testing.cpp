@@ -79,6 +79,32 @@ extern "C" int lindx_trisylv(const void* T, void* X, int n, double sr, double si
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -4;
 }
 
+// the same solve with the block eigenbases of T's diagonal blocks for pairs whose condition
+// numbers are <= thr; kap (host, optional, ceil(n / 32) doubles) receives those condition numbers
+extern "C" int lindx_trisylv_blk(const void* T, void* X, int n, double sr, double si, double thr, double* kap,
+                                 void* stream) {
+  if (n < 1 || !T || !X) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  const long long be = trisylv_blk_elems(n), nbk = (n + 31) / 32;
+  zd *ws = nullptr, *y = nullptr, *yi = nullptr;
+  double* kd = nullptr;
+  int rc = 0;
+  if (hipMalloc(&ws, sizeof(zd) * (size_t)trisylv_ws_elems(n)) != hipSuccess ||
+      hipMalloc(&y, sizeof(zd) * (size_t)be) != hipSuccess || hipMalloc(&yi, sizeof(zd) * (size_t)be) != hipSuccess ||
+      hipMalloc(&kd, sizeof(double) * (size_t)nbk) != hipSuccess)
+    rc = -5;
+  if (!rc) rc = trisylv_blk_setup((const zd*)T, n, y, yi, kd, st);
+  TsBlk blk;
+  blk.Y = y; blk.Yi = yi; blk.kap = kd; blk.thr = thr;
+  if (!rc) rc = trisylv((const zd*)T, (zd*)X, n, zmk(sr, si), ws, st, &blk);
+  if (!rc && kap && hipMemcpyAsync(kap, kd, sizeof(double) * (size_t)nbk, hipMemcpyDeviceToHost, st) != hipSuccess)
+    rc = -4;
+  if (hipStreamSynchronize(st) != hipSuccess && rc == 0) rc = -4;
+  for (void* p : {(void*)ws, (void*)y, (void*)yi, (void*)kd})
+    if (p) hipFree(p);
+  return rc;
+}
+
 __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n) {
   long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];

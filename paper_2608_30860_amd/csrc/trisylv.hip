@@ -15,6 +15,15 @@
 //    PMAX workgroups per block (FP64 MFMA, operands through LDS); each writes its partial sum to
 //    the workspace half that the next launch reads.
 // The critical path is then one launch per anti-diagonal, with the long product sums beside it.
+//
+// Block eigenbases (optional, for the low-precision modes of the map Phi): a diagonal block has
+// T_II = Y_I D_I Y_I^{-1} with Y_I unit upper triangular (its eigenvectors), so the block equation
+// T_II X + X T_JJ^H + sigma X = C has the solution
+//   X = Y_I [ (Y_I^{-1} C Y_J^{-H})_ab / (t_a + conj(t_b) + sigma) ] Y_J^H,
+// four 32 x 32 products on the matrix cores in place of the 63-step sweep.  Its rounding error
+// grows with kappa(Y_I) kappa(Y_J), so it is taken only for block pairs whose condition numbers
+// (computed once per factorisation, infinity norm) are both within a threshold; every other pair is
+// swept.  Both ways are FP64 throughout.
 #include "kernels.hpp"
 
 namespace lindx {
@@ -25,9 +34,10 @@ static constexpr int TP = TB + 1;  // row stride of the product tiles
 // lanes), a lane stride of SP - 1 = 33 entries = 528 bytes, which falls on distinct LDS banks
 // (32 entries = 512 bytes would put every lane on the same ones).
 static constexpr int SP = TB + 2;
-// partial sums per block: enough update workgroups that a block's far products finish within the
-// time of a diagonal-block solve, few enough that the solve reads them in one round trip
-static constexpr int PMAX = 4;
+// partial sums per block: a block has up to 2 n / 32 far products (100 at n = 1600), taken by up to
+// 16 update workgroups in runs of at most 7, so that they finish beside the solve of the block
+// pairs of the next anti-diagonal; the solve reads the partial sums four slots at a time
+static constexpr int PMAX = 16;
 
 typedef double v4d_s __attribute__((ext_vector_type(4)));
 
@@ -119,13 +129,78 @@ constexpr SweepOrder make_sweep_order() {
 }
 __constant__ SweepOrder c_sweep = make_sweep_order();
 
+// Eigenvectors of diagonal block I of T: Y (unit upper triangular, column k solves
+// (T_II - t_kk) y = 0 by back substitution), its inverse, and kap = ||Y||_inf ||Y^{-1}||_inf (infinite
+// or NaN when two diagonal entries coincide).  A last block of b < 32 rows is padded with the identity.
+__global__ __launch_bounds__(64) void k_blk_eig(const zd* __restrict__ T, int n, zd* __restrict__ Y,
+                                                zd* __restrict__ Yi, double* __restrict__ kap) {
+  __shared__ zd Ts[TB][TB + 1];
+  __shared__ zd Ys[TB][TB + 1];
+  __shared__ zd Zs[TB][TB + 1];
+  __shared__ double rs[2][TB];
+  const int I = blockIdx.x, t = threadIdx.x;
+  const int i0 = I * TB, b = min(TB, n - i0);
+  for (int e = t; e < TB * TB; e += 64) {
+    const int r = e / TB, q = e % TB;
+    Ts[r][q] = (r < b && q < b) ? T[(long long)(i0 + r) * n + i0 + q] : zmk(0, 0);
+  }
+  __syncthreads();
+  if (t < TB) {
+    const int k = t;
+    for (int i = 0; i < TB; ++i) Ys[i][k] = zmk(i == k ? 1.0 : 0.0, 0.0);
+    if (k < b)
+      for (int i = k - 1; i >= 0; --i) {
+        zd acc = zmk(0, 0);
+        for (int m = i + 1; m <= k; ++m) acc = zadd(acc, zmul(Ts[i][m], Ys[m][k]));
+        Ys[i][k] = zdiv(zmk(-acc.x, -acc.y), zsub(Ts[i][i], Ts[k][k]));
+      }
+  }
+  __syncthreads();
+  if (t < TB) {
+    const int k = t;
+    for (int i = 0; i < TB; ++i) Zs[i][k] = zmk(i == k ? 1.0 : 0.0, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+      zd acc = zmk(0, 0);
+      for (int m = i + 1; m <= k; ++m) acc = zadd(acc, zmul(Ys[i][m], Zs[m][k]));
+      Zs[i][k] = zmk(-acc.x, -acc.y);
+    }
+  }
+  __syncthreads();
+  if (t < TB) {
+    double sy = 0, sz = 0;
+    for (int q = 0; q < TB; ++q) {
+      sy += sqrt(zabs2(Ys[t][q]));
+      sz += sqrt(zabs2(Zs[t][q]));
+    }
+    rs[0][t] = sy;
+    rs[1][t] = sz;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double my = 0, mz = 0;
+    bool finite = true;
+    for (int r = 0; r < TB; ++r) {
+      finite = finite && isfinite(rs[0][r]) && isfinite(rs[1][r]);
+      my = fmax(my, rs[0][r]);
+      mz = fmax(mz, rs[1][r]);
+    }
+    kap[I] = finite ? my * mz : INFINITY;
+  }
+  for (int e = t; e < TB * TB; e += 64) {
+    const int r = e / TB, q = e % TB;
+    Y[(long long)I * TB * TB + e] = Ys[r][q];
+    Yi[(long long)I * TB * TB + e] = Zs[r][q];
+  }
+}
+
 // One launch per anti-diagonal S: workgroups [0, cnt) solve the blocks I = Imin + b of S; the
 // next cntu * py workgroups compute partial sums of the far products of the blocks of S - 1
 // (block Iu = Iminu + b', slot p; terms p, p + PMAX, ...).  wsr holds the partial sums of S
 // (written by the previous launch), wsw receives those of S - 1.
 __global__ __launch_bounds__(256) void k_trisylv_level(const zd* __restrict__ T, zd* __restrict__ X, int n, int nb,
                                                        int S, int Imin, int cnt, int Iminu, int py, zd sigma,
-                                                       const zd* __restrict__ wsr, zd* __restrict__ wsw) {
+                                                       const zd* __restrict__ wsr, zd* __restrict__ wsw,
+                                                       TsBlk blk) {
   __shared__ zd sm[3 * TB * SP];
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -184,24 +259,34 @@ __global__ __launch_bounds__(256) void k_trisylv_level(const zd* __restrict__ T,
     ok[u] = er[u] < bi && eq[u] < bj;
     v[u] = ok[u] ? X[(long long)(i0 + er[u]) * n + j0 + eq[u]] : zmk(0, 0);
   }
-  // T_II and T_JJ^H pass through registers while LDS holds the product tiles
+  // block eigenbases for this pair (uniform over the workgroup)?
+  const double kapI = blk.kap ? blk.kap[I] : INFINITY, kapJ = blk.kap ? blk.kap[J] : INFINITY;
+  const bool eig = kapI < INFINITY && kapJ < INFINITY && kapI <= blk.thr && kapJ <= blk.thr;
+  // T_II and T_JJ^H (sweep), or Y_I^{-1} and Y_J^{-1} (eigenbases), pass through registers while
+  // LDS holds the product tiles
   zd ta[4], tb[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = t + 256 * k;
     const int r = e >> 5, q = e & 31;
-    ta[k] = (r < bi && q < bi) ? T[(long long)(i0 + r) * n + i0 + q] : zmk(0, 0);
-    tb[k] = (r < bj && q < bj) ? zconj(T[(long long)(j0 + r) * n + j0 + q]) : zmk(0, 0);
+    if (eig) {
+      ta[k] = blk.Yi[(long long)I * TB * TB + e];
+      tb[k] = blk.Yi[(long long)J * TB * TB + e];
+    } else {
+      ta[k] = (r < bi && q < bi) ? T[(long long)(i0 + r) * n + i0 + q] : zmk(0, 0);
+      tb[k] = (r < bj && q < bj) ? zconj(T[(long long)(j0 + r) * n + j0 + q]) : zmk(0, 0);
+    }
   }
-  {
-    zd part[PMAX][4];
+  // partial sums in groups of four slots, all loads of a group in flight together
+  for (int p0 = 0; p0 < np; p0 += 4) {
+    zd part[4][4];
 #pragma unroll
-    for (int pp = 0; pp < PMAX; ++pp)
+    for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        part[pp][u] = pp < np ? wsr[((long long)b * PMAX + pp) * TB * TB + er[u] * TB + eq[u]] : zmk(0, 0);
+        part[pp][u] = p0 + pp < np ? wsr[((long long)b * PMAX + p0 + pp) * TB * TB + er[u] * TB + eq[u]] : zmk(0, 0);
 #pragma unroll
-    for (int pp = 0; pp < PMAX; ++pp)
+    for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[u] = zsub(v[u], part[pp][u]);
   }
@@ -227,6 +312,84 @@ __global__ __launch_bounds__(256) void k_trisylv_level(const zd* __restrict__ T,
 #pragma unroll
     for (int u = 0; u < 4; ++u) v[u] = zsub(v[u], Cs[er[u] * SP + eq[u]]);
     __syncthreads();
+  }
+  if (eig) {
+    // block eigenbases: X = Y_I [(Y_I^{-1} C Y_J^{-H}) / (t_a + conj t_b + sigma)] Y_J^H, four
+    // products of 32 x 32 tiles in LDS (row stride TP), each wave one 16 x 16 quadrant; the
+    // inverses came in with the right-hand side, the eigenvector tiles and the diagonal entries
+    // are loaded while the first two products run
+    zd* Ap = sm;
+    zd* Bp = sm + TB * SP;
+    zd* Cp = sm + 2 * TB * SP;
+    const int ra0 = qi + (lane >> 4), cb = qj + (lane & 15);
+    zd yi[4], yj[4], da[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = t + 256 * k;
+      yi[k] = blk.Y[(long long)I * TB * TB + e];
+      yj[k] = blk.Y[(long long)J * TB * TB + e];
+      const int a = ra0 + 4 * k;
+      da[k] = a < bi ? T[(long long)(i0 + a) * n + i0 + a] : zmk(1, 0);
+    }
+    const zd tbd = cb < bj ? zconj(T[(long long)(j0 + cb) * n + j0 + cb]) : zmk(0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Cp[er[u] * TP + eq[u]] = v[u];  // zero outside the block
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = t + 256 * k;
+      Ap[(e >> 5) * TP + (e & 31)] = ta[k];
+    }
+    __syncthreads();
+    v4d_s cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    term_mfma(Ap, Cp, lane, qi, qj, cr, ci);  // Y_I^{-1} C
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ap[(ra0 + 4 * r) * TP + cb] = zmk(cr[r], ci[r]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = t + 256 * k;
+      Bp[(e & 31) * TP + (e >> 5)] = zconj(tb[k]);  // Bp[k][c] = conj(Y_J^{-1}[c][k])
+    }
+    __syncthreads();
+    cr = v4d_s{0, 0, 0, 0};
+    ci = v4d_s{0, 0, 0, 0};
+    term_mfma(Ap, Bp, lane, qi, qj, cr, ci);  // (Y_I^{-1} C) Y_J^{-H}
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = ra0 + 4 * r;
+      zd w = zmk(0, 0);
+      if (a < bi && cb < bj) w = zdiv(zmk(cr[r], ci[r]), zadd(zadd(da[r], tbd), sigma));
+      Cp[a * TP + cb] = w;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = t + 256 * k;
+      Ap[(e >> 5) * TP + (e & 31)] = yi[k];
+    }
+    __syncthreads();
+    cr = v4d_s{0, 0, 0, 0};
+    ci = v4d_s{0, 0, 0, 0};
+    term_mfma(Ap, Cp, lane, qi, qj, cr, ci);  // Y_I W
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ap[(ra0 + 4 * r) * TP + cb] = zmk(cr[r], ci[r]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = t + 256 * k;
+      Bp[(e & 31) * TP + (e >> 5)] = zconj(yj[k]);  // Bp[k][c] = conj(Y_J[c][k])
+    }
+    __syncthreads();
+    cr = v4d_s{0, 0, 0, 0};
+    ci = v4d_s{0, 0, 0, 0};
+    term_mfma(Ap, Bp, lane, qi, qj, cr, ci);  // (Y_I W) Y_J^H
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = ra0 + 4 * r;
+      if (a < bi && cb < bj) X[(long long)(i0 + a) * n + j0 + cb] = zmk(cr[r], ci[r]);
+    }
+    return;
   }
   // the zero slot (padding column of row 0 of As) stands in for both operands of a product that
   // does not apply
@@ -308,7 +471,17 @@ __global__ __launch_bounds__(256) void k_trisylv_level(const zd* __restrict__ T,
     if (ok[u]) X[(long long)(i0 + er[u]) * n + j0 + eq[u]] = v[u];
 }
 
-int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st) {
+long long trisylv_blk_elems(int n) { return (long long)((n + TB - 1) / TB) * TB * TB; }
+
+int trisylv_blk_setup(const zd* T, int n, zd* Y, zd* Yi, double* kap, hipStream_t st) {
+  if (n <= 0) return 0;
+  if (!T || !Y || !Yi || !kap) return -1;
+  hipLaunchKernelGGL(k_blk_eig, dim3((n + TB - 1) / TB), dim3(64), 0, st, T, n, Y, Yi, kap);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st, const TsBlk* blkp) {
+  const TsBlk blk = blkp ? *blkp : TsBlk{};
   if (n <= 0) return 0;
   if (!ws) return -1;
   const int nb = (n + TB - 1) / TB;
@@ -337,7 +510,7 @@ int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st) {
     const zd* wsr = ws + (lev & 1) * half;
     zd* wsw = ws + ((lev + 1) & 1) * half;
     hipLaunchKernelGGL(k_trisylv_level, dim3(cnt + cntu * py), dim3(256), 0, st, T, X, n, nb, S, Imin, cnt, Iminu,
-                       py, shift, wsr, wsw);
+                       py, shift, wsr, wsw, blk);
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }

@@ -19,6 +19,7 @@ def lib():
     L.lindx_trevec.argtypes = [vp, vp, ci, vp]
     L.lindx_triinv.argtypes = [vp, vp, ci, vp]
     L.lindx_trisylv.argtypes = [vp, vp, ci, cd, cd, vp]
+    L.lindx_trisylv_blk.argtypes = [vp, vp, ci, cd, cd, cd, ctypes.POINTER(cd), vp]
     L.lindx_p4_test.argtypes = [vp, vp, ci, ci, ci, ci, ci, ci, ci, vp, vp, vp, vp]
     L.lindx_cgs2.argtypes = [vp, ll, ci, vp, ll, vp, vp, ci, vp]
     return L
@@ -239,6 +240,60 @@ def test_trisylv(n, shift):
     Xn = X.cpu().numpy()
     res = Tm @ Xn + Xn @ Tm.conj().T + shift * Xn - C
     assert np.max(np.abs(res)) < 1e-12 * np.abs(C).max() * n
+
+
+@pytest.mark.parametrize("n", [37, 130, 300])
+@pytest.mark.parametrize("shift", [0.0, -0.3 + 0.2j])
+@pytest.mark.parametrize("case", ["spread-1e4", "spread-median", "spread-none", "clustered-1e4", "repeated-1e4"])
+def test_trisylv_block_eigenbases(n, shift, case):
+    """The triangular Sylvester solve with 32 x 32 diagonal block pairs taken through their
+    eigenvector matrices (the low-precision maps of the Schur route).  'spread': diagonal entries
+    spread over the left half-plane as a generator's eigenvalues are (moderate block condition
+    numbers), with the library's threshold 1e4, with the median condition number as threshold
+    (a mix of both ways) and with threshold 0 (every pair swept: equal to the sweep bit for bit).
+    'clustered': the near-equal diagonal of the sweep test (block condition numbers up to 1e13):
+    pairs above the threshold must fall back to the sweep.  'repeated': two equal diagonal entries
+    in the first block (infinite condition number).  Residual against T, C on the host: the
+    block-eigenbasis products round at about u 32 kappa_I kappa_J of the largest entry (four
+    products of length 32 with matrices of those condition numbers), bounded by
+    1e-14 kappa_max^2 n max|C| with kappa_max the largest condition number of a block taken that way."""
+    rng = np.random.default_rng(n + 7)
+    kind, how = case.split("-")
+    if kind == "spread":
+        d = -(0.2 + rng.random(n)) + 1j * rng.standard_normal(n)
+        Tm = 0.3 * np.triu(crand(rng, n, n), 1) / np.sqrt(n) + np.diag(d)
+    else:
+        Tm = np.triu(crand(rng, n, n)) / np.sqrt(n) - 2.0 * np.eye(n)
+    if kind == "repeated":
+        Tm[5, 5] = Tm[9, 9]
+    C = crand(rng, n, n)
+    nb = (n + 31) // 32
+    kap = (ctypes.c_double * nb)()
+    Tt = T(Tm)
+    if how == "median":
+        Xp = T(C)
+        assert lib().lindx_trisylv_blk(P(Tt), P(Xp), n, shift.real, shift.imag, 0.0, kap, None) == 0
+        thr = float(np.median(np.array(kap[:])))
+    else:
+        thr = {"1e4": 1e4, "none": 0.0}[how]
+    X = T(C)
+    assert lib().lindx_trisylv_blk(P(Tt), P(X), n, shift.real, shift.imag, thr, kap, None) == 0
+    kv = np.array(kap[:])
+    used = kv[np.isfinite(kv) & (kv <= thr)]
+    kmax = max(1.0, float(used.max())) if used.size else 1.0
+    Xn = X.cpu().numpy()
+    res = np.max(np.abs(Tm @ Xn + Xn @ Tm.conj().T + shift * Xn - C))
+    print(f"[case] {case} n={n}: kappa min {kv.min():.3g} median {np.median(kv):.3g} max {kv.max():.3g}, "
+          f"{used.size} of {nb} blocks below the threshold, residual {res:.3g}", flush=True)
+    if kind == "repeated":
+        assert not np.isfinite(kv[0])
+    if kind == "spread" and how == "1e4":
+        assert used.size == nb  # the eigenbasis way is the one under test here
+    assert res < (1e-14 * kmax ** 2 + 1e-12) * n * np.abs(C).max()
+    if how == "none":
+        Xs = T(C)
+        assert lib().lindx_trisylv(P(Tt), P(Xs), n, shift.real, shift.imag, None) == 0
+        assert torch.equal(X, Xs)
 
 
 @pytest.mark.parametrize("k,length,pad", [(1, 1, 0), (9, 5000, 3), (64, 4096, 0), (65, 3001, 7), (200, 20000, 16),
