@@ -32,6 +32,17 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
 
 
+def test_every_internal_symbol_is_exported(lib):
+    """include/lind_internal.h (kernel-level entry points for the tests and the benchmark): every
+    declared function is exported by the library."""
+    txt = open(os.path.join(ROOT, "include", "lind_internal.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = sorted(set(re.findall(r"\b(lindx_[a-z0-9_]+)\s*\(", txt)))
+    assert "lindx_trisylv_blk" in names and "lindx_p4_test" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
 def test_binding_symbol_list_matches_header():
     from paper_2608_30860_amd import SYMBOLS
     assert sorted(SYMBOLS) == header_functions()
