@@ -634,6 +634,142 @@ __global__ __launch_bounds__(512) void zgemm64_dma(GemmDesc g, int a_bytes, int 
       }
 }
 
+// ---------------------------------------------------------------------------------------------
+// FP32 kernel with direct-to-LDS staging: the FP64 kernel's structure at half the element size.
+// Block tile 128 x 128, 32 complex k per stage (again 256-byte rows, two 64 KB LDS stages), each
+// lane's 16-byte buffer_load ... lds moving two consecutive complex64 (two k in a "row-k" tile,
+// whose 16-byte chunks are XOR-swizzled by the row's low four bits; two m or n in a "k-row" tile,
+// one 1 KB row per wave-load).  Requires even K (and even M or N for an operand held k-row), even
+// leading and batch strides and 16-byte aligned bases, so that a chunk never straddles the end of a
+// row or of the operand.  8 waves of 64 x 32 on
+// v_mfma_f32_16x16x4f32, FP32 accumulation.
+// ---------------------------------------------------------------------------------------------
+constexpr int Z32_BK = 32;
+
+template <bool AN, bool BN, typename CplxOut>
+__global__ __launch_bounds__(512) void zgemm32_dma(GemmDesc g, int a_bytes, int b_bytes) {
+  __shared__ __attribute__((aligned(1024))) float2 S[2][2][Z64_TB * Z32_BK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave >> 2) * 64, wn0 = (wave & 3) * 32;
+  const int tm = (g.M + Z64_TB - 1) / Z64_TB, tn = (g.N + Z64_TB - 1) / Z64_TB;
+  const int tiles = tm * tn;
+  const int split = blockIdx.x / tiles;
+  int bm, bn;
+  tile_of(blockIdx.x - split * tiles, tm, tn, bm, bn);
+  const int m0 = bm * Z64_TB, n0 = bn * Z64_TB;
+  const int ktiles = (g.K + Z32_BK - 1) / Z32_BK;
+  const int bps = g.nbatch / g.nsplit;
+  const int it_begin = split * bps * ktiles;
+  const int total = bps * ktiles;
+
+  // loader: waves 0-3 stage A, 4-7 stage B, 8 wave-loads of 1 KB each.  Lane l of wave-load q
+  // writes bytes [16 l, 16 l + 16) of the operand tile's 1 KB block q.
+  const int lop = wave >> 2;
+  const bool rk = lop ? !BN : AN;
+  const long long ld = lop ? g.ldb : g.lda;
+  const long long bstride = lop ? g.sB : g.sA;
+  const int x0 = lop ? n0 : m0;
+  const int xvalid = lop ? g.N : g.M;
+  __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(lop ? g.B : g.A), (short)0,
+                                                                   lop ? b_bytes : a_bytes, 0x00020000);
+  long long eoff[8];  // element offset of this lane's first element for k0 = 0, batch 0
+  int kk[8];          // its k within the stage
+  bool rowok[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = (wave & 3) * 8 + u;
+    if (rk) {
+      // rows 4q .. 4q + 3, 16 chunks of two k each; slot (lane & 15) holds chunk slot ^ (r & 15)
+      const int r = 4 * q + (lane >> 4);
+      const int k = 2 * ((lane & 15) ^ (r & 15));
+      kk[u] = k;
+      rowok[u] = x0 + r < xvalid;
+      eoff[u] = (long long)(x0 + r) * ld + k;
+    } else {
+      // row k = q, elements 2 lane and 2 lane + 1 of the 128 m (or n)
+      kk[u] = q;
+      rowok[u] = x0 + 2 * lane < xvalid;
+      eoff[u] = (long long)q * ld + x0 + 2 * lane;
+    }
+  }
+  auto issue = [&](int itl, int buf) {
+    const int it = it_begin + itl;
+    const int b = it / ktiles;
+    const int k0 = (it - b * ktiles) * Z32_BK;
+    const long long kofs = rk ? (long long)k0 : (long long)k0 * ld;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = (wave & 3) * 8 + u;
+      const bool ok = rowok[u] && (k0 + kk[u] < g.K);
+      const unsigned off = ok ? (unsigned)((b * bstride + kofs + eoff[u]) * 8) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t*)&S[buf][lop][128 * q], 16, off, 0, 0, 0);
+    }
+  };
+
+  v4f cr[4][2], ci[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = v4f{0, 0, 0, 0};
+      ci[i][j] = v4f{0, 0, 0, 0};
+    }
+  // element (x, k) of a row-k tile: row x, chunk k / 2 in slot (k / 2) ^ (x & 15)
+  auto rk_at = [](int x, int k) { return x * Z32_BK + 2 * ((k >> 1) ^ (x & 15)) + (k & 1); };
+  if (total > 0) issue(0, 0);
+  for (int it = 0; it < total; ++it) {
+    const int buf = it & 1;
+    __syncthreads();  // this stage has landed; every wave is done with the other buffer
+    if (it + 1 < total) issue(it + 1, buf ^ 1);
+#pragma unroll
+    for (int st = 0; st < Z32_BK / 4; ++st) {
+      const int k = 4 * st + (lane >> 4);
+      float2 a[4], bq[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = wm0 + i * 16 + (lane & 15);
+        a[i] = AN ? S[buf][0][rk_at(m, k)] : S[buf][0][k * 128 + m];
+        if (!AN) a[i].y = -a[i].y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int nn = wn0 + j * 16 + (lane & 15);
+        bq[j] = BN ? S[buf][1][k * 128 + nn] : S[buf][1][rk_at(nn, k)];
+        if (!BN) bq[j].y = -bq[j].y;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float nai = -a[i].y;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, bq[j].x, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, bq[j].y, ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bq[j].y, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, bq[j].x, ci[i][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // the FP32 MFMA leaves rows 4 (lane / 16) + r of a 16 x 16 block in a lane (FP64: 4 r + lane / 16)
+        const int row = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn0 + j * 16 + (lane & 15);
+        if (g.nsplit > 1) {
+          if (row < g.M && col < g.N)
+            ((float2*)g.ws)[((long long)split * g.M + row) * g.N + col] = make_float2(cr[i][j][r], ci[i][j][r]);
+        } else {
+          epilogue_store<CplxOut>(g, row, col, cr[i][j][r], ci[i][j][r]);
+        }
+      }
+}
+
 // bytes an operand spans (batches included), or -1 past the reach of a 32-bit buffer offset
 static long long z64_extent(long long rows, long long cols, long long ld, long long bstride, int nbatch) {
   if (rows <= 0 || cols <= 0) return 0;
@@ -768,6 +904,40 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
     return rc;
   }
   if (prec == PREC_F32) {
+    // direct-to-LDS kernel when the operands allow it and 128 x 128 tiles fill the chip
+    {
+      const bool an = g.opA == OP_N, bn = g.opB == OP_N;
+      auto ext = [](long long rows, long long cols, long long ld, long long bs, int nb) -> long long {
+        if (rows <= 0 || cols <= 0) return 0;
+        const long long e = ((long long)(nb - 1) * bs + (rows - 1) * ld + cols) * 8;
+        return e < 0x7ff00000LL ? e : -1;
+      };
+      const long long ea = an ? ext(g.M, g.K, g.lda, g.sA, g.nbatch) : ext(g.K, g.M, g.lda, g.sA, g.nbatch);
+      const long long eb = bn ? ext(g.K, g.N, g.ldb, g.sB, g.nbatch) : ext(g.N, g.K, g.ldb, g.sB, g.nbatch);
+      // a 16-byte chunk holds two k (row-k tile) or two m / n (k-row tile): those counts even, so
+      // that no chunk reaches past its row or the operand
+      const bool even = (g.K % 2 == 0) && (g.lda % 2 == 0) && (g.ldb % 2 == 0) && (g.sA % 2 == 0) &&
+                        (g.sB % 2 == 0) && (an || g.M % 2 == 0) && (!bn || g.N % 2 == 0);
+      const bool aligned = (((unsigned long long)g.A | (unsigned long long)g.B) & 15) == 0;
+      const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.nsplit;
+      if (ea > 0 && eb > 0 && even && aligned && t128 >= 128) {
+        const int tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+        const dim3 grid(tm * tn * g.nsplit), blk(512);
+#define Z32_LAUNCH(OUT)                                                                                           \
+  do {                                                                                                           \
+    if (an && bn) hipLaunchKernelGGL((zgemm32_dma<true, true, OUT>), grid, blk, 0, st, g, (int)ea, (int)eb);       \
+    else if (an) hipLaunchKernelGGL((zgemm32_dma<true, false, OUT>), grid, blk, 0, st, g, (int)ea, (int)eb);      \
+    else if (bn) hipLaunchKernelGGL((zgemm32_dma<false, true, OUT>), grid, blk, 0, st, g, (int)ea, (int)eb);      \
+    else hipLaunchKernelGGL((zgemm32_dma<false, false, OUT>), grid, blk, 0, st, g, (int)ea, (int)eb);             \
+  } while (0)
+        if (g.out64 && g.nsplit == 1) Z32_LAUNCH(double2);
+        else Z32_LAUNCH(float2);
+#undef Z32_LAUNCH
+        rc = hipGetLastError() == hipSuccess ? 0 : -4;
+        if (!rc && g.nsplit > 1) rc = g.out64 ? launch_reduce<float2, double2>(g, st) : launch_reduce<float2, float2>(g, st);
+        return rc;
+      }
+    }
     // 128 x 128 tiles for split or large products, else 64 x 64; 32 x 32 when the larger tiles
     // would leave most of the chip idle
     int bt = (g.nsplit > 1 || (g.M >= 1024 && g.N >= 1024)) ? 128 : 64;
