@@ -19,8 +19,9 @@ static thread_local std::string g_create_err;
     if (rc__) return rc__ < 0 ? rc__ : LIND_EDEVICE;     \
   } while (0)
 
-// BF16x3 eigen route: split the constant operands of Phi into bf16 planes once, and allocate the
-// planes of its intermediates (all zero-padded to whole tiles)
+// BF16x3: split the constant operands of Phi into bf16 planes once (the basis change by V on the
+// eigen route, by Z on the Schur route, and the fused jump operators), and allocate the planes of
+// its intermediates (all zero-padded to whole tiles)
 static int setup_p4(Ctx& c) {
   const int n = c.n, d = c.d;
   P4* bufs[7] = {&c.p4_VH, &c.p4_VT, &c.p4_Lt, &c.p4_xiT, &c.p4_C1, &c.p4_XhT, &c.p4_Y};
@@ -30,9 +31,10 @@ static int setup_p4(Ctx& c) {
     if (p4_alloc(*bufs[i], rows[i], n)) return c.fail(LIND_ENOMEM, "out of device memory (bf16 planes)");
     c.allocs.push_back(bufs[i]->p);
   }
-  // V^H (rows m, k: conj V[k][m]), V^T (rows j, k: V[k][j]), L_j U stacked (rows, k)
-  if (p4_split(c.V, 1, n, n, n, 1, 1, c.p4_VH, c.st)) return LIND_EDEVICE;
-  if (p4_split(c.V, 1, n, n, n, 1, 0, c.p4_VT, c.st)) return LIND_EDEVICE;
+  // B^H (rows m, k: conj B[k][m]), B^T (rows j, k: B[k][j]) for B = V or Z, L_j U or L_j Z stacked
+  const zd* Bm = c.route == LIND_ROUTE_EIG ? c.V : c.Z;
+  if (p4_split(Bm, 1, n, n, n, 1, 1, c.p4_VH, c.st)) return LIND_EDEVICE;
+  if (p4_split(Bm, 1, n, n, n, 1, 0, c.p4_VT, c.st)) return LIND_EDEVICE;
   if (p4_split(c.Lt, 1, n, d * n, n, 0, 0, c.p4_Lt, c.st)) return LIND_EDEVICE;
   // split-K of the jump reduction (d n-long products summed; only the tiles on and above the
   // diagonal of its Hermitian result are computed) in runs that fill whole rounds of the chip
@@ -235,7 +237,7 @@ static int ctx_factor(lind_ctx* X) {
     TRY(to_c64(c.Z, c.Z32, n2, c.st));
     if (d > 0) TRY(to_c64(c.Lt, c.Lt32, (long long)d * n2, c.st));
   }
-  if (c.prec == PREC_BF16X3 && route == LIND_ROUTE_EIG && d > 0) TRY(setup_p4(c));
+  if (c.prec == PREC_BF16X3 && d > 0) TRY(setup_p4(c));
   TRY(c.sync());
   c.t_factor = now_s() - t0;
   return 0;

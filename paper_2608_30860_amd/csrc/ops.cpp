@@ -213,6 +213,52 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian) {
   const long long n2 = c.n2;
   const cplx one(1, 0), mone(-1, 0);
   if (d == 0) return fill_zero(out, n2 * (long long)sizeof(zd), c.st) ? LIND_EDEVICE : 0;
+  if (c.route == LIND_ROUTE_SCHUR && prec == PREC_BF16X3 && c.p4_ready) {
+    // pre-split BF16 products around the FP64 triangular solve: C1 = Z^H xi (planes), W = C1 Z
+    // (complex128 through the split-K path), T Xh + Xh T^H = W, Xh^T into planes, then the jump
+    // products of the eigen route with Lt_j = L_j Z
+    const int sp = c.prof_begin(PROF_PHI);
+    int s0 = c.prof_begin(PROF_BASIS_IN);
+    TRY(p4_split(xi, 1, n, n, n, 1, 0, c.p4_xiT, c.st));
+    P4Desc g;
+    g.M = n; g.N = n; g.K = n;
+    g.A = c.p4_VH.p; g.lda = c.p4_VH.ld; g.pA = c.p4_VH.pstride;
+    g.B = c.p4_xiT.p; g.ldb = c.p4_xiT.ld; g.pB = c.p4_xiT.pstride;
+    g.out = P4OUT_PLANES; g.C = c.p4_C1.p; g.ldc = c.p4_C1.ld; g.pC = c.p4_C1.pstride;
+    TRY(p4_gemm(g, c.st));
+    P4Desc h;
+    h.M = n; h.N = n; h.K = n;
+    h.A = c.p4_C1.p; h.lda = c.p4_C1.ld; h.pA = c.p4_C1.pstride;
+    h.B = c.p4_VT.p; h.ldb = c.p4_VT.ld; h.pB = c.p4_VT.pstride;
+    h.tri = hermitian;  // Hermitian xi: Z^H xi Z is Hermitian
+    const long long tm = (n + 127) / 128;
+    h.nsplit = std::min(c.p4_nsplit, p4_pick_split(hermitian ? tm * (tm + 1) / 2 : tm * tm, 1, n, device_cus(c.dev)));
+    h.out = P4OUT_WS; h.ws = c.p4_ws; h.out64 = c.w2; h.ldo = n; h.alpha = 1.0;
+    TRY(p4_gemm(h, c.st));
+    c.prof_end(s0);
+    TRY(trisylv(c.T, c.w2, n, zmk(0, 0), c.tsws, c.st, &c.tsb));
+    TRY(p4_split(c.w2, 1, n, n, n, 1, 0, c.p4_XhT, c.st));
+    int s1 = c.prof_begin(PROF_JUMP_STACK);
+    P4Desc y;
+    y.M = d * n; y.N = n; y.K = n;
+    y.A = c.p4_Lt.p; y.lda = c.p4_Lt.ld; y.pA = c.p4_Lt.pstride;
+    y.B = c.p4_XhT.p; y.ldb = c.p4_XhT.ld; y.pB = c.p4_XhT.pstride;
+    y.out = P4OUT_PLANES; y.C = c.p4_Y.p; y.ldc = c.p4_Y.ld; y.pC = c.p4_Y.pstride;
+    TRY(p4_gemm(y, c.st));
+    c.prof_end(s1);
+    P4Desc r;
+    r.M = n; r.N = n; r.K = n; r.nbatch = d; r.nsplit = c.p4_nsplit;
+    r.A = c.p4_Y.p; r.lda = c.p4_Y.ld; r.pA = c.p4_Y.pstride; r.sA = (long long)n * c.p4_Y.ld;
+    r.B = c.p4_Lt.p; r.ldb = c.p4_Lt.ld; r.pB = c.p4_Lt.pstride; r.sB = (long long)n * c.p4_Lt.ld;
+    r.conjB = 1;
+    r.out = P4OUT_WS; r.ws = c.p4_ws; r.out64 = out; r.ldo = n; r.alpha = -1.0;
+    r.tri = hermitian;
+    int s2 = c.prof_begin(PROF_JUMP_REDUCE);
+    TRY(p4_gemm(r, c.st));
+    c.prof_end(s2);
+    c.prof_end(sp);
+    return 0;
+  }
   if (c.route == LIND_ROUTE_SCHUR) {
     // FP64 triangular solve between basis changes and jump products in the working precision
     const bool lowp = prec != PREC_F64 && c.Z32;

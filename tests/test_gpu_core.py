@@ -206,23 +206,31 @@ def test_singular_generator_is_reported():
     assert e.value.code == -2
 
 
-@pytest.mark.parametrize("n,d", [(37, 3), (130, 2)])
-def test_schur_route_sinv_phi_steady(n, d):
+@pytest.mark.parametrize("n,d", [(37, 3), (130, 2), (300, 3)])
+@pytest.mark.parametrize("prec,phi_tol,tol", [("fp64", 1e-11, 1e-10), ("fp32", 3e-5, 1e-8), ("bf16x3", 3e-4, 1e-8)])
+def test_schur_route_sinv_phi_steady(n, d, prec, phi_tol, tol):
     """Bartels-Stewart route (Section A.1): the triangular Sylvester solve gives the same S^{-1},
-    Phi and steady state as the oracle."""
-    print(f"[case] schur route n={n} d={d}", flush=True)
+    Phi and steady state as the oracle.  In the FP32 and BF16x3 contexts Phi's basis changes and
+    jump products run in the working precision around the FP64 solve (which takes well-conditioned
+    diagonal block pairs through their eigenbases), held to the eigen route's Phi tolerances;
+    S^{-1} itself stays FP64 in every context, and the mixed steady states are refined to 1e-8."""
+    print(f"[case] schur route n={n} d={d} {prec}", flush=True)
     H, Ls = li.random_dense(n, d, 3)
     G = ol.no_jump_generator(H, Ls)
-    m = make(H, Ls, route="schur")
+    m = make(H, Ls, route="schur", prec=prec)
     Y = li.random_state(n, seed=3, hermitian=False)
     for mu in (0.0, 0.35 + 0.2j):
         X = N(m.sinv(T(Y), mu))
         res = G @ X + X @ G.conj().T - mu * X - Y
         assert np.max(np.abs(res)) < 1e-11 * max(1.0, np.max(np.abs(Y)))
     xi = li.random_state(n, seed=5)
-    assert relerr(N(m.phi(T(xi))), ol.phi_apply(G, Ls, xi)) < 1e-11
-    rho = N(m.steady_state(1e-10).rho)
-    assert ol.trace_norm(ol.lindblad_apply(H, Ls, rho)) < 1e-10
+    err = relerr(N(m.phi(T(xi))), ol.phi_apply(G, Ls, xi))
+    print(prec, "phi rel err", err, flush=True)
+    assert err < phi_tol
+    r = m.steady_state(tol)
+    rho = N(r.rho)
+    assert ol.trace_norm(ol.lindblad_apply(H, Ls, rho)) < tol
+    assert r.info["route_used"] == 2
     m.close()
 
 
