@@ -503,7 +503,7 @@ def main():
     if not args.no_configs:
         per_config = []
         for wname, precs, loops in [("kerr32", ["fp64"], 2000), ("two_photon256", ["fp64", "fp32"], 400),
-                                    ("coupled_kerr1600", ["fp32"], 20), ("kerr512_dephasing", ["fp64"], 100),
+                                    ("coupled_kerr1600", ["fp32", "bf16x3"], 20), ("kerr512_dephasing", ["fp64"], 100),
                                     ("random1024_d4", ["fp64", "bf16x3"], 50)]:
             Hc, Lc, _ = li.workload(wname)
             nc = Hc.shape[0]
