@@ -200,7 +200,7 @@ __global__ __launch_bounds__(64) void k_blk_eig(const zd* __restrict__ T, int n,
 __global__ __launch_bounds__(256) void k_trisylv_level(const zd* __restrict__ T, zd* __restrict__ X, int n, int nb,
                                                        int S, int Imin, int cnt, int Iminu, int py, zd sigma,
                                                        const zd* __restrict__ wsr, zd* __restrict__ wsw,
-                                                       TsBlk blk) {
+                                                       int pyr, TsBlk blk) {
   __shared__ zd sm[3 * TB * SP];
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -222,11 +222,11 @@ __global__ __launch_bounds__(256) void k_trisylv_level(const zd* __restrict__ T,
     v4d_s cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
     // the tiles of the next term are loaded while the current one is multiplied
     term_load(T, X, n, i0, j0, bi, bj, p < nA ? I + 2 + p : J + 2 + (p - nA), p < nA, t, ra, rb);
-    for (int term = p; term < terms; term += PMAX) {
+    for (int term = p; term < terms; term += py) {
       __syncthreads();
       term_store(As, Bs, term < nA, t, ra, rb);
       __syncthreads();
-      const int nx = term + PMAX;
+      const int nx = term + py;
       if (nx < terms) term_load(T, X, n, i0, j0, bi, bj, nx < nA ? I + 2 + nx : J + 2 + (nx - nA), nx < nA, t, ra, rb);
       term_mfma(As, Bs, lane, qi, qj, cr, ci);
     }
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_trisylv_level(const zd* __restrict__ T,
   const int I = Imin + b, J = S - I;
   const int i0 = I * TB, j0 = J * TB;
   const int bi = min(TB, n - i0), bj = min(TB, n - j0);
-  const int np = min(PMAX, far_terms(nb, I, J));
+  const int np = min(pyr, far_terms(nb, I, J));  // slots the previous launch wrote for this block
   const bool nearA = I + 1 < nb, nearB = J + 1 < nb;
   if (nearA) term_load(T, X, n, i0, j0, bi, bj, I + 1, true, t, ra, rb);
   // thread t owns the entries 256 u + t of the sweep order and keeps them in registers until
@@ -488,11 +488,17 @@ int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st, const T
   const long long half = (long long)nb * PMAX * TB * TB;
   auto imin = [&](int S) { return S - (nb - 1) > 0 ? S - (nb - 1) : 0; };
   auto imax = [&](int S) { return S < nb - 1 ? S : nb - 1; };
+  // workgroups the chip holds at once (two per compute unit at this kernel's register use): a
+  // launch wider than that runs in two rounds, so the far products are spread no wider
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -4;
+  const int resident = 2 * device_cus(dev);
+  int py_prev = 0;
   for (int lev = 0; lev <= 2 * (nb - 1); ++lev) {
     const int S = 2 * (nb - 1) - lev;  // I + J
     const int Imin = imin(S), cnt = imax(S) - Imin + 1;
     // far products of anti-diagonal S - 1, spread over py workgroups per block (py = the most far
-    // terms a block of S - 1 has, at most PMAX)
+    // terms a block of S - 1 has, at most PMAX, and no more than one round of the chip allows)
     int cntu = 0, py = 1, Iminu = 0;
     if (S >= 1) {
       int terms = 0;
@@ -502,15 +508,18 @@ int trisylv(const zd* T, zd* X, int n, zd shift, zd* ws, hipStream_t st, const T
         terms = f > terms ? f : terms;
       }
       if (terms > 0) {
-        py = terms < PMAX ? terms : PMAX;
         Iminu = imin(S - 1);
         cntu = imax(S - 1) - Iminu + 1;
+        py = terms < PMAX ? terms : PMAX;
+        const int fit = (resident - cnt) / cntu;
+        if (py > fit) py = fit > 1 ? fit : 1;
       }
     }
     const zd* wsr = ws + (lev & 1) * half;
     zd* wsw = ws + ((lev + 1) & 1) * half;
     hipLaunchKernelGGL(k_trisylv_level, dim3(cnt + cntu * py), dim3(256), 0, st, T, X, n, nb, S, Imin, cnt, Iminu,
-                       py, shift, wsr, wsw, blk);
+                       py, shift, wsr, wsw, py_prev, blk);
+    py_prev = cntu ? py : 0;
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
