@@ -36,6 +36,14 @@ int lindx_small_eig(const void* A, int m, void* w, void* Y, void* stream);
    (synchronous).  n = 0 does nothing; n < 0 or n > 10240 (the column's right-hand sides must fit
    in 160 KB of LDS) returns -1, -5 if the workspace cannot be allocated. */
 int lindx_trevec(const void* T, void* Y, int n, void* stream);
+
+/* Ritz pair of the steady-state Arnoldi driver: for an upper Hessenberg H (k x k, k <= 64,
+   complex128 row-major, device), the eigenvalue nearest sigma and its eigenvector by inverse
+   iteration with the fixed shift sigma.  out (device, k + 2 complex128): out[0] = theta = y^H H y,
+   out[1 .. k] = y (unit 2-norm, largest-modulus entry real positive), out[k + 1] = (||H y - theta
+   y||_2, 0).  *iters (host, may be NULL) receives the iteration count.  Synchronous; 0, -1 on bad
+   arguments, -4 on a device error, -5 when a workspace cannot be allocated. */
+int lindx_ritz_near(const void* H, int k, double sigma_re, double sigma_im, void* out, int* iters, void* stream);
 int lindx_triinv(const void* Y, void* Yinv, int n, void* stream);
 
 /* T X + X T^H + shift X = C in place (X holds C on entry), T upper triangular */

@@ -190,6 +190,8 @@ struct lind_ctx {
 namespace lindx {
 // helpers shared by the drivers (lind.cpp)
 int ensure_solver_bufs(lind_ctx* X);
+int ritz_near_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, cplx& theta, std::vector<cplx>& y,
+                   double& rin);
 int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std::vector<cplx>& w,
                    std::vector<cplx>& Y);
 int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst);

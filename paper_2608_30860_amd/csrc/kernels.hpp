@@ -152,6 +152,9 @@ int diag_extract(const zd* T, zd* s, int n, hipStream_t st);
 // in: A (m x m, leading dim lda) -- general complex.  out: w (m eigenvalues), Y (m x m right
 // eigenvectors, column j for w[j], unit 2-norm), info (device int: 0 ok, 1 no convergence).
 int small_eig(const zd* A, int lda, int m, zd* w, zd* Y, int* info, hipStream_t st);
+// Ritz pair of an upper Hessenberg H (k x k, k <= 64) with the eigenvalue nearest sigma, by inverse
+// iteration: out[0] = theta, out[1..k] = unit y, out[k + 1] = (||H y - theta y||, 0); info = iterations
+int ritz_near(const zd* H, int ld, int k, zd sigma, zd* out, int* info, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // triangular Sylvester solve  T X + X T^H + shift*X = Y  (T upper triangular, n x n)

@@ -477,20 +477,6 @@ int lindx::ensure_solver_bufs(lind_ctx* X) {
   return rc ? LIND_ENOMEM : 0;
 }
 
-// Ritz value nearest 1 among w[0..k); ties toward real, then Im >= 0
-static int pick_nearest_one(const std::vector<cplx>& w) {
-  double best = 1e300;
-  for (auto& z : w) best = std::min(best, std::abs(z - 1.0));
-  int idx = -1;
-  for (int i = 0; i < (int)w.size(); ++i) {
-    if (std::abs(w[i] - 1.0) > best * (1 + 1e-9) + 1e-14) continue;
-    if (idx < 0) { idx = i; continue; }
-    double a = std::fabs(w[i].imag()), b = std::fabs(w[idx].imag());
-    if (a < b - 1e-14 || (std::fabs(a - b) <= 1e-14 && w[i].imag() > w[idx].imag())) idx = i;
-  }
-  return idx < 0 ? 0 : idx;
-}
-
 // small eigenproblem of the k x k leading block of the host matrix Hh (row stride ld)
 int lindx::small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std::vector<cplx>& w,
                           std::vector<cplx>& Y) {
@@ -511,6 +497,26 @@ int lindx::small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int 
   for (int i = 0; i < k * k; ++i) Y[i] = cplx(c.hsc[64 + i].x, c.hsc[64 + i].y);
   int info = *(const int*)(c.hsc + 8000);
   return info ? LIND_ENOCONV : 0;
+}
+
+// Ritz pair of the k x k leading block of the host Hessenberg matrix Hh (row stride ld) whose
+// value is nearest 1: theta, the unit-norm vector y (largest entry real positive) and the residual
+// ||H y - theta y|| inside the Krylov space
+int lindx::ritz_near_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, cplx& theta, std::vector<cplx>& y,
+                          double& rin) {
+  Ctx& c = X->c;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) c.hsc[i * k + j] = zmk(Hh[(size_t)i * ld + j].real(), Hh[(size_t)i * ld + j].imag());
+  if (hipMemcpyAsync(X->hm, c.hsc, sizeof(zd) * k * k, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
+  TRY(ritz_near(X->hm, k, k, zmk(1.0, 0.0), X->Yv, X->sinfo, c.st));
+  if (hipMemcpyAsync(c.hsc, X->Yv, sizeof(zd) * (k + 2), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+    return LIND_EDEVICE;
+  TRY(c.sync());
+  theta = cplx(c.hsc[0].x, c.hsc[0].y);
+  y.resize(k);
+  for (int i = 0; i < k; ++i) y[i] = cplx(c.hsc[1 + i].x, c.hsc[1 + i].y);
+  rin = c.hsc[k + 1].x;
+  return std::isfinite(rin) && std::isfinite(theta.real()) ? 0 : LIND_ENOCONV;
 }
 
 int lindx::upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst) {
@@ -600,7 +606,7 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   const double eps_floor = (p == PREC_F64) ? 0.0 : (p == PREC_F32 ? 1e-6 : 3e-3);
   double best = 1e300, best_max = 0;
   bool converged = false;
-  std::vector<cplx> Hh((size_t)(m + 1) * m), w, Y;
+  std::vector<cplx> Hh((size_t)(m + 1) * m);
   double colsum = 0, mx = 0, fro = 0;
   bool floor_hit = false;
   bool best_is_last = false;  // rhoB / resB hold the best state and its FP64 residual
@@ -617,8 +623,11 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     for (int rs = 0; restarts_left > 0 && !converged; ++rs) {
       --restarts_left;
       std::fill(Hh.begin(), Hh.end(), cplx(0));
-      int k = 0, sel = 0, k_ritz = 0;  // k_ritz: the Krylov dimension the Ritz pair (w, Y) belongs to
+      int k = 0, k_ritz = 0;  // k_ritz: the Krylov dimension the Ritz pair (theta, ysel) belongs to
       double est = 1e300;
+      cplx theta(0.0, 0.0);
+      double rin = 0.0;
+      std::vector<cplx> ysel;
       for (int j = 0; j < m; ++j) {
         zd* vj = K + (long long)j * n2;
         zd* wv = K + (long long)(j + 1) * n2;
@@ -640,26 +649,18 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
         k = j + 1;
         bool check = (k >= 3 && (k % 2 == 1)) || k == m || hn == 0.0;
         if (check) {
-          int rc = small_eig_host(X, Hh, m, k, w, Y);
-          if (rc && rc != LIND_ENOCONV) return rc;
+          // Ritz pair nearest 1; the estimate also carries the pair's residual inside the
+          // Krylov space, which is zero for an exact eigenpair of H
+          TRY(ritz_near_host(X, Hh, m, k, theta, ysel, rin));
           k_ritz = k;
-          sel = pick_nearest_one(w);
-          cplx th = w[sel];
-          cplx ylast = Y[(size_t)(k - 1) * k + sel];
-          est = std::sqrt(std::norm(th - 1.0) + hn * hn * std::norm(ylast));
+          est = std::sqrt(std::norm(theta - 1.0) + rin * rin + hn * hn * std::norm(ysel[k - 1]));
           if (c_scale * est <= std::max(0.25 * tol, eps_floor) || hn == 0.0) break;
         }
         if (deadline > 0 && now_s() > deadline) break;
       }
       // the cycle may end (time limit) at a step without a Ritz evaluation: evaluate it for this k
-      if (k_ritz != k) {
-        int rc = small_eig_host(X, Hh, m, k, w, Y);
-        if (rc && rc != LIND_ENOCONV) return rc;
-        sel = pick_nearest_one(w);
-      }
+      if (k_ritz != k) TRY(ritz_near_host(X, Hh, m, k, theta, ysel, rin));
       // Ritz vector xi = V_k y
-      std::vector<cplx> ysel(k);
-      for (int i = 0; i < k; ++i) ysel[i] = Y[(size_t)i * k + sel];
       TRY(upload_vec(X, ysel.data(), k, X->yv));
       TRY(multi_axpy(K, n2, k, X->yv, X->xiB, n2, 0, 1.0, c.st));
       // the fixed point xi = -S(rho_inf) is Hermitian: keep the restart vector Hermitian

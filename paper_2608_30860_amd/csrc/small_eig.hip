@@ -71,6 +71,139 @@ __global__ __launch_bounds__(64) void k_small_eig(const zd* A, int lda, int m, z
     for (int j = t; j < m; j += 64) Yout[(long long)i * m + j] = Hs[i * LDM + j];
 }
 
+// The Ritz pair of an upper Hessenberg H (k x k, k <= 64) whose eigenvalue is nearest sigma, by
+// inverse iteration with the fixed shift sigma: one LU factorisation of H - sigma I with partial
+// pivoting (a Hessenberg matrix only ever swaps neighbouring rows), then per iteration a forward
+// and a back substitution, x <- (H - sigma I)^{-1} x / ||.||, until the direction settles.  The
+// iteration converges to the eigenvector of the eigenvalue nearest sigma at the rate
+// |lambda_1 - sigma| / |lambda_2 - sigma|.  A zero pivot is replaced by ulp ||H||_F (H - sigma I is
+// singular exactly when sigma is an eigenvalue, and then the first solve already gives the
+// eigenvector).  Output out[0] = theta = y^H H y, out[1 .. k] = y with unit norm and its
+// largest-modulus entry real positive, out[k + 1] = (||H y - theta y||_2, 0), info = iterations.
+// One wave; lane c owns column c in the elimination and row c in the substitutions.
+__global__ __launch_bounds__(64) void k_ritz_near(const zd* H, int ld, int k, zd sigma, zd* out, int* info) {
+  __shared__ zd A[64 * LDM];
+  __shared__ zd x[64], b[64];
+  __shared__ zd lf[64];
+  __shared__ int piv[64];
+  const int t = threadIdx.x;
+  double fro = 0;
+  for (int i = 0; i < k; ++i) {
+    if (t < k) {
+      zd h = H[(long long)i * ld + t];
+      fro += zabs2(h);
+      if (i == t) h = zsub(h, sigma);
+      A[i * LDM + t] = h;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) fro += __shfl_xor(fro, o, 64);
+  const double tiny = fmax(2.220446049250313e-16 * sqrt(fro), 1e-300);
+  __syncthreads();
+  // LU of the Hessenberg matrix: step j pivots between rows j and j + 1 and eliminates A[j+1][j]
+  for (int j = 0; j + 1 < k; ++j) {
+    const zd d = A[j * LDM + j], e = A[(j + 1) * LDM + j];
+    const bool sw = cabs1(e) > cabs1(d);
+    if (sw && t >= j && t < k) {
+      const zd u = A[j * LDM + t];
+      A[j * LDM + t] = A[(j + 1) * LDM + t];
+      A[(j + 1) * LDM + t] = u;
+    }
+    __syncthreads();
+    zd p = A[j * LDM + j];
+    if (cabs1(p) < tiny) p = zmk(tiny, 0);
+    const zd l = zdiv(A[(j + 1) * LDM + j], p);
+    if (t > j && t < k) A[(j + 1) * LDM + t] = zsub(A[(j + 1) * LDM + t], zmul(l, A[j * LDM + t]));
+    if (t == 0) {
+      A[j * LDM + j] = p;
+      lf[j] = l;
+      piv[j] = sw ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  if (t == 0 && cabs1(A[(k - 1) * LDM + k - 1]) < tiny) A[(k - 1) * LDM + k - 1] = zmk(tiny, 0);
+  // start: all ones (a fixed vector, so the result is deterministic)
+  if (t < k) x[t] = zmk(1.0 / sqrt((double)k), 0);
+  __syncthreads();
+  int it = 0;
+  double dprev = 1e300;
+  for (; it < 60; ++it) {
+    // forward: the row swaps and eliminations applied to b = x
+    if (t == 0) {
+      for (int i = 0; i < k; ++i) b[i] = x[i];
+      for (int j = 0; j + 1 < k; ++j) {
+        if (piv[j]) { const zd u = b[j]; b[j] = b[j + 1]; b[j + 1] = u; }
+        b[j + 1] = zsub(b[j + 1], zmul(lf[j], b[j]));
+      }
+    }
+    __syncthreads();
+    // back substitution, column oriented: x_i = b_i / U_ii, then b_r -= U_ri x_i for r < i
+    zd bi = t < k ? b[t] : zmk(0, 0);
+    zd xi = zmk(0, 0);
+    for (int i = k - 1; i >= 0; --i) {
+      const zd xv = zdiv(zmk(__shfl(bi.x, i, 64), __shfl(bi.y, i, 64)), A[i * LDM + i]);
+      if (t == i) xi = xv;
+      if (t < i) bi = zsub(bi, zmul(A[t * LDM + i], xv));
+    }
+    // normalise; the direction has settled when the new vector, rotated onto the old one's phase,
+    // differs from it by rounding only (or stops getting closer)
+    double nn = t < k ? zabs2(xi) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
+    xi = zscale(xi, 1.0 / sqrt(nn));
+    const zd old = t < k ? x[t] : zmk(0, 0);
+    zd ov = zcmul(xi, old);  // <new, old>
+    for (int o = 32; o > 0; o >>= 1) {
+      ov.x += __shfl_xor(ov.x, o, 64);
+      ov.y += __shfl_xor(ov.y, o, 64);
+    }
+    const double aov = sqrt(zabs2(ov));
+    const zd rot = aov > 0 ? zscale(ov, 1.0 / aov) : zmk(1, 0);
+    xi = zmul(xi, rot);  // same phase as the old vector
+    double dd = t < k ? zabs2(zsub(xi, old)) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) dd += __shfl_xor(dd, o, 64);
+    __syncthreads();
+    if (t < k) x[t] = xi;
+    __syncthreads();
+    const double dist = sqrt(dd);
+    if (dist <= 4e-15 || (it >= 8 && dist >= 0.5 * dprev)) { ++it; break; }
+    dprev = dist;
+  }
+  // theta = y^H H y and the residual ||H y - theta y|| (H re-read from global memory)
+  zd hy = zmk(0, 0);
+  if (t < k)
+    for (int j = 0; j < k; ++j) hy = zadd(hy, zmul(H[(long long)t * ld + j], x[j]));
+  const zd yt = t < k ? x[t] : zmk(0, 0);
+  zd th = zcmul(yt, hy);
+  for (int o = 32; o > 0; o >>= 1) {
+    th.x += __shfl_xor(th.x, o, 64);
+    th.y += __shfl_xor(th.y, o, 64);
+  }
+  double rr = t < k ? zabs2(zsub(hy, zmul(th, yt))) : 0.0;
+  for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o, 64);
+  // phase: the largest-modulus entry real positive (first one on ties)
+  double a = t < k ? zabs2(yt) : -1.0;
+  int am = t;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double a2 = __shfl_xor(a, o, 64);
+    const int m2 = __shfl_xor(am, o, 64);
+    if (a2 > a || (a2 == a && m2 < am)) { a = a2; am = m2; }
+  }
+  const zd ph = zmk(__shfl(yt.x, am, 64), __shfl(yt.y, am, 64));
+  const double aph = sqrt(zabs2(ph));
+  const zd f = aph > 0 ? zscale(zconj(ph), 1.0 / aph) : zmk(1, 0);
+  if (t < k) out[1 + t] = zmul(yt, f);
+  if (t == 0) {
+    out[0] = th;
+    out[k + 1] = zmk(sqrt(rr), 0);
+    info[0] = it;
+  }
+}
+
+int ritz_near(const zd* H, int ld, int k, zd sigma, zd* out, int* info, hipStream_t st) {
+  if (k < 1 || k > 64 || ld < k) return -1;
+  hipLaunchKernelGGL(k_ritz_near, dim3(1), dim3(64), 0, st, H, ld, k, sigma, out, info);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 int small_eig(const zd* A, int lda, int m, zd* w, zd* Y, int* info, hipStream_t st) {
   if (m < 1 || m > 64) return -1;
   hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(64), 0, st, A, lda, m, w, Y, info);

@@ -63,6 +63,20 @@ static int with_square_ws(int n, int (*f)(const zd*, zd*, zd*, int, hipStream_t)
   hipFree(ws);
   return rc;
 }
+// Ritz pair of an upper Hessenberg H (k x k complex128, device) nearest sigma (synchronous):
+// out (device, k + 2 complex128) = [theta, y_1 .. y_k, (||H y - theta y||, 0)], iterations in *iters
+extern "C" int lindx_ritz_near(const void* H, int k, double sr, double si, void* out, int* iters, void* stream) {
+  if (!H || !out || k < 1 || k > 64) return -1;
+  int* di = nullptr;
+  if (hipMalloc(&di, sizeof(int)) != hipSuccess) return -5;
+  int rc = ritz_near((const zd*)H, k, k, zmk(sr, si), (zd*)out, di, (hipStream_t)stream);
+  if (!rc && iters && hipMemcpyAsync(iters, di, sizeof(int), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
+    rc = -4;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == 0) rc = -4;
+  hipFree(di);
+  return rc;
+}
+
 extern "C" int lindx_trevec(const void* T, void* Y, int n, void* stream) {
   return with_square_ws(n, trevec, T, Y, stream);
 }

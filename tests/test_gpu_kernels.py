@@ -17,6 +17,7 @@ def lib():
     L.lindx_schur.argtypes = [vp, vp, ci, ci, vp]
     L.lindx_small_eig.argtypes = [vp, ci, vp, vp, vp]
     L.lindx_trevec.argtypes = [vp, vp, ci, vp]
+    L.lindx_ritz_near.argtypes = [vp, ci, cd, cd, vp, ctypes.POINTER(ci), vp]
     L.lindx_triinv.argtypes = [vp, vp, ci, vp]
     L.lindx_trisylv.argtypes = [vp, vp, ci, cd, cd, vp]
     L.lindx_trisylv_blk.argtypes = [vp, vp, ci, cd, cd, cd, ctypes.POINTER(cd), vp]
@@ -246,6 +247,47 @@ def test_trisylv(n, shift):
     Xn = X.cpu().numpy()
     res = Tm @ Xn + Xn @ Tm.conj().T + shift * Xn - C
     assert np.max(np.abs(res)) < 1e-12 * np.abs(C).max() * n
+
+
+@pytest.mark.parametrize("k", [1, 3, 16, 30, 64])
+@pytest.mark.parametrize("kind", ["real", "complex", "exact1"])
+def test_ritz_near(k, kind):
+    """The Ritz pair nearest 1 of an upper Hessenberg matrix by inverse iteration, against
+    numpy.linalg.eig: the eigenvalue to 1e-12 (relative to ||H||), the eigenvector up to phase to
+    1e-9 (its condition number grows with 1 / gap), the in-space residual it reports against one
+    recomputed on the host.  'real' is a real Hessenberg matrix (the steady-state iteration's, whose
+    Krylov vectors are Hermitian) with an eigenvalue close to 1; 'exact1' has 1 as an exact
+    eigenvalue (a converged iteration), where H - I is singular."""
+    rng = np.random.default_rng(17 * k + len(kind))
+    # spectrum: one eigenvalue at 0.97 (or exactly 1), the rest within 0.3 of the origin; a random
+    # similarity, then the Hessenberg form (real throughout for the real kinds)
+    cplx_kind = kind == "complex"
+    w = 0.3 * (rng.random(k) * 2 - 1) + (0.3j * (rng.random(k) * 2 - 1) if cplx_kind else 0)
+    w[0] = 1.0 if kind == "exact1" else 0.97
+    Q = rng.standard_normal((k, k)) + (1j * rng.standard_normal((k, k)) if cplx_kind else 0)
+    A = Q @ np.diag(w) @ np.linalg.inv(Q)
+    import scipy.linalg as sl
+    Hm = np.asarray(sl.hessenberg(A if cplx_kind else A.real), dtype=np.complex128)
+    out = T(np.zeros(k + 2))
+    its = ctypes.c_int(0)
+    Ht = T(Hm)
+    assert lib().lindx_ritz_near(P(Ht), k, 1.0, 0.0, P(out), ctypes.byref(its), None) == 0
+    o = out.cpu().numpy()
+    theta, y, rin = o[0], o[1:k + 1], o[k + 1].real
+    w, V = np.linalg.eig(Hm)
+    i = int(np.argmin(np.abs(w - 1)))
+    scale = max(1.0, np.linalg.norm(Hm))
+    print(f"[case] ritz k={k} {kind}: theta {theta:.15g} ref {w[i]:.15g}, {its.value} iterations, rin {rin:.2e}",
+          flush=True)
+    assert abs(theta - w[i]) <= 1e-12 * scale
+    v = V[:, i] / np.linalg.norm(V[:, i])
+    ph = np.vdot(v, y)
+    assert np.linalg.norm(y - v * ph / abs(ph)) <= 1e-9
+    assert abs(np.linalg.norm(y) - 1) < 1e-13
+    j = int(np.argmax(np.abs(y)))
+    assert abs(y[j].imag) <= 1e-14 and y[j].real > 0
+    r_host = np.linalg.norm(Hm @ y - theta * y)
+    assert abs(rin - r_host) <= 1e-12 * scale + 1e-3 * r_host
 
 
 @pytest.mark.parametrize("n", [37, 130, 300])
