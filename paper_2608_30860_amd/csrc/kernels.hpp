@@ -33,6 +33,10 @@ struct GemmDesc {
 };
 // workspace bytes gemm() needs for a split-K launch of this shape (0 if it would not split)
 long long gemm_ws_bytes(int prec, int M, int N, int nbatch);
+// Phi(xi) = -sum_j Lt_j [(V^H xi V) / (s_a + conj s_b)] Lt_j^H for n <= 32 in one workgroup (FP64;
+// all operands complex128 row-major on the device, Lt stacked d x n x n)
+int phi_small(const zd* xi, const zd* V, const zd* Lt, const zd* s, const zd* sbar, int n, int d, zd* out,
+              hipStream_t st);
 
 // prec = PREC_F64: A, B, C, E are complex128.
 // prec = PREC_F32 / PREC_BF16X3: A, B are complex64; C (and E) complex64 unless out64.

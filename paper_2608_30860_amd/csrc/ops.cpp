@@ -292,6 +292,12 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian) {
     return 0;
   }
   const int sp = c.prof_begin(PROF_PHI);
+  if (prec == PREC_F64 && n <= 32) {
+    // small system: one workgroup instead of the chain of product launches
+    TRY(phi_small(xi, c.V, c.Lt, c.s, c.sbar, n, d, out, c.st));
+    c.prof_end(sp);
+    return 0;
+  }
   if (prec == PREC_F64) {
     int s0 = c.prof_begin(PROF_BASIS_IN);
     TRY(op_gemm(c, PREC_F64, n, n, n, c.V, n, OP_C, xi, n, OP_N, c.w1, n, one, 0));

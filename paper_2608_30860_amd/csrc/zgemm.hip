@@ -770,6 +770,78 @@ __global__ __launch_bounds__(512) void zgemm32_dma(GemmDesc g, int a_bytes, int 
       }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Phi of a small system in one workgroup (n <= 32, FP64, eigen route): Xh = (V^H xi V) / (s_a +
+// conj s_b), then -sum_j Lt_j Xh Lt_j^H with each Lt_j staged in LDS in turn.  At this size the
+// matrix work is a few microseconds of FP64 arithmetic and the general path's chain of launches
+// would be all of the cost.  Thread t holds the entries t + 256 u (u < 4) of the 32 x 32 tile.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_phi_small(const zd* __restrict__ xi, const zd* __restrict__ V,
+                                                   const zd* __restrict__ Lt, const zd* __restrict__ s,
+                                                   const zd* __restrict__ sbar, int n, int d, zd* __restrict__ out) {
+  __shared__ zd A[32][33], B[32][33], X[32][33];
+  const int t = threadIdx.x;
+  int er[4], eq[4];
+  bool ok[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = t + 256 * u;
+    er[u] = e >> 5;
+    eq[u] = e & 31;
+    ok[u] = er[u] < n && eq[u] < n;
+    A[er[u]][eq[u]] = ok[u] ? xi[er[u] * n + eq[u]] : zmk(0, 0);
+    B[er[u]][eq[u]] = ok[u] ? V[er[u] * n + eq[u]] : zmk(0, 0);
+  }
+  __syncthreads();
+  // V^H xi
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    zd acc = zmk(0, 0);
+    for (int k = 0; k < n; ++k) acc = zadd(acc, zcmul(B[k][er[u]], A[k][eq[u]]));
+    X[er[u]][eq[u]] = acc;
+  }
+  __syncthreads();
+  // Xh = (V^H xi V) / (s_a + conj s_b), into A
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    zd acc = zmk(0, 0);
+    for (int k = 0; k < n; ++k) acc = zadd(acc, zmul(X[er[u]][k], B[k][eq[u]]));
+    A[er[u]][eq[u]] = ok[u] ? zdiv(acc, zadd(s[er[u]], sbar[eq[u]])) : zmk(0, 0);
+  }
+  zd o[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) o[u] = zmk(0, 0);
+  for (int j = 0; j < d; ++j) {
+    __syncthreads();
+    const zd* L = Lt + (long long)j * n * n;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) B[er[u]][eq[u]] = ok[u] ? L[er[u] * n + eq[u]] : zmk(0, 0);
+    __syncthreads();
+    // Y = Lt_j Xh
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      zd acc = zmk(0, 0);
+      for (int k = 0; k < n; ++k) acc = zadd(acc, zmul(B[er[u]][k], A[k][eq[u]]));
+      X[er[u]][eq[u]] = acc;
+    }
+    __syncthreads();
+    // += Y Lt_j^H
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      for (int k = 0; k < n; ++k) o[u] = zadd(o[u], zmul(X[er[u]][k], zconj(B[eq[u]][k])));
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (ok[u]) out[er[u] * n + eq[u]] = zmk(-o[u].x, -o[u].y);
+}
+
+int phi_small(const zd* xi, const zd* V, const zd* Lt, const zd* s, const zd* sbar, int n, int d, zd* out,
+              hipStream_t st) {
+  if (n < 1 || n > 32 || d < 1) return -1;
+  hipLaunchKernelGGL(k_phi_small, dim3(1), dim3(256), 0, st, xi, V, Lt, s, sbar, n, d, out);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 // bytes an operand spans (batches included), or -1 past the reach of a 32-bit buffer offset
 static long long z64_extent(long long rows, long long cols, long long ld, long long bstride, int nbatch) {
   if (rows <= 0 || cols <= 0) return 0;

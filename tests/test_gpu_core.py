@@ -49,7 +49,8 @@ def relerr(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-CASES = [("random", 37, 3), ("random", 130, 2), ("kerr", 32, 1), ("random", 200, 5), ("paper", 65, 3)]
+CASES = [("random", 37, 3), ("random", 130, 2), ("kerr", 32, 1), ("random", 200, 5), ("paper", 65, 3),
+         ("random", 17, 4)]
 
 
 @pytest.mark.parametrize("kind,n,d", CASES)
