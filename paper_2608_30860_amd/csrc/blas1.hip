@@ -212,6 +212,37 @@ int scale_by_inv(zd* w, long long len, const double* s, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
+// The end of Arnoldi step j: w <- w / s, and the step's column of the Hessenberg matrix written on
+// the device, so that the host need not read it back at every step.  Workgroup 0 stores
+// Hd[i][j] = h1[i] + h2[i] (i <= j, the two Gram-Schmidt passes), Hd[j+1][j] = s and sub[j] = s.
+// A norm that is not positive (breakdown: w is exactly zero) leaves w as it is.
+__global__ void k_scale_inv_hcol(zd* w, long long len, const double* s, const zd* h1, const zd* h2, zd* Hd,
+                                 int ld, int j, double* sub) {
+  const double sv = s[0];
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+      const zd a = h1[i], b = h2[i];
+      Hd[(long long)i * ld + j] = zmk(a.x + b.x, a.y + b.y);
+    }
+    if (threadIdx.x == 0) {
+      Hd[(long long)(j + 1) * ld + j] = zmk(sv, 0.0);
+      sub[j] = sv;
+    }
+  }
+  if (!(sv > 0)) return;
+  const double f = 1.0 / sv;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    zd x = w[i];
+    w[i] = zmk(x.x * f, x.y * f);
+  }
+}
+int scale_by_inv_hcol(zd* w, long long len, const double* s, const zd* h1, const zd* h2, zd* Hd, int ld, int j,
+                      double* sub, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_inv_hcol, dim3(grid_for(len)), dim3(RB), 0, st, w, len, s, h1, h2, Hd, ld, j, sub);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 __global__ void k_axpby(zd a, const zd* x, zd b, zd* y, long long len) {
   long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {

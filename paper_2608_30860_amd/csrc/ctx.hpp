@@ -184,14 +184,15 @@ struct lind_ctx {
   lindx::Ctx c;
   lindx::zd *rhoB = nullptr, *resB = nullptr, *xiB = nullptr, *zetaB = nullptr, *delB = nullptr;
   lindx::zd *hm = nullptr, *ev = nullptr, *Yv = nullptr, *yv = nullptr;
+  lindx::zd* hd = nullptr;  // (m + 1) x m Hessenberg matrix of the steady-state Arnoldi cycle
   int* sinfo = nullptr;
 };
 
 namespace lindx {
 // helpers shared by the drivers (lind.cpp)
 int ensure_solver_bufs(lind_ctx* X);
-int ritz_near_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, cplx& theta, std::vector<cplx>& y,
-                   double& rin);
+int ritz_near_dev(lind_ctx* X, const zd* Hd, int ld, int& k, const double* sub, cplx& theta, std::vector<cplx>& y,
+                  double& rin, double& hn);
 int small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, std::vector<cplx>& w,
                    std::vector<cplx>& Y);
 int upload_vec(lind_ctx* X, const cplx* v, int k, zd* dst);

@@ -97,6 +97,10 @@ int multi_axpy(const zd* V, long long ld, int k, const zd* h, zd* w, long long l
 int nrm2(const zd* w, long long len, double* out, double* scratch, hipStream_t st);
 // w *= 1/s where s is a device double (scalar produced by nrm2)
 int scale_by_inv(zd* w, long long len, const double* s, hipStream_t st);
+// as scale_by_inv (no scaling when s <= 0), and column j of the device Hessenberg matrix Hd (row stride
+// ld): Hd[i][j] = h1[i] + h2[i] for i <= j, Hd[j+1][j] = s, sub[j] = s
+int scale_by_inv_hcol(zd* w, long long len, const double* s, const zd* h1, const zd* h2, zd* Hd, int ld, int j,
+                      double* sub, hipStream_t st);
 // y = a*x + b*y with host scalars
 int axpby(zd a, const zd* x, zd b, zd* y, long long len, hipStream_t st);
 int copy(const zd* x, zd* y, long long len, hipStream_t st);

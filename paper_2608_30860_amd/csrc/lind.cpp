@@ -293,7 +293,7 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
   rc |= c.alloc(&c.w1, n2); rc |= c.alloc(&c.w2, n2); rc |= c.alloc(&c.w3, n2); rc |= c.alloc(&c.w4, n2);
   rc |= c.alloc(&c.Ys, nd); rc |= c.alloc(&c.dsc, 1024); rc |= c.alloc(&c.dscr, (size_t)c.dscr_len);
   rc |= c.alloc(&X->hm, 64 * 64); rc |= c.alloc(&X->ev, 64); rc |= c.alloc(&X->Yv, 64 * 64);
-  rc |= c.alloc(&X->yv, 64); rc |= c.alloc(&X->sinfo, 16);
+  rc |= c.alloc(&X->yv, 64); rc |= c.alloc(&X->sinfo, 16); rc |= c.alloc(&X->hd, 65 * 64);
   if (c.prec != PREC_F64) {
     rc |= c.alloc(&c.U32, n2); rc |= c.alloc(&c.V32, n2); rc |= c.alloc(&c.Z32, n2);
     rc |= c.alloc(&c.Lt32, nd); rc |= c.alloc(&c.a32, n2); rc |= c.alloc(&c.b32, n2); rc |= c.alloc(&c.Y32, nd);
@@ -499,23 +499,34 @@ int lindx::small_eig_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int 
   return info ? LIND_ENOCONV : 0;
 }
 
-// Ritz pair of the k x k leading block of the host Hessenberg matrix Hh (row stride ld) whose
-// value is nearest 1: theta, the unit-norm vector y (largest entry real positive) and the residual
-// ||H y - theta y|| inside the Krylov space
-int lindx::ritz_near_host(lind_ctx* X, const std::vector<cplx>& Hh, int ld, int k, cplx& theta, std::vector<cplx>& y,
-                          double& rin) {
+// Ritz pair of the k x k leading block of the device Hessenberg matrix Hd (row stride ld) whose
+// value is nearest 1: theta, the unit-norm vector y (largest entry real positive; it also stays on
+// the device at Yv + 1) and the residual ||H y - theta y|| inside the Krylov space.  The
+// subdiagonal entries sub[0 .. k) come back in the same synchronisation: an exact zero among the
+// first k - 1 (an invariant Krylov space) cuts k to the first such column and the pair is taken
+// again there.  hn = sub[k - 1] for the k finally used.
+int lindx::ritz_near_dev(lind_ctx* X, const zd* Hd, int ld, int& k, const double* sub, cplx& theta,
+                         std::vector<cplx>& y, double& rin, double& hn) {
   Ctx& c = X->c;
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) c.hsc[i * k + j] = zmk(Hh[(size_t)i * ld + j].real(), Hh[(size_t)i * ld + j].imag());
-  if (hipMemcpyAsync(X->hm, c.hsc, sizeof(zd) * k * k, hipMemcpyHostToDevice, c.st) != hipSuccess) return LIND_EDEVICE;
-  TRY(ritz_near(X->hm, k, k, zmk(1.0, 0.0), X->Yv, X->sinfo, c.st));
-  if (hipMemcpyAsync(c.hsc, X->Yv, sizeof(zd) * (k + 2), hipMemcpyDeviceToHost, c.st) != hipSuccess)
-    return LIND_EDEVICE;
-  TRY(c.sync());
-  theta = cplx(c.hsc[0].x, c.hsc[0].y);
-  y.resize(k);
-  for (int i = 0; i < k; ++i) y[i] = cplx(c.hsc[1 + i].x, c.hsc[1 + i].y);
-  rin = c.hsc[k + 1].x;
+  for (int pass = 0; pass < 2; ++pass) {
+    TRY(ritz_near(Hd, ld, k, zmk(1.0, 0.0), X->Yv, X->sinfo, c.st));
+    if (hipMemcpyAsync(c.hsc, X->Yv, sizeof(zd) * (k + 2), hipMemcpyDeviceToHost, c.st) != hipSuccess)
+      return LIND_EDEVICE;
+    if (hipMemcpyAsync(c.hsc + 80, sub, sizeof(double) * k, hipMemcpyDeviceToHost, c.st) != hipSuccess)
+      return LIND_EDEVICE;
+    TRY(c.sync());
+    const double* hs = (const double*)(c.hsc + 80);
+    int kb = k;
+    for (int i = 0; i + 1 < k; ++i)
+      if (hs[i] == 0.0) { kb = i + 1; break; }
+    if (kb < k && pass == 0) { k = kb; continue; }
+    hn = hs[k - 1];
+    theta = cplx(c.hsc[0].x, c.hsc[0].y);
+    y.resize(k);
+    for (int i = 0; i < k; ++i) y[i] = cplx(c.hsc[1 + i].x, c.hsc[1 + i].y);
+    rin = c.hsc[k + 1].x;
+    break;
+  }
   return std::isfinite(rin) && std::isfinite(theta.real()) ? 0 : LIND_ENOCONV;
 }
 
@@ -606,7 +617,6 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
   const double eps_floor = (p == PREC_F64) ? 0.0 : (p == PREC_F32 ? 1e-6 : 3e-3);
   double best = 1e300, best_max = 0;
   bool converged = false;
-  std::vector<cplx> Hh((size_t)(m + 1) * m);
   double colsum = 0, mx = 0, fro = 0;
   bool floor_hit = false;
   bool best_is_last = false;  // rhoB / resB hold the best state and its FP64 residual
@@ -622,12 +632,18 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
     floor_hit = false;
     for (int rs = 0; restarts_left > 0 && !converged; ++rs) {
       --restarts_left;
-      std::fill(Hh.begin(), Hh.end(), cplx(0));
       int k = 0, k_ritz = 0;  // k_ritz: the Krylov dimension the Ritz pair (theta, ysel) belongs to
       double est = 1e300;
       cplx theta(0.0, 0.0);
       double rin = 0.0;
       std::vector<cplx> ysel;
+      // The Hessenberg matrix is built on the device (row stride m; the entries below the
+      // subdiagonal stay zero) and read back only when a Ritz pair is evaluated, so that the steps
+      // in between queue without a host round trip.  A breakdown (zero norm) leaves the next
+      // vectors zero until that evaluation finds it and cuts the space there.
+      if (hipMemsetAsync(X->hd, 0, sizeof(zd) * (size_t)(m + 1) * m, c.st) != hipSuccess) return LIND_EDEVICE;
+      double* subd = (double*)(c.dsc + 400);
+      double hn = 0.0;
       for (int j = 0; j < m; ++j) {
         zd* vj = K + (long long)j * n2;
         zd* wv = K + (long long)(j + 1) * n2;
@@ -640,18 +656,13 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
         TRY(multi_dot(K, n2, j + 1, wv, n2, h2, (zd*)c.dscr, c.st));
         TRY(multi_axpy(K, n2, j + 1, h2, wv, n2, 1, -1.0, c.st));
         TRY(nrm2(wv, n2, (double*)(c.dsc + 4), c.dscr, c.st));
-        TRY(c.fetch(c.dsc, sizeof(zd) * 160));
-        double hn = ((const double*)(c.hsc + 4))[0];
-        for (int i = 0; i <= j; ++i)
-          Hh[(size_t)i * m + j] = cplx(c.hsc[8 + i].x + c.hsc[80 + i].x, c.hsc[8 + i].y + c.hsc[80 + i].y);
-        Hh[(size_t)(j + 1) * m + j] = hn;
-        if (hn > 0) TRY(scale_by_inv(wv, n2, (const double*)(c.dsc + 4), c.st));
+        TRY(scale_by_inv_hcol(wv, n2, (const double*)(c.dsc + 4), h1, h2, X->hd, m, j, subd, c.st));
         k = j + 1;
-        bool check = (k >= 3 && (k % 2 == 1)) || k == m || hn == 0.0;
+        bool check = (k >= 3 && (k % 2 == 1)) || k == m;
         if (check) {
           // Ritz pair nearest 1; the estimate also carries the pair's residual inside the
           // Krylov space, which is zero for an exact eigenpair of H
-          TRY(ritz_near_host(X, Hh, m, k, theta, ysel, rin));
+          TRY(ritz_near_dev(X, X->hd, m, k, subd, theta, ysel, rin, hn));
           k_ritz = k;
           est = std::sqrt(std::norm(theta - 1.0) + rin * rin + hn * hn * std::norm(ysel[k - 1]));
           if (c_scale * est <= std::max(0.25 * tol, eps_floor) || hn == 0.0) break;
@@ -659,10 +670,9 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
         if (deadline > 0 && now_s() > deadline) break;
       }
       // the cycle may end (time limit) at a step without a Ritz evaluation: evaluate it for this k
-      if (k_ritz != k) TRY(ritz_near_host(X, Hh, m, k, theta, ysel, rin));
-      // Ritz vector xi = V_k y
-      TRY(upload_vec(X, ysel.data(), k, X->yv));
-      TRY(multi_axpy(K, n2, k, X->yv, X->xiB, n2, 0, 1.0, c.st));
+      if (k_ritz != k) TRY(ritz_near_dev(X, X->hd, m, k, subd, theta, ysel, rin, hn));
+      // Ritz vector xi = V_k y (y left on the device by the last evaluation)
+      TRY(multi_axpy(K, n2, k, X->Yv + 1, X->xiB, n2, 0, 1.0, c.st));
       // the fixed point xi = -S(rho_inf) is Hermitian: keep the restart vector Hermitian
       TRY(hermitize(X->xiB, n, 0, nullptr, c.dscr, c.st));
       // rho = -S^{-1} xi, hermitised and normalised (the sign cancels in the normalisation)
