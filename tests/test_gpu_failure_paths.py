@@ -7,6 +7,8 @@ made to fail).
 * lind_create refuses non-finite H or L_j with LIND_EINVAL.
 * The reductions use no atomics: two FP64 (or BF16x3) solves, on one context or on two contexts
   built from the same input, agree bit for bit.
+* An Arnoldi breakdown (the Krylov space invariant after one step) ends the cycle with the exact
+  fixed point instead of a division by the zero norm.
 """
 import numpy as np
 import pytest
@@ -103,3 +105,24 @@ def test_solves_are_bitwise_deterministic(prec, n, d):
         assert torch.equal(a.factor(which), b.factor(which)), which
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_invariant_krylov_space_at_the_first_step(prec):
+    """With L_1 = I and H diagonal every diagonal state is steady and Phi is the identity on
+    diagonal matrices, so the first Krylov vector (the start I/n turned into -S(I/n)) spans an
+    invariant space: the Arnoldi step's norm is zero (up to rounding) and the driver must stop
+    there with the Ritz value 1 and return I/n, without dividing by the zero norm."""
+    n = 4
+    H = np.diag([0.3, -0.1, 0.7, 0.2]).astype(np.complex128)
+    Ls = [np.eye(n, dtype=np.complex128)]
+    Ht, Lt = _dev(H, Ls)
+    m = Lindblad(Ht, Lt, prec=prec, m=8)
+    r = m.steady_state(1e-12)
+    print(prec, r.info, flush=True)
+    rho = r.rho.cpu().numpy()
+    assert r.info["status"] == LIND_OK
+    assert np.all(np.isfinite(rho))
+    assert ol.trace_distance(rho, np.eye(n) / n) <= 1e-12
+    assert r.info["n_phi"] <= 3
+    m.close()
