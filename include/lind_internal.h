@@ -90,6 +90,13 @@ int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch,
 int lindx_cgs2(const void* V, long long ld, int k, void* w, long long len, void* h, void* nrm, int reps,
                void* stream);
 
+/* The same step in one workgroup, as the steady-state Arnoldi driver runs it for systems of at most
+   4096 entries: afterwards w holds w2 / ||w2|| (w2 unchanged when ||w2|| = 0), hcol (device, k + 1
+   complex128) the Hessenberg column [h1 + h2; ||w2||] and nrm (device double) ||w2||.  k <= 64,
+   len <= 4096.  Synchronous; allocates the column workspace.  Returns 0, -1 for invalid arguments,
+   -4, -5. */
+int lindx_cgs2_small(const void* V, long long ld, int k, void* w, long long len, void* hcol, void* nrm, void* stream);
+
 /* out = L(X) for the context's Lindbladian with BF16x3 products on pre-split planes (the operator
    of the inner shift-invert solves of lind_eigs in BF16x3 contexts); X, out: device n x n
    complex128, may not alias.  The planes of G and the L_j are split on the first call (eigenbasis

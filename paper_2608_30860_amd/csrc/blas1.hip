@@ -243,6 +243,81 @@ int scale_by_inv_hcol(zd* w, long long len, const double* s, const zd* h1, const
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
+// The whole CGS2 step of Arnoldi for a small system in one workgroup: w (len <= CG_MAXLEN
+// entries) is held in LDS, each pass takes the k dot products with the basis (wave c of the
+// workgroup owns basis vectors c, c + CG_W, ...) and then the update of w, and the step ends with
+// the norm, the scaling and the Hessenberg column (the same outputs as scale_by_inv_hcol after
+// two multi_dot / multi_axpy passes and nrm2).  Each basis vector is read once per dot and once
+// per update from L2; no partial sums leave the workgroup, so one launch replaces eight.
+static constexpr int CG_T = 1024;
+static constexpr int CG_W = CG_T / 64;
+static constexpr int CG_MAXLEN = 4096;
+__global__ __launch_bounds__(CG_T) void k_cgs2_small(const zd* __restrict__ V, long long ld, int k,
+                                                     zd* __restrict__ w, int len, zd* __restrict__ Hd, int ldh,
+                                                     double* __restrict__ sub) {
+  __shared__ zd ws[CG_MAXLEN];
+  __shared__ zd hs[64];
+  __shared__ double red[CG_W];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int i = t; i < len; i += CG_T) ws[i] = w[i];
+  zd hacc = zmk(0.0, 0.0);
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int c = wv; c < k; c += CG_W) {
+      const zd* Vc = V + (long long)c * ld;
+      double sr = 0, si = 0;
+      for (int i = lane; i < len; i += 64) {
+        const zd v = Vc[i], x = ws[i];
+        sr += v.x * x.x + v.y * x.y;
+        si += v.x * x.y - v.y * x.x;
+      }
+      sr = warp_sum(sr);
+      si = warp_sum(si);
+      if (lane == 0) hs[c] = zmk(sr, si);
+    }
+    __syncthreads();
+    if (t < k) hacc = zmk(hacc.x + hs[t].x, hacc.y + hs[t].y);
+    for (int i = t; i < len; i += CG_T) {
+      double ar = 0, ai = 0;
+      for (int c = 0; c < k; ++c) {
+        const zd v = V[(long long)c * ld + i], h = hs[c];
+        ar += h.x * v.x - h.y * v.y;
+        ai += h.x * v.y + h.y * v.x;
+      }
+      const zd x = ws[i];
+      ws[i] = zmk(x.x - ar, x.y - ai);
+    }
+    __syncthreads();
+  }
+  double sq = 0;
+  for (int i = t; i < len; i += CG_T) {
+    const zd x = ws[i];
+    sq += x.x * x.x + x.y * x.y;
+  }
+  sq = warp_sum(sq);
+  if (lane == 0) red[wv] = sq;
+  __syncthreads();
+  double tot = 0;
+  for (int q = 0; q < CG_W; ++q) tot += red[q];
+  const double nrm = sqrt(tot);
+  const int j = k - 1;
+  if (t < k) Hd[(long long)t * ldh + j] = hacc;
+  if (t == 0) {
+    Hd[(long long)(j + 1) * ldh + j] = zmk(nrm, 0.0);
+    sub[j] = nrm;
+  }
+  const double f = nrm > 0 ? 1.0 / nrm : 1.0;
+  for (int i = t; i < len; i += CG_T) {
+    const zd x = ws[i];
+    w[i] = zmk(x.x * f, x.y * f);
+  }
+}
+int cgs2_small(const zd* V, long long ld, int k, zd* w, long long len, zd* Hd, int ldh, double* sub, hipStream_t st) {
+  if (len < 1 || len > CG_MAXLEN || k < 1 || k > 64) return -1;
+  hipLaunchKernelGGL(k_cgs2_small, dim3(1), dim3(CG_T), 0, st, V, ld, k, w, (int)len, Hd, ldh, sub);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
 __global__ void k_axpby(zd a, const zd* x, zd b, zd* y, long long len) {
   long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {

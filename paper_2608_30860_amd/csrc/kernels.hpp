@@ -101,6 +101,9 @@ int scale_by_inv(zd* w, long long len, const double* s, hipStream_t st);
 // ld): Hd[i][j] = h1[i] + h2[i] for i <= j, Hd[j+1][j] = s, sub[j] = s
 int scale_by_inv_hcol(zd* w, long long len, const double* s, const zd* h1, const zd* h2, zd* Hd, int ld, int j,
                       double* sub, hipStream_t st);
+// the two CGS2 passes of Arnoldi step j = k - 1 against V_0 .. V_{k-1}, the norm, the scaling of w and
+// its Hessenberg column (as above) in one workgroup, for len <= 4096 entries and k <= 64; -1 otherwise
+int cgs2_small(const zd* V, long long ld, int k, zd* w, long long len, zd* Hd, int ldh, double* sub, hipStream_t st);
 // y = a*x + b*y with host scalars
 int axpby(zd a, const zd* x, zd b, zd* y, long long len, hipStream_t st);
 int copy(const zd* x, zd* y, long long len, hipStream_t st);

@@ -649,14 +649,19 @@ int lindx::steady_state_impl(lind_ctx* ctx, double tol, const zd* rho0, zd* rho_
         zd* wv = K + (long long)(j + 1) * n2;
         TRY(op_phi(c, vj, wv, p, true));  // Krylov vectors of a Hermitian start stay Hermitian
         ++inf.n_phi;
-        zd* h1 = c.dsc + 8;
-        zd* h2 = c.dsc + 80;
-        TRY(multi_dot(K, n2, j + 1, wv, n2, h1, (zd*)c.dscr, c.st));
-        TRY(multi_axpy(K, n2, j + 1, h1, wv, n2, 1, -1.0, c.st));
-        TRY(multi_dot(K, n2, j + 1, wv, n2, h2, (zd*)c.dscr, c.st));
-        TRY(multi_axpy(K, n2, j + 1, h2, wv, n2, 1, -1.0, c.st));
-        TRY(nrm2(wv, n2, (double*)(c.dsc + 4), c.dscr, c.st));
-        TRY(scale_by_inv_hcol(wv, n2, (const double*)(c.dsc + 4), h1, h2, X->hd, m, j, subd, c.st));
+        if (n2 <= 4096) {
+          // small systems: the whole CGS2 step in one workgroup (launch latency dominates here)
+          TRY(cgs2_small(K, n2, j + 1, wv, n2, X->hd, m, subd, c.st));
+        } else {
+          zd* h1 = c.dsc + 8;
+          zd* h2 = c.dsc + 80;
+          TRY(multi_dot(K, n2, j + 1, wv, n2, h1, (zd*)c.dscr, c.st));
+          TRY(multi_axpy(K, n2, j + 1, h1, wv, n2, 1, -1.0, c.st));
+          TRY(multi_dot(K, n2, j + 1, wv, n2, h2, (zd*)c.dscr, c.st));
+          TRY(multi_axpy(K, n2, j + 1, h2, wv, n2, 1, -1.0, c.st));
+          TRY(nrm2(wv, n2, (double*)(c.dsc + 4), c.dscr, c.st));
+          TRY(scale_by_inv_hcol(wv, n2, (const double*)(c.dsc + 4), h1, h2, X->hd, m, j, subd, c.st));
+        }
         k = j + 1;
         bool check = (k >= 3 && (k % 2 == 1)) || k == m;
         if (check) {

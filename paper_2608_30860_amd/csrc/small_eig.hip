@@ -83,7 +83,7 @@ __global__ __launch_bounds__(64) void k_small_eig(const zd* A, int lda, int m, z
 // One wave; lane c owns column c in the elimination and row c in the substitutions.
 __global__ __launch_bounds__(64) void k_ritz_near(const zd* H, int ld, int k, zd sigma, zd* out, int* info) {
   __shared__ zd A[64 * LDM];
-  __shared__ zd x[64], b[64];
+  __shared__ zd x[64];
   __shared__ zd lf[64];
   __shared__ int piv[64];
   const int t = threadIdx.x;
@@ -121,26 +121,37 @@ __global__ __launch_bounds__(64) void k_ritz_near(const zd* H, int ld, int k, zd
     __syncthreads();
   }
   if (t == 0 && cabs1(A[(k - 1) * LDM + k - 1]) < tiny) A[(k - 1) * LDM + k - 1] = zmk(tiny, 0);
-  // start: all ones (a fixed vector, so the result is deterministic)
-  if (t < k) x[t] = zmk(1.0 / sqrt((double)k), 0);
   __syncthreads();
+  // per-lane operands of the substitutions: lane j holds l_j and the swap flag of elimination step
+  // j and the reciprocal of U_jj, so that both substitutions pass their running value by
+  // v_readlane instead of an LDS round trip per row
+  const zd lj = (t + 1 < k) ? lf[t] : zmk(0, 0);
+  const int pj = (t + 1 < k) ? piv[t] : 0;
+  const zd rj = t < k ? zdiv(zmk(1.0, 0.0), A[t * LDM + t]) : zmk(0, 0);
+  // start: all ones (a fixed vector, so the result is deterministic)
+  zd xr = t < k ? zmk(1.0 / sqrt((double)k), 0) : zmk(0, 0);
   int it = 0;
   double dprev = 1e300;
   for (; it < 60; ++it) {
-    // forward: the row swaps and eliminations applied to b = x
-    if (t == 0) {
-      for (int i = 0; i < k; ++i) b[i] = x[i];
-      for (int j = 0; j + 1 < k; ++j) {
-        if (piv[j]) { const zd u = b[j]; b[j] = b[j + 1]; b[j + 1] = u; }
-        b[j + 1] = zsub(b[j + 1], zmul(lf[j], b[j]));
-      }
+    // forward: the row swaps and eliminations applied to x.  Step j leaves its final entry j
+    // (row j + 1's original value if the rows were swapped, else the running value) and carries
+    // the updated row j + 1 on.
+    zd carry = zreadlane(xr, 0);
+    zd bi = zmk(0, 0);
+    for (int j = 0; j + 1 < k; ++j) {
+      const zd nb = zreadlane(xr, j + 1);
+      const zd l = zreadlane(lj, j);
+      const bool sw = __builtin_amdgcn_readlane(pj, j) != 0;
+      const zd fin = sw ? nb : carry;
+      const zd oth = sw ? carry : nb;
+      if (t == j) bi = fin;
+      carry = zsub(oth, zmul(l, fin));
     }
-    __syncthreads();
+    if (t == k - 1) bi = carry;
     // back substitution, column oriented: x_i = b_i / U_ii, then b_r -= U_ri x_i for r < i
-    zd bi = t < k ? b[t] : zmk(0, 0);
     zd xi = zmk(0, 0);
     for (int i = k - 1; i >= 0; --i) {
-      const zd xv = zdiv(zmk(__shfl(bi.x, i, 64), __shfl(bi.y, i, 64)), A[i * LDM + i]);
+      const zd xv = zmul(zreadlane(bi, i), zreadlane(rj, i));
       if (t == i) xi = xv;
       if (t < i) bi = zsub(bi, zmul(A[t * LDM + i], xv));
     }
@@ -149,7 +160,7 @@ __global__ __launch_bounds__(64) void k_ritz_near(const zd* H, int ld, int k, zd
     double nn = t < k ? zabs2(xi) : 0.0;
     for (int o = 32; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 64);
     xi = zscale(xi, 1.0 / sqrt(nn));
-    const zd old = t < k ? x[t] : zmk(0, 0);
+    const zd old = xr;
     zd ov = zcmul(xi, old);  // <new, old>
     for (int o = 32; o > 0; o >>= 1) {
       ov.x += __shfl_xor(ov.x, o, 64);
@@ -160,13 +171,13 @@ __global__ __launch_bounds__(64) void k_ritz_near(const zd* H, int ld, int k, zd
     xi = zmul(xi, rot);  // same phase as the old vector
     double dd = t < k ? zabs2(zsub(xi, old)) : 0.0;
     for (int o = 32; o > 0; o >>= 1) dd += __shfl_xor(dd, o, 64);
-    __syncthreads();
-    if (t < k) x[t] = xi;
-    __syncthreads();
+    xr = t < k ? xi : zmk(0, 0);
     const double dist = sqrt(dd);
     if (dist <= 4e-15 || (it >= 8 && dist >= 0.5 * dprev)) { ++it; break; }
     dprev = dist;
   }
+  if (t < k) x[t] = xr;
+  __syncthreads();
   // theta = y^H H y and the residual ||H y - theta y|| (H re-read from global memory)
   zd hy = zmk(0, 0);
   if (t < k)

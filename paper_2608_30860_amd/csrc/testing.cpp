@@ -223,3 +223,28 @@ extern "C" int lindx_cgs2(const void* V, long long ld, int k, void* w, long long
   hipFree(scr);
   return rc;
 }
+
+// The one-workgroup form of the same step used for small systems (len <= 4096, k <= 64): w is
+// replaced by w2 / ||w2||; hcol (device, k + 1 complex128) receives the Hessenberg column
+// (h1 + h2, then ||w2||) and nrm (device double) the norm as the driver's subdiagonal record.
+extern "C" int lindx_cgs2_small(const void* V, long long ld, int k, void* w, long long len, void* hcol, void* nrm,
+                                void* stream) {
+  if (!V || !w || !hcol || !nrm || k < 1 || k > 64 || len < 1 || len > 4096 || ld < len) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  zd* Hd = nullptr;
+  double* sub = nullptr;
+  if (hipMalloc(&Hd, sizeof(zd) * (size_t)(k + 1) * k) != hipSuccess) return -5;
+  if (hipMalloc(&sub, sizeof(double) * (size_t)k) != hipSuccess) {
+    hipFree(Hd);
+    return -5;
+  }
+  int rc = cgs2_small((const zd*)V, ld, k, (zd*)w, len, Hd, k, sub, st);
+  if (!rc && hipMemcpy2DAsync(hcol, sizeof(zd), Hd + (k - 1), sizeof(zd) * k, sizeof(zd), k + 1,
+                              hipMemcpyDeviceToDevice, st) != hipSuccess)
+    rc = -4;
+  if (!rc && hipMemcpyAsync(nrm, sub + (k - 1), sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) rc = -4;
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = -4;
+  hipFree(sub);
+  hipFree(Hd);
+  return rc;
+}

@@ -23,6 +23,7 @@ def lib():
     L.lindx_trisylv_blk.argtypes = [vp, vp, ci, cd, cd, cd, ctypes.POINTER(cd), vp]
     L.lindx_p4_test.argtypes = [vp, vp, ci, ci, ci, ci, ci, ci, ci, vp, vp, vp, vp]
     L.lindx_cgs2.argtypes = [vp, ll, ci, vp, ll, vp, vp, ci, vp]
+    L.lindx_cgs2_small.argtypes = [vp, ll, ci, vp, ll, vp, vp, vp]
     return L
 
 
@@ -374,6 +375,64 @@ def test_cgs2_step(k, length, pad):
     assert np.max(np.abs(h[k:] - h2)) <= 1e-13 * scale
     assert np.max(np.abs(w_d.cpu().numpy() - w2)) <= 1e-13 * scale
     assert abs(float(nrm_d.cpu()[0]) - np.linalg.norm(w2)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("k,length,pad", [(1, 1024, 0), (7, 1024, 0), (30, 1024, 0), (64, 4096, 0), (17, 1000, 24),
+                                          (5, 9, 3), (40, 4096, 0)])
+def test_cgs2_small_step(k, length, pad):
+    """The one-workgroup Gram-Schmidt step of small systems against NumPy and against the
+    multi-kernel step: the Hessenberg column h1 + h2 and ||w2||, the normalised vector.  Ragged
+    lengths, padded strides, k from 1 to the largest Krylov dimension."""
+    print(f"[case] cgs2_small k={k} len={length} pad={pad}", flush=True)
+    rng = np.random.default_rng(3 * k + length + pad)
+    ld = length + pad
+    Vh = crand(rng, k, length)
+    if k <= length:
+        Q, _ = np.linalg.qr(Vh.T)
+        Vh = Q.T.copy()
+    Vst = np.zeros((k, ld), dtype=np.complex128)
+    Vst[:, :length] = Vh
+    w0 = crand(rng, length)
+    V_d, w_d = T(Vst), T(w0)
+    hcol = torch.zeros(k + 1, dtype=torch.complex128, device="cuda:0")
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    assert lib().lindx_cgs2_small(P(V_d), ld, k, P(w_d), length, P(hcol), P(nrm), None) == 0
+    h1 = Vh.conj() @ w0
+    w1 = w0 - Vh.T @ h1
+    h2 = Vh.conj() @ w1
+    w2 = w1 - Vh.T @ h2
+    nw = np.linalg.norm(w2)
+    scale = np.linalg.norm(w0)
+    hc = hcol.cpu().numpy()
+    assert np.max(np.abs(hc[:k] - (h1 + h2))) <= 1e-13 * scale
+    assert abs(hc[k] - nw) <= 1e-12 * scale and hc[k].imag == 0
+    assert float(nrm.cpu()[0]) == hc[k].real
+    assert np.max(np.abs(w_d.cpu().numpy() - w2 / nw)) <= 1e-12 * scale / nw
+    # the multi-kernel step on the same input
+    w_m = T(w0)
+    h_m = torch.zeros(2 * k, dtype=torch.complex128, device="cuda:0")
+    n_m = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    assert lib().lindx_cgs2(P(V_d), ld, k, P(w_m), length, P(h_m), P(n_m), 1, None) == 0
+    hm = h_m.cpu().numpy()
+    assert np.max(np.abs(hc[:k] - (hm[:k] + hm[k:]))) <= 1e-13 * scale
+    assert abs(hc[k].real - float(n_m.cpu()[0])) <= 1e-13 * scale
+
+
+def test_cgs2_small_zero_norm():
+    """w exactly in the span of the basis (a breakdown; standard basis vectors keep every operation
+    exact): the column is the coefficients, the norm is exactly zero and w is left as the zero
+    vector instead of being divided by it."""
+    Vh = np.zeros((3, 64), dtype=np.complex128)
+    Vh[0, 0] = Vh[1, 5] = Vh[2, 9] = 1.0
+    w0 = Vh.T @ np.array([1.0, 0.5j, 0.25])
+    V_d, w_d = T(Vh), T(w0)
+    hcol = torch.zeros(4, dtype=torch.complex128, device="cuda:0")
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    assert lib().lindx_cgs2_small(P(V_d), 64, 3, P(w_d), 64, P(hcol), P(nrm), None) == 0
+    hc = hcol.cpu().numpy()
+    assert np.array_equal(hc, [1.0, 0.5j, 0.25, 0.0])
+    assert float(nrm.cpu()[0]) == 0.0
+    assert np.array_equal(w_d.cpu().numpy(), np.zeros(64))
 
 
 @pytest.mark.parametrize("n,d", [(200, 3), (256, 2), (1024, 4)])
