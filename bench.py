@@ -95,6 +95,30 @@ def cpu_alg4(n, d, seed, tol):
             "sample": f"one full solve at n={n}, d={d}, seed={seed} (includes eig(G) and the condition estimate)"}
 
 
+def small_steady_states(li, Lindblad, torch, np, dev, solves):
+    """Steady states of the small workloads, factorisation excluded: median of `solves` solves on one
+    context after a warm-up solve (these sizes are launch- and synchronisation-bound)."""
+    out = []
+    for wname, pc, tol in [("kerr32", "fp64", 1e-10), ("two_photon256", "fp64", 1e-10),
+                           ("two_photon256", "fp32", 1e-8)]:
+        Hc, Lc, _ = li.workload(wname)
+        mc = Lindblad(torch.from_numpy(Hc).to(dev), torch.from_numpy(np.stack(Lc)).to(dev), prec=pc)
+        mc.steady_state(tol)
+        ts = []
+        for _ in range(solves):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = mc.steady_state(tol)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        i = r.info
+        out.append({"workload": wname, "n": Hc.shape[0], "d": len(Lc), "prec": pc, "tol": tol,
+                    "median_ms": 1e3 * float(np.median(ts)), "n_phi": i["n_phi"], "n_restarts": i["n_restarts"],
+                    "n_refine": i["n_refine"], "resid_trace": i["resid_trace"]})
+        mc.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,8 +143,8 @@ def main():
     ap.add_argument("--eigs-mu", type=float, default=-0.7408,
                     help="shift of the spectrum measurement (0.03 right of the edge of the n = 2048, d = 8 workload)")
     ap.add_argument("--kernel-only", default=None,
-                    help="profiling mode: fp64 | fp32 | bf16x3 (the stacked jump product alone) or hbm "
-                         "(the bandwidth-bound kernels)")
+                    help="profiling mode: fp64 | fp32 | bf16x3 (the stacked jump product alone), hbm "
+                         "(the bandwidth-bound kernels) or small (steady states of the small workloads)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -153,6 +177,10 @@ def main():
     Lt = torch.from_numpy(np.stack(Ls)).to(dev)
     torch.cuda.synchronize()
 
+    if args.kernel_only == "small":
+        res = small_steady_states(li, Lindblad, torch, np, dev, 3)
+        log(f"[bench] kernel-only small: {res}")
+        return
     if args.kernel_only == "hbm":
         # counter runs of the bandwidth-bound kernels at the benchmarked size: three Gram-Schmidt
         # steps against 31 basis vectors (the longest step of an Arnoldi cycle of 30), then two mixed
@@ -500,6 +528,7 @@ def main():
     # Phi-applications per second on the other workloads (after the timed region): plain loops of
     # Phi on a seeded Hermitian state, per precision mode the workload is specified with
     per_config = None
+    small_ss = None
     if not args.no_configs:
         per_config = []
         for wname, precs, loops in [("kerr32", ["fp64"], 2000), ("two_photon256", ["fp64", "fp32"], 400),
@@ -525,6 +554,8 @@ def main():
                                    "phi_per_s": loops / dtc, "us_per_phi": 1e6 * dtc / loops, "create_s": tc})
                 mc.close()
         log(f"[bench] per-config Phi rates {per_config}")
+        small_ss = small_steady_states(li, Lindblad, torch, np, dev, 5)
+        log(f"[bench] small-workload steady states {small_ss}")
 
     cpu = None
     if not args.no_cpu:
@@ -544,7 +575,8 @@ def main():
                               "reported in time_to_tol", "parallelism": "single GPU"},
            "time_to_tol": t_to_tol, "roofline": roof, "kernels": other, "hbm_kernels": hbm, "cpu_baseline": cpu,
            "low_spectrum": spectrum,
-           "create_s": t_create, "resolvent": extras, "phi_rates": per_config}
+           "create_s": t_create, "resolvent": extras, "phi_rates": per_config,
+           "small_steady_states": small_ss}
     model.close()
     print(json.dumps(out), flush=True)
 

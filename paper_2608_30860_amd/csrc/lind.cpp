@@ -300,6 +300,9 @@ extern "C" int lind_create(lind_ctx** out, const void* H, const void* Ls, int n,
   }
   {
     long long wsb = std::max(gemm_ws_bytes(PREC_F64, n, n, std::max(d, 1)), gemm_ws_bytes(c.prec, n, n, std::max(d, 1)));
+    // single products of small systems split along K
+    wsb = std::max(wsb, gemm_ws_bytes(PREC_F64, n, n, 1));
+    if (d >= 1) wsb = std::max(wsb, gemm_ws_bytes(PREC_F64, d * n, n, 1));
     // room for up to 8 FP64 split-K partials (the Hermitian residual runs on half the tiles)
     if (d >= 2) wsb = std::max(wsb, (long long)std::min(d, 8) * n2 * 16);
     if (wsb > 0) rc |= c.alloc((char**)&c.gws, (size_t)wsb);

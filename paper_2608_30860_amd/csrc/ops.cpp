@@ -96,6 +96,7 @@ int op_gemm(Ctx& c, int prec, int M, int N, int K, const void* A, long long lda,
   g.C = C; g.ldc = ldc;
   g.ar = alpha.real(); g.ai = alpha.imag();
   g.beta = beta;
+  g.ws = c.gws; g.ws_bytes = c.gws_bytes;  // split-K room for small products
   return gemm(prec, g, c.st) ? LIND_EDEVICE : 0;
 }
 
@@ -142,6 +143,7 @@ int op_sinv(Ctx& c, const zd* Y, zd* X, cplx mu, int prec, bool adjoint) {
       g.dc = adjoint ? c.s : c.sbar;
       cplx m = adjoint ? std::conj(mu) : mu;
       g.dzr = -m.real(); g.dzi = -m.imag();
+      g.ws = c.gws; g.ws_bytes = c.gws_bytes;  // split-K room for small systems
       TRY(gemm(PREC_F64, g, c.st));
       TRY(op_gemm(c, PREC_F64, n, n, n, Q, n, OP_N, c.w2, n, OP_N, c.w1, n, one, 0));
       TRY(op_gemm(c, PREC_F64, n, n, n, c.w1, n, OP_N, Q, n, OP_C, X, n, one, 0));
@@ -161,6 +163,7 @@ int op_sinv(Ctx& c, const zd* Y, zd* X, cplx mu, int prec, bool adjoint) {
     g.dc = adjoint ? c.s : c.sbar;
     cplx m = adjoint ? std::conj(mu) : mu;
     g.dzr = -m.real(); g.dzi = -m.imag();
+    g.ws = c.gws; g.ws_bytes = c.gws_bytes;  // split-K room for small systems
     TRY(gemm(prec, g, c.st));
     TRY(op_gemm(c, prec, n, n, n, Q, n, OP_N, c.a32, n, OP_N, c.b32, n, one, 0));
     GemmDesc h;
@@ -308,6 +311,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian) {
     g.C = c.w2; g.ldc = n;
     g.epi = EPI_DIV; g.dr = c.s; g.dc = c.sbar;
     g.tri = hermitian;  // Hermitian xi: Xh = (V^H xi V) / (s_i + conj s_j) is Hermitian
+    g.ws = c.gws; g.ws_bytes = c.gws_bytes;  // split-K room for small systems
     TRY(gemm(PREC_F64, g, c.st));
     c.prof_end(s0);
     int s1 = c.prof_begin(PROF_JUMP_STACK);
@@ -376,6 +380,7 @@ int op_phi(Ctx& c, const zd* xi, zd* out, int prec, bool hermitian) {
   g.B = c.V32; g.ldb = n; g.opB = OP_N;
   g.C = c.a32; g.ldc = n;
   g.epi = EPI_DIV; g.dr = c.s; g.dc = c.sbar;
+  g.ws = c.gws; g.ws_bytes = c.gws_bytes;  // split-K room for small systems
   TRY(gemm(prec, g, c.st));
   c.prof_end(s0);
   int s1 = c.prof_begin(PROF_JUMP_STACK);

@@ -908,10 +908,46 @@ static int choose_split(int prec, int M, int N, int nbatch) {
   return s;
 }
 
+// tiles of the register-staged FP64 kernel for a product too small for 128 x 128 tiles: 64 x 64 when
+// they reach half the chip, else 32 x 32
+static int small_tile64(int M, int N, int nbatch) {
+  return ((long long)((M + 63) / 64) * ((N + 63) / 64) * nbatch >= 128) ? 64 : 32;
+}
+static long long small_tiles(int M, int N, int bt) { return (long long)((M + bt - 1) / bt) * ((N + bt - 1) / bt); }
+static bool f64_small(int M, int N, int nbatch) {
+  return (long long)((M + 127) / 128) * ((N + 127) / 128) * nbatch < 96;
+}
+// chunks of K for a single small FP64 product whose tiles leave most of the chip idle: the chunks
+// become the batches of a reduction (partials in the workspace), up to 8, each at least 32 deep
+static constexpr int kMaxKSplit = 8;
+static int ksplit_for(int M, int N, int K, long long tiles, long long ws_avail, int elem) {
+  int ks = 1;
+  while (ks * 2 <= kMaxKSplit && tiles * ks * 2 <= 256 && K % (ks * 2) == 0 && K / (ks * 2) >= 32 &&
+         (long long)(ks * 2) * M * N * elem <= ws_avail)
+    ks *= 2;
+  return ks;
+}
+// the FP32 products of this size run on 32 x 32 tiles of the register-staged kernel
+static bool f32_small32(int M, int N) {
+  return !(M >= 1024 && N >= 1024) && small_tiles(M, N, 64) < 96 && small_tiles(M, N, 32) < 128;
+}
+// a single product described as ks batches of K / ks (the reduction sums them)
+static void split_k_as_batches(GemmDesc& g, int ks) {
+  const int kc = g.K / ks;
+  g.K = kc;
+  g.nbatch = ks;
+  g.sA = g.opA == OP_N ? (long long)kc : (long long)kc * g.lda;
+  g.sB = g.opB == OP_N ? (long long)kc * g.ldb : (long long)kc;
+  g.nsplit = ks;
+}
+
 long long gemm_ws_bytes(int prec, int M, int N, int nbatch) {
   int s = choose_split(prec, M, N, nbatch);
-  if (s <= 1) return 0;
-  return (long long)s * M * N * (prec == PREC_F64 ? 16 : 8);
+  long long b = s > 1 ? (long long)s * M * N * (prec == PREC_F64 ? 16 : 8) : 0;
+  if (prec == PREC_F64 && nbatch == 1 && f64_small(M, N, 1) && small_tiles(M, N, small_tile64(M, N, 1)) < 128)
+    b = std::max(b, (long long)kMaxKSplit * M * N * 16);
+  if (prec == PREC_F32 && nbatch == 1 && f32_small32(M, N)) b = std::max(b, (long long)kMaxKSplit * M * N * 8);
+  return b;
 }
 
 int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
@@ -936,14 +972,19 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
       // too few 128 x 128 tiles (even split over every batch) to occupy the chip: 64 x 64 or
       // 32 x 32 tiles of the register-staged kernel, split-K over the batches
       g.tri = 0;
-      const int bt = ((long long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nbatch >= 128) ? 64 : 32;
-      const long long tiles = (long long)((g.M + bt - 1) / bt) * ((g.N + bt - 1) / bt);
+      const int bt = small_tile64(g.M, g.N, g.nbatch);
+      const long long tiles = small_tiles(g.M, g.N, bt);
       int s = 1;
       if (g0.ws)
         while (s * 2 <= g.nbatch && (g.nbatch % (s * 2)) == 0 && tiles * s < 512 &&
                (long long)(s * 2) * g.M * g.N * 16 <= ws_avail)
           s *= 2;
       g.nsplit = s;
+      if (g0.ws && g.nbatch == 1 && tiles < 128) {
+        // one product on a few dozen tiles: its K chunks as the batches of a reduction
+        const int ks = ksplit_for(g.M, g.N, g.K, tiles, ws_avail, 16);
+        if (ks > 1) split_k_as_batches(g, ks);
+      }
       rc = bt == 64 ? launch(zgemm_kernel<double, 64, 64, 16, double2>, 64, 64, g, st)
                     : launch(zgemm_kernel<double, 32, 32, 16, double2>, 32, 32, g, st);
       if (!rc && g.nsplit > 1) rc = launch_reduce<double2, double2>(g, st);
@@ -1009,6 +1050,12 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
         if (!rc && g.nsplit > 1) rc = g.out64 ? launch_reduce<float2, double2>(g, st) : launch_reduce<float2, float2>(g, st);
         return rc;
       }
+    }
+    if (g0.ws && g.nbatch == 1 && g.nsplit == 1 && f32_small32(g.M, g.N)) {
+      // one product on a few dozen 32 x 32 tiles: its K chunks as the batches of a reduction
+      const long long ws_avail = g0.ws_bytes > 0 ? g0.ws_bytes : gemm_ws_bytes(PREC_F32, g.M, g.N, 1);
+      const int ks = ksplit_for(g.M, g.N, g.K, small_tiles(g.M, g.N, 32), ws_avail, 8);
+      if (ks > 1) split_k_as_batches(g, ks);
     }
     // 128 x 128 tiles for split or large products, else 64 x 64; 32 x 32 when the larger tiles
     // would leave most of the chip idle
