@@ -917,7 +917,7 @@ static long long small_tiles(int M, int N, int bt) { return (long long)((M + bt 
 static bool f64_small(int M, int N, int nbatch) {
   return (long long)((M + 127) / 128) * ((N + 127) / 128) * nbatch < 96;
 }
-// chunks of K for a single small FP64 product whose tiles leave most of the chip idle: the chunks
+// chunks of K for a single small product whose tiles leave half the chip or more idle: the chunks
 // become the batches of a reduction (partials in the workspace), up to 8, each at least 32 deep
 static constexpr int kMaxKSplit = 8;
 static int ksplit_for(int M, int N, int K, long long tiles, long long ws_avail, int elem) {
@@ -929,7 +929,7 @@ static int ksplit_for(int M, int N, int K, long long tiles, long long ws_avail, 
 }
 // the FP32 products of this size run on 32 x 32 tiles of the register-staged kernel
 static bool f32_small32(int M, int N) {
-  return !(M >= 1024 && N >= 1024) && small_tiles(M, N, 64) < 96 && small_tiles(M, N, 32) < 128;
+  return !(M >= 1024 && N >= 1024) && small_tiles(M, N, 64) < 96 && small_tiles(M, N, 32) <= 128;
 }
 // a single product described as ks batches of K / ks (the reduction sums them)
 static void split_k_as_batches(GemmDesc& g, int ks) {
@@ -944,7 +944,7 @@ static void split_k_as_batches(GemmDesc& g, int ks) {
 long long gemm_ws_bytes(int prec, int M, int N, int nbatch) {
   int s = choose_split(prec, M, N, nbatch);
   long long b = s > 1 ? (long long)s * M * N * (prec == PREC_F64 ? 16 : 8) : 0;
-  if (prec == PREC_F64 && nbatch == 1 && f64_small(M, N, 1) && small_tiles(M, N, small_tile64(M, N, 1)) < 128)
+  if (prec == PREC_F64 && nbatch == 1 && f64_small(M, N, 1) && small_tiles(M, N, small_tile64(M, N, 1)) <= 128)
     b = std::max(b, (long long)kMaxKSplit * M * N * 16);
   if (prec == PREC_F32 && nbatch == 1 && f32_small32(M, N)) b = std::max(b, (long long)kMaxKSplit * M * N * 8);
   return b;
@@ -980,7 +980,7 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
                (long long)(s * 2) * g.M * g.N * 16 <= ws_avail)
           s *= 2;
       g.nsplit = s;
-      if (g0.ws && g.nbatch == 1 && tiles < 128) {
+      if (g0.ws && g.nbatch == 1 && tiles <= 128) {
         // one product on a few dozen tiles: its K chunks as the batches of a reduction
         const int ks = ksplit_for(g.M, g.N, g.K, tiles, ws_avail, 16);
         if (ks > 1) split_k_as_batches(g, ks);

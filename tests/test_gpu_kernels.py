@@ -47,15 +47,16 @@ def op(X, o):
 @pytest.mark.parametrize("M,N,K,nb", [(37, 45, 29, 1), (130, 70, 200, 1), (64, 64, 64, 3), (200, 200, 200, 2),
                                       (1, 1, 1, 1), (1024, 1024, 96, 1), (300, 260, 72, 8), (1024, 1024, 64, 4),
                                       (2048, 1040, 96, 1), (1536, 1538, 64, 2), (2050, 1030, 40, 1),
-                                      (2047, 1031, 96, 1), (256, 256, 256, 1), (96, 80, 250, 1)])
+                                      (2047, 1031, 96, 1), (256, 256, 256, 1), (96, 80, 250, 1),
+                                      (512, 256, 256, 1)])
 @pytest.mark.parametrize("opA,opB", [(0, 0), (2, 0), (0, 2), (2, 2)])
 def test_gemm(prec, tol, M, N, K, nb, opA, opB):
     """Complex products against NumPy, relative to the largest entry.  The four large shapes fill
     more than 128 tiles of 128 x 128, where the FP64 and FP32 products run the direct-to-LDS
     kernels: ragged edges in m, n and k, a split-K batch reduction, and an odd shape that the FP32
     one must hand to the register-staged kernel (its 16-byte chunks need even sizes).  Single
-    products on a few dozen 32 x 32 tiles (130 x 70 x 200, 256^3, 96 x 80 x 250) run with their K
-    split into chunks summed by the reduction (FP64 and FP32)."""
+    products on at most 128 tiles of 32 x 32 (130 x 70 x 200, 256^3, 96 x 80 x 250, 512 x 256 x 256)
+    run with their K split into chunks summed by the reduction (FP64 and FP32)."""
     print(f"[case] gemm prec={prec} {M}x{N}x{K} nb={nb} ops={opA},{opB}", flush=True)
     rng = np.random.default_rng(M * 7 + N + K + nb)
     Ash = (nb, M, K) if opA == 0 else (nb, K, M)
