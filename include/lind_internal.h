@@ -82,6 +82,12 @@ int lindx_profile_read(lind_ctx* ctx, int kind, long long* count, double* total_
 int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch, int opA, int opB, int out_mode,
                   const void* dr, const void* dc, void* C, void* stream);
 
+/* Host only (no device work; usable without a GPU): the number of K chunks (1, 2, 4 or 8) into
+   which lindx_gemm and the library's products split a single product of prec (0 FP64, 1 FP32,
+   2 BF16x3) and shape M x N x K when ws_bytes of split-K workspace are available.  -1 for an
+   invalid precision. */
+int lindx_gemm_ksplit(int prec, int M, int N, int K, long long ws_bytes);
+
 /* One classical Gram-Schmidt step with re-orthogonalisation, as in the Arnoldi and GMRES drivers:
    h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, nrm = ||w||_2 (FP64).  V: k basis vectors of len
    complex128 entries at stride ld (>= len); h: 2k complex128 (h1, then h2); nrm: one double (all

@@ -33,6 +33,10 @@ struct GemmDesc {
 };
 // workspace bytes gemm() needs for a split-K launch of this shape (0 if it would not split)
 long long gemm_ws_bytes(int prec, int M, int N, int nbatch);
+// chunks of K (1, 2, 4 or 8) that gemm() splits a single small product into, given ws_avail bytes of
+// workspace: only where its 32 x 32 (FP64: or 64 x 64) tiles fill at most half the chip; each chunk
+// at least 32 deep and K divisible by the count.  Host only.
+int gemm_small_ksplit(int prec, int M, int N, int K, long long ws_avail);
 // Phi(xi) = -sum_j Lt_j [(V^H xi V) / (s_a + conj s_b)] Lt_j^H for n <= 32 in one workgroup (FP64;
 // all operands complex128 row-major on the device, Lt stacked d x n x n)
 int phi_small(const zd* xi, const zd* V, const zd* Lt, const zd* s, const zd* sbar, int n, int d, zd* out,

@@ -4,6 +4,12 @@
 
 using namespace lindx;
 
+// the K-split plan of a single small product (host only, no device work)
+extern "C" int lindx_gemm_ksplit(int prec, int M, int N, int K, long long ws_bytes) {
+  if (prec < 0 || prec > 2) return -1;
+  return gemm_small_ksplit(prec, M, N, K, ws_bytes);
+}
+
 extern "C" int lindx_gemm(int prec, int M, int N, int K, int nbatch, const void* A, long long lda, long long sA,
                           int opA, const void* B, long long ldb, long long sB, int opB, void* C, long long ldc,
                           double alpha_re, double alpha_im, int beta, int out64, int flags, void* stream) {

@@ -941,6 +941,17 @@ static void split_k_as_batches(GemmDesc& g, int ks) {
   g.nsplit = ks;
 }
 
+int gemm_small_ksplit(int prec, int M, int N, int K, long long ws_avail) {
+  if (M <= 0 || N <= 0 || K <= 0) return 1;
+  if (prec == PREC_F64) {
+    if (!f64_small(M, N, 1)) return 1;
+    const long long tiles = small_tiles(M, N, small_tile64(M, N, 1));
+    return tiles <= 128 ? ksplit_for(M, N, K, tiles, ws_avail, 16) : 1;
+  }
+  if (prec == PREC_F32) return f32_small32(M, N) ? ksplit_for(M, N, K, small_tiles(M, N, 32), ws_avail, 8) : 1;
+  return 1;
+}
+
 long long gemm_ws_bytes(int prec, int M, int N, int nbatch) {
   int s = choose_split(prec, M, N, nbatch);
   long long b = s > 1 ? (long long)s * M * N * (prec == PREC_F64 ? 16 : 8) : 0;
@@ -980,9 +991,9 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
                (long long)(s * 2) * g.M * g.N * 16 <= ws_avail)
           s *= 2;
       g.nsplit = s;
-      if (g0.ws && g.nbatch == 1 && tiles <= 128) {
+      if (g0.ws && g.nbatch == 1) {
         // one product on a few dozen tiles: its K chunks as the batches of a reduction
-        const int ks = ksplit_for(g.M, g.N, g.K, tiles, ws_avail, 16);
+        const int ks = gemm_small_ksplit(PREC_F64, g.M, g.N, g.K, ws_avail);
         if (ks > 1) split_k_as_batches(g, ks);
       }
       rc = bt == 64 ? launch(zgemm_kernel<double, 64, 64, 16, double2>, 64, 64, g, st)
@@ -1051,10 +1062,10 @@ int gemm(int prec, const GemmDesc& g0, hipStream_t st) {
         return rc;
       }
     }
-    if (g0.ws && g.nbatch == 1 && g.nsplit == 1 && f32_small32(g.M, g.N)) {
+    if (g0.ws && g.nbatch == 1 && g.nsplit == 1) {
       // one product on a few dozen 32 x 32 tiles: its K chunks as the batches of a reduction
       const long long ws_avail = g0.ws_bytes > 0 ? g0.ws_bytes : gemm_ws_bytes(PREC_F32, g.M, g.N, 1);
-      const int ks = ksplit_for(g.M, g.N, g.K, small_tiles(g.M, g.N, 32), ws_avail, 8);
+      const int ks = gemm_small_ksplit(PREC_F32, g.M, g.N, g.K, ws_avail);
       if (ks > 1) split_k_as_batches(g, ks);
     }
     // 128 x 128 tiles for split or large products, else 64 x 64; 32 x 32 when the larger tiles

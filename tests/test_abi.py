@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -112,3 +113,49 @@ def test_binding_rejects_host_tensors_and_wrong_dtypes():
         Lindblad(H, Ls)
     with pytest.raises(TypeError, match="complex128"):
         Lindblad(H.to(torch.complex64), Ls)
+
+
+def test_small_product_ksplit_plan(lib):
+    """The K-split plan of single small products (host logic, no GPU): the chunk count divides K,
+    every chunk is at least 32 deep, the partials fit the workspace, the split workgroups stay
+    within one round of 256 compute units, and large products or a missing workspace are not
+    split.  Concrete cases: the basis change of n = 256 (64 tiles of 32 x 32, four chunks), the
+    stacked product of the dephased Kerr cavity at n = 512 in FP64 (128 tiles of 64 x 64, two)."""
+    f = lib.lindx_gemm_ksplit
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_longlong]
+    f.restype = ctypes.c_int
+    big = 1 << 40
+    assert f(0, 256, 256, 256, big) == 4
+    assert f(1, 256, 256, 256, big) == 4
+    assert f(0, 1024, 512, 512, big) == 2
+    assert f(0, 512, 256, 256, big) == 2
+    assert f(0, 96, 80, 250, big) == 2
+    assert f(0, 37, 45, 29, big) == 1
+    assert f(0, 2048, 2048, 2048, big) == 1
+    assert f(1, 2048, 2048, 2048, big) == 1
+    assert f(2, 256, 256, 256, big) == 1  # BF16x3 products are not split this way
+    assert f(0, 256, 256, 256, 0) == 1
+    assert f(0, 256, 256, 256, 2 * 256 * 256 * 16) == 2  # workspace for two partials only
+    assert f(3, 256, 256, 256, big) == -1
+
+    def tiles(M, N, b):
+        return ((M + b - 1) // b) * ((N + b - 1) // b)
+
+    rng = np.random.default_rng(0)
+    for _ in range(400):
+        M, N, K = (int(v) for v in rng.integers(1, 1300, size=3))
+        prec = int(rng.integers(0, 2))
+        ws = int(rng.choice([0, 1 << 20, 1 << 26, big]))
+        ks = f(prec, M, N, K, ws)
+        assert ks in (1, 2, 4, 8), (prec, M, N, K, ws, ks)
+        if ks == 1:
+            continue
+        elem = 16 if prec == 0 else 8
+        assert K % ks == 0 and K // ks >= 32
+        assert ks * M * N * elem <= ws
+        if prec == 0:
+            bt = 64 if tiles(M, N, 64) >= 128 else 32
+        else:
+            bt = 32
+        assert tiles(M, N, bt) * ks <= 256
+        assert tiles(M, N, 128) < 96
