@@ -131,6 +131,8 @@ int lind_phi(lind_ctx* ctx, const void* xi, void* out);
    iterative refinement: r = L rho (FP64), solve (I - Phi) zeta = r by GMRES on Phi in the
    context's precision, rho <- normalise(herm(rho - S^{-1} zeta)).
    rho0: device n x n start state (NULL -> I/n); the Arnoldi start vector is xi0 = -S(rho0).
+   A Krylov space that becomes invariant (an exactly zero Arnoldi norm) ends the cycle with the
+   Ritz pair of the space built so far.
    rho_out: device n x n.  info may be NULL.  Returns ENOCONV (best iterate written) when the
    restart/refinement caps or the time limit are hit. */
 int lind_steady_state(lind_ctx* ctx, double tol, const void* rho0, void* rho_out, lind_info* info);
