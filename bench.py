@@ -13,7 +13,8 @@ value = Phi applications per second over the timed steps (all Phi applications i
 
 Also reported: the FP64 path's time-to-1e-8 on the same input, pure Phi-loop rates per
 precision, the dominant kernel's roofline (event-timed inside the timed region), and the CPU
-oracle timed on the host (rank 0, bounded sample).
+oracle timed on the host (rank 0): a bounded sample of Phi applications for the rate, and its own
+Algorithm 4 to the tolerance for the time-to-tolerance (cpu_baseline.alg4; --no-cpu-alg4 skips it).
 """
 from __future__ import annotations
 
@@ -131,9 +132,9 @@ def main():
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 / FP32 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-alg4", action="store_true",
-                    help="also time the oracle's own Algorithm 4 to the tolerance on the host (about two minutes "
-                         "at n = 2048 on 16 threads)")
+    ap.add_argument("--no-cpu-alg4", dest="cpu_alg4", action="store_false",
+                    help="skip timing the oracle's own Algorithm 4 to the tolerance on the host (about a minute at "
+                         "n = 2048 on 16 threads, reported as cpu_baseline.alg4)")
     ap.add_argument("--no-extras", action="store_true", help="skip the resolvent / implicit Euler measurement")
     ap.add_argument("--no-configs", action="store_true", help="skip the Phi rates of the other workloads")
     ap.add_argument("--phi-loop", type=int, default=10, help="Phi applications per precision in the pure loop")
