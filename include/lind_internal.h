@@ -82,6 +82,13 @@ int lindx_profile_read(lind_ctx* ctx, int kind, long long* count, double* total_
 int lindx_p4_test(const void* A, const void* B, int M, int N, int K, int nbatch, int opA, int opB, int out_mode,
                   const void* dr, const void* dc, void* C, void* stream);
 
+/* Host only (no device work; usable without a GPU): the number of split-K runs the pre-split BF16
+   product uses for `tiles` output tiles of 128 x 128, nbatch products of k_len each summed, on
+   `cus` compute units: the run count s <= 64 (and <= the 32-deep stages available) that minimises
+   rounds(s) x stages per run, the work of the longest workgroup chain, plus the partial-sum traffic
+   s x tiles.  -1 for a negative argument. */
+int lindx_p4_pick_split(long long tiles, int nbatch, int k_len, int cus);
+
 /* Host only (no device work; usable without a GPU): the number of K chunks (1, 2, 4 or 8) into
    which lindx_gemm and the library's products split a single product of prec (0 FP64, 1 FP32,
    2 BF16x3) and shape M x N x K when ws_bytes of split-K workspace are available.  -1 for an

@@ -4,6 +4,12 @@
 
 using namespace lindx;
 
+// the split-K run count of the pre-split BF16 product (host only, no device work)
+extern "C" int lindx_p4_pick_split(long long tiles, int nbatch, int k_len, int cus) {
+  if (tiles < 0 || nbatch < 0 || k_len < 0 || cus < 0) return -1;
+  return p4_pick_split(tiles, nbatch, k_len, cus);
+}
+
 // the K-split plan of a single small product (host only, no device work)
 extern "C" int lindx_gemm_ksplit(int prec, int M, int N, int K, long long ws_bytes) {
   if (prec < 0 || prec > 2) return -1;

@@ -159,3 +159,29 @@ def test_small_product_ksplit_plan(lib):
             bt = 32
         assert tiles(M, N, bt) * ks <= 256
         assert tiles(M, N, 128) < 96
+
+
+def test_p4_split_run_count(lib):
+    """The split-K run count of the pre-split BF16 product (host logic, no GPU): within [1, 64] and
+    never more runs than 32-deep stages; one run when the tiles alone fill whole rounds of the
+    chip; the jump reduction of the n = 2048, d = 8 workload (136 upper tiles, 8 products of 2048)
+    in 9 runs, so that its 1224 workgroups fill whole rounds of 256 compute units but the last."""
+    f = lib.lindx_p4_pick_split
+    f.argtypes = [ctypes.c_longlong, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    f.restype = ctypes.c_int
+    assert f(136, 8, 2048, 256) == 9
+    assert f(2048, 1, 2048, 256) == 1
+    assert f(256, 1, 2048, 256) == 1
+    assert f(1, 1, 1, 256) == 1
+    assert f(-1, 1, 1, 256) == -1
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        tiles = int(rng.integers(1, 3000))
+        nb = int(rng.integers(1, 12))
+        k = int(rng.integers(1, 5000))
+        cus = int(rng.choice([64, 256, 304]))
+        s = f(tiles, nb, k, cus)
+        stages = nb * ((k + 31) // 32)
+        assert 1 <= s <= min(64, stages), (tiles, nb, k, cus, s)
+        if tiles % cus == 0:
+            assert s == 1  # whole rounds already: splitting only adds partial-sum traffic
